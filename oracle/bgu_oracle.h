@@ -1,0 +1,105 @@
+/*
+ * bgu_oracle.h -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow, FP64 CPU reference of the Givens bidiagonal update (BGU) of
+ * Brust & Saunders, "Fast and Accurate SVD-Type Updating in Streaming Data",
+ * Section 3.4 ("Givens Low Rank") and Algorithm 2, together with the dense
+ * factorizations used to check it (Householder and Golub-Kahan
+ * bidiagonalization of Section 2, one-sided Jacobi singular values).
+ *
+ * Only the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark may load this library.  The GPU library shares no code, header,
+ * table or helper with it.
+ *
+ * Conventions: matrices are column-major FP64 with an explicit leading
+ * dimension; vectors and matrix indices in comments are 1-based as in the
+ * paper, array offsets in code are 0-based.
+ */
+#ifndef BGU_ORACLE_H
+#define BGU_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define ORC_OK 0
+#define ORC_EINVAL (-1)
+#define ORC_ENOMEM (-2)
+#define ORC_ESTRUCT (-10) /* a band/zero-pattern assertion failed */
+
+/* flags for orc_bgu_pass / orc_bgu_update */
+#define ORC_CHECK_PHASES 1 /* assert the zero pattern after each phase */
+#define ORC_CHECK_EVERY 2  /* assert the one-bulge invariant after every rotation (tiny n) */
+#define ORC_FULL_ROT 4     /* rotate whole rows/columns of the working matrix, not a window */
+#define ORC_NO_QP 8        /* do not accumulate into Q and P (schedule/structure studies) */
+
+/* One recorded rotation: side 0 = left (rows i,i+1 of the working matrix,
+ * columns i,i+1 of Q), side 1 = right (columns i,i+1, columns of P).
+ * phase: 0 spike, 1 elimination phase, 2 band-to-bidiagonal phase. */
+typedef struct {
+    int32_t side;
+    int32_t phase;
+    int64_t i;
+    double c;
+    double s;
+} orc_rot;
+
+/* out[i] = sum_j A(j,i) x[j] accumulated as acc = fma(A(j,i), x[j], acc),
+ * j ascending from acc = 0: the projections Q^T b and P^T c of
+ * eq. (bidiagsubproblem) in a fixed summation order. */
+void orc_project(int64_t rows, int64_t cols, const double *A, int64_t lda,
+                 const double *x, double *out);
+
+/* Rotation generator of eq. (giv1): mode 1 annihilates the first entry
+ * ([c -s; s c][a;b] = [0;r]), mode 2 annihilates the second
+ * ([c -s; s c][a;b] = [r;0]). r = +sqrt(a^2+b^2); identity if the target is 0. */
+void orc_givens(double a, double b, int mode, double *c, double *s, double *r);
+
+/* (x, y) <- (c x - s y, s x + c y) evaluated as fma(c,x,-(s*y)), fma(s,x,c*y). */
+void orc_rot2(double c, double s, double *x, double *y);
+
+/* One rank-1 BGU pass on the already projected vectors u (length m) and
+ * v (length n): Bd + u v^T = Q1 Bd+ P1^T, Q <- Q Q1, P <- P P1
+ * (eq. bidiagplus).  d has n entries, e has n-1.  u and v are overwritten.
+ * trace (optional, capacity trace_cap) receives every rotation in order;
+ * counts (optional, 6 entries) receives
+ * {left, right, phase0, phase1, phase2, phase-2 chains that rotate}.
+ * Returns ORC_OK, ORC_EINVAL or ORC_ESTRUCT. */
+int orc_bgu_pass(int64_t m, int64_t n, double *Q, int64_t ldq, double *d,
+                 double *e, double *P, int64_t ldp, double *u, double *v,
+                 int flags, orc_rot *trace, int64_t trace_cap, int64_t *counts);
+
+/* Rank-r update A + B C^T (eq. main) as r rank-1 passes (Section 3.1): for
+ * column i = 1..r, u = Q^T B(:,i), v = P^T C(:,i) with the current Q, P,
+ * then one pass.  B is m x r (ldb), C is n x r (ldc). */
+int orc_bgu_update(int64_t m, int64_t n, double *Q, int64_t ldq, double *d,
+                   double *e, double *P, int64_t ldp, const double *B,
+                   int64_t ldb, const double *C, int64_t ldc, int r, int flags);
+
+/* Householder bidiagonalization A = Q B P^T (Section 2, eq. (house)),
+ * m >= n >= 1.  Q is m x m, P is n x n (P e1 = e1), d n entries, e n-1. */
+int orc_bidiag_householder(int64_t m, int64_t n, const double *A, int64_t lda,
+                           double *Q, double *d, double *e, double *P);
+
+/* Golub-Kahan (Lanczos) bidiagonalization from the unit start vector p1
+ * (Section 2, recurrences for A P = Q B and A^T Q = P B^T), with full
+ * reorthogonalization.  Returns the n diagonal and n-1 superdiagonal
+ * entries of B. */
+int orc_bidiag_gk(int64_t m, int64_t n, const double *A, int64_t lda,
+                  const double *p1, double *d, double *e);
+
+/* Singular values of A (m x n, m >= n) by one-sided Jacobi, descending. */
+int orc_jacobi_sv(int64_t m, int64_t n, const double *A, int64_t lda,
+                  double *sigma);
+
+/* Test hook: plant a deliberate mistake (0 = none) so the test suite can
+ * show that its pins catch it.  See the MUT_* list in bgu_oracle.c. */
+void orc_set_mutation(int which);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,218 @@
+"""TEST INFRASTRUCTURE ONLY: ctypes front end of the FP64 CPU oracle.
+
+The oracle (``bgu_oracle.c``) is a plain, slow reference of the Givens
+bidiagonal update of Brust & Saunders (Section 3.4, Algorithm 2) plus the
+dense factorizations that check it (Section 2).  Only the test suite, the
+smoke check and the benchmark's CPU-baseline leg may import this module.
+It shares no code with the GPU library.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "bgu_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle_bgu.so")
+
+CHECK_PHASES = 1
+CHECK_EVERY = 2
+FULL_ROT = 4
+NO_QP = 8
+
+ORC_OK = 0
+ORC_ESTRUCT = -10
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no fused multiply-add beyond the explicit
+    fma calls; IEEE sqrt and division)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-mfma",
+               "-fPIC", "-shared", "-Wall", "-o", _LIB, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+    return _LIB
+
+
+class RotRec(ctypes.Structure):
+    _fields_ = [("side", ctypes.c_int32), ("phase", ctypes.c_int32),
+                ("i", ctypes.c_int64), ("c", ctypes.c_double),
+                ("s", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        i64 = ctypes.c_int64
+        L.orc_project.argtypes = [i64, i64, dp, i64, dp, dp]
+        L.orc_project.restype = None
+        L.orc_givens.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int, dp, dp, dp]
+        L.orc_givens.restype = None
+        L.orc_rot2.argtypes = [ctypes.c_double, ctypes.c_double, dp, dp]
+        L.orc_rot2.restype = None
+        L.orc_bgu_pass.argtypes = [i64, i64, dp, i64, dp, dp, dp, i64, dp, dp,
+                                   ctypes.c_int, ctypes.POINTER(RotRec), i64,
+                                   ctypes.POINTER(ctypes.c_int64)]
+        L.orc_bgu_pass.restype = ctypes.c_int
+        L.orc_bgu_update.argtypes = [i64, i64, dp, i64, dp, dp, dp, i64, dp, i64,
+                                     dp, i64, ctypes.c_int, ctypes.c_int]
+        L.orc_bgu_update.restype = ctypes.c_int
+        L.orc_bidiag_householder.argtypes = [i64, i64, dp, i64, dp, dp, dp, dp]
+        L.orc_bidiag_householder.restype = ctypes.c_int
+        L.orc_bidiag_gk.argtypes = [i64, i64, dp, i64, dp, dp, dp]
+        L.orc_bidiag_gk.restype = ctypes.c_int
+        L.orc_jacobi_sv.argtypes = [i64, i64, dp, i64, dp]
+        L.orc_jacobi_sv.restype = ctypes.c_int
+        L.orc_set_mutation.argtypes = [ctypes.c_int]
+        L.orc_set_mutation.restype = None
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a, order="F"):
+    return np.require(np.asarray(a, dtype=np.float64), requirements=[order, "W", "A"])
+
+
+def project(A: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """out = A^T x with sequential fma accumulation (column-major A)."""
+    A = np.asfortranarray(A, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    rows, cols = A.shape
+    out = np.empty(cols)
+    lib().orc_project(rows, cols, _p(A), rows, _p(x), _p(out))
+    return out
+
+
+def givens(a: float, b: float, mode: int):
+    c, s, r = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    lib().orc_givens(a, b, mode, ctypes.byref(c), ctypes.byref(s), ctypes.byref(r))
+    return c.value, s.value, r.value
+
+
+def rot2(c: float, s: float, x: float, y: float):
+    xx, yy = ctypes.c_double(x), ctypes.c_double(y)
+    lib().orc_rot2(c, s, ctypes.byref(xx), ctypes.byref(yy))
+    return xx.value, yy.value
+
+
+class State:
+    """A factorization A = Q diag-bidiag(d, e) P^T held on the host."""
+
+    def __init__(self, Q, d, e, P):
+        self.Q = _f64(Q).copy(order="F")
+        self.P = _f64(P).copy(order="F")
+        self.d = np.array(d, dtype=np.float64)
+        self.e = np.array(e, dtype=np.float64)
+        self.m, self.n = self.Q.shape[0], self.P.shape[0]
+
+    def copy(self) -> "State":
+        return State(self.Q, self.d, self.e, self.P)
+
+    def B(self) -> np.ndarray:
+        Bd = np.zeros((self.m, self.n))
+        Bd[np.arange(self.n), np.arange(self.n)] = self.d
+        Bd[np.arange(self.n - 1), np.arange(1, self.n)] = self.e
+        return Bd
+
+    def A(self) -> np.ndarray:
+        return self.Q @ self.B() @ self.P.T
+
+
+def bgu_pass(st: State, u, v, flags: int = CHECK_PHASES, trace_cap: int = 0,
+             check_status: bool = True):
+    """One rank-1 pass from projected u (m), v (n); updates st in place.
+    Returns (counts[6], trace or None, status)."""
+    u = np.array(u, dtype=np.float64)
+    v = np.array(v, dtype=np.float64)
+    counts = (ctypes.c_int64 * 6)()
+    tr = (RotRec * trace_cap)() if trace_cap else None
+    Q = st.Q if not (flags & NO_QP) else np.zeros((1, 1), order="F")
+    P = st.P if not (flags & NO_QP) else np.zeros((1, 1), order="F")
+    ldq = st.m
+    ldp = st.n
+    status = lib().orc_bgu_pass(st.m, st.n, _p(Q), ldq, _p(st.d), _p(st.e), _p(P), ldp,
+                                _p(u), _p(v), flags, tr, trace_cap, counts)
+    if check_status and status != ORC_OK:
+        raise RuntimeError(f"orc_bgu_pass failed with status {status}")
+    trace = None
+    if tr is not None:
+        nrec = min(trace_cap, counts[0] + counts[1])
+        trace = np.array([(tr[k].side, tr[k].phase, tr[k].i, tr[k].c, tr[k].s)
+                          for k in range(nrec)],
+                         dtype=[("side", "i4"), ("phase", "i4"), ("i", "i8"),
+                                ("c", "f8"), ("s", "f8")])
+    return list(counts), trace, status
+
+
+def bgu_update(st: State, B, C, flags: int = 0) -> int:
+    """Rank-r update A + B C^T as r rank-1 passes; updates st in place."""
+    B = np.asarray(B, dtype=np.float64)
+    C = np.asarray(C, dtype=np.float64)
+    if B.ndim == 1:
+        B, C = B[:, None], C[:, None]
+    B, C = np.asfortranarray(B), np.asfortranarray(C)
+    r = B.shape[1]
+    status = lib().orc_bgu_update(st.m, st.n, _p(st.Q), st.m, _p(st.d), _p(st.e),
+                                  _p(st.P), st.n, _p(B), st.m, _p(C), st.n, r, flags)
+    if status != ORC_OK:
+        raise RuntimeError(f"orc_bgu_update failed with status {status}")
+    return status
+
+
+def bidiag_householder(A):
+    A = np.asfortranarray(A, dtype=np.float64)
+    m, n = A.shape
+    Q = np.empty((m, m), order="F")
+    P = np.empty((n, n), order="F")
+    d = np.empty(n)
+    e = np.empty(max(n - 1, 0) or 1)
+    st = lib().orc_bidiag_householder(m, n, _p(A), m, _p(Q), _p(d), _p(e), _p(P))
+    assert st == ORC_OK
+    return Q, d, e[: n - 1], P
+
+
+def bidiag_gk(A, p1):
+    A = np.asfortranarray(A, dtype=np.float64)
+    m, n = A.shape
+    p1 = np.ascontiguousarray(p1, dtype=np.float64)
+    d = np.empty(n)
+    e = np.empty(max(n - 1, 1))
+    st = lib().orc_bidiag_gk(m, n, _p(A), m, _p(p1), _p(d), _p(e))
+    assert st == ORC_OK
+    return d, e[: n - 1]
+
+
+def jacobi_sv(A):
+    A = np.asfortranarray(A, dtype=np.float64)
+    m, n = A.shape
+    sig = np.empty(n)
+    st = lib().orc_jacobi_sv(m, n, _p(A), m, _p(sig))
+    assert st == ORC_OK
+    return sig
+
+
+def bidiag_sv(d, e):
+    """Singular values of the upper bidiagonal (d, e) by the oracle's Jacobi."""
+    n = len(d)
+    Bd = np.zeros((n, n))
+    Bd[np.arange(n), np.arange(n)] = d
+    Bd[np.arange(n - 1), np.arange(1, n)] = e
+    return jacobi_sv(Bd)
+
+
+def set_mutation(k: int) -> None:
+    lib().orc_set_mutation(k)
