@@ -1,0 +1,137 @@
+/*
+ * bdu.h -- FP64 bidiagonal updating on one MI355X (gfx950).
+ *
+ * A handle holds a factorization A = Q Bd P^T in device memory, with Q m x m
+ * and P n x n orthogonal (column-major, leading dimension = rows) and Bd
+ * upper bidiagonal (diagonal d[0..n-1], superdiagonal e[0..n-2]), the
+ * bidiagonal factorization of Brust & Saunders, "Fast and Accurate SVD-Type
+ * Updating in Streaming Data", eq. (bidiag).  An update replaces it by a
+ * factorization of A + B C^T (eq. main) with the Givens method of Section 3.4
+ * (Algorithm 2): project u = Q^T b, v = P^T c (eq. bidiagsubproblem),
+ * generate the rotations that fold u v^T into Bd and chase the fill back to
+ * bidiagonal form, and accumulate them into Q and P (eq. bidiagplus).  A
+ * rank-r update is r rank-1 passes in column order, each projecting its
+ * column with the current Q and P (Section 3.1).
+ *
+ * Everything is FP64.  The numbers produced are exactly those of the
+ * schedule and rounding conventions the library documents: projections are
+ * sequential fma dot products, rotations are r = sqrt(fma(a,a,b*b)),
+ * c and s by IEEE division, applied as fma(c,x,-(s*y)), fma(s,x,c*y).
+ *
+ * Pointers: any matrix or vector argument may be a host pointer or a device
+ * pointer (the library asks the HIP runtime which).  The library never keeps
+ * a caller pointer after a call returns.
+ *
+ * Status codes are negative on failure; nothing throws across this ABI.
+ * One handle is not thread-safe; distinct handles may be used from
+ * different threads.  A device fault poisons the handle: every later call on
+ * it returns BDU_EDEVICE.
+ */
+#ifndef BDU_H
+#define BDU_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bdu_ctx *bdu_handle;
+
+enum {
+    BDU_OK = 0,
+    BDU_EINVAL = -1,     /* bad shape, NULL argument, or m < n */
+    BDU_ENOMEM = -2,     /* device allocation failed or over the memory budget */
+    BDU_EDEVICE = -3,    /* a HIP call failed; the handle is poisoned */
+    BDU_ENONFINITE = -4, /* reserved: non-finite input rejected */
+    BDU_EBUSY = -5       /* serving queue full */
+};
+
+/* Create a handle from A = Q Bd P^T (eq. bidiag).  Requires m >= n >= 2.
+ * Q: m*m doubles, P: n*n doubles, column-major; d: n doubles; e: n-1
+ * doubles.  The library copies all four into device memory it owns and
+ * builds (or reuses) the rotation schedule for the shape (m, n). */
+int bdu_create(int64_t m, int64_t n, const double *Q, const double *d,
+               const double *e, const double *P, bdu_handle *out);
+
+/* A <- A + B C^T (eq. main), B m x r and C n x r column-major (leading
+ * dimensions m and n), r >= 1: r rank-1 passes of Section 3.4 in column order.
+ * Work is queued on the handle's stream; host inputs are copied before the
+ * call returns, device inputs must stay valid until the stream reaches the
+ * update (bdu_sync). */
+int bdu_update(bdu_handle h, const double *B, const double *C, int r);
+
+/* Same as bdu_update on each handle in turn (results are bit-identical to
+ * that loop), but every stage of every handle is issued as one launch over
+ * all handles.  Handles must be distinct and share no stream requirement; the
+ * work runs on the first handle's stream.  rs[i] >= 1. */
+int bdu_update_batched(const bdu_handle *hs, const double *const *Bs,
+                       const double *const *Cs, const int *rs, int count);
+
+/* One rank-1 pass from already projected vectors u = Q^T b (m doubles) and
+ * v = P^T c (n doubles) (eq. bidiagsubproblem, the right-hand side).  Useful
+ * when the caller holds the projections, and to test the rotation stages on
+ * their own. */
+int bdu_update_projected(bdu_handle h, const double *u, const double *v);
+
+/* Projection only: u = Q^T b (m doubles), v = P^T c (n doubles), as the
+ * next update would compute them; u and v may be host or device pointers. */
+int bdu_project(bdu_handle h, const double *b, const double *c, double *u,
+                double *v);
+
+/* Copy the current factorization out (waits for queued work).  Any output
+ * pointer may be NULL to skip it. */
+int bdu_read(bdu_handle h, double *Q, double *d, double *e, double *P);
+
+/* Rotations of the most recent pass in schedule order: side[k] = 0 for a
+ * left rotation on rows/Q columns (i, i+1), 1 for a right rotation on
+ * columns/P columns (i, i+1); idx[k] = i (1-based); c[k], s[k] its
+ * coefficients.  Returns the count, or a negative status; writes at most cap
+ * entries (any output may be NULL). */
+int64_t bdu_last_rotations(bdu_handle h, int32_t *side, int64_t *idx,
+                           double *c, double *s, int64_t cap);
+
+/* Run the handle's work on this HIP stream (hipStream_t passed as void*;
+ * NULL = the null stream). */
+int bdu_set_stream(bdu_handle h, void *stream);
+int bdu_sync(bdu_handle h);
+int bdu_destroy(bdu_handle h);
+const char *bdu_strerror(int status);
+
+/* Device bytes a handle of shape (m, n) holds (factors, projections,
+ * rotation streams), for admission control. */
+int64_t bdu_footprint_bytes(int64_t m, int64_t n);
+
+/* Applier tiling (chains per wavefront k0 in {6, 12}, wavefronts per
+ * workgroup nw in {1, 2, 4}); applies to handles created afterwards.
+ * Results do not depend on it. */
+int bdu_set_tiling(int k0, int nw);
+int bdu_get_tiling(int *k0, int *nw);
+
+/* The device rotation generator of eq. (giv1) on count pairs (a[i], b[i]):
+ * mode 1 annihilates a, mode 2 annihilates b; outputs c, s and the
+ * survivor r.  Host or device pointers.  For checking the device arithmetic
+ * (IEEE sqrt and division) against a reference. */
+int bdu_givens_device(const double *a, const double *b, int mode, double *c,
+                      double *s, double *r, int64_t count);
+
+/* ---- schedule inspection (host only, no device needed) ---------------- */
+
+/* Statistics of the rotation schedule for (m, n) under the current tiling:
+ * out[0] left rotations, out[1] right rotations, out[2] spike rotations,
+ * out[3] generation chains, out[4] generation ticks, out[5] left stream
+ * slots, out[6] right stream slots, out[7] generation threads. */
+int bdu_plan_stats(int64_t m, int64_t n, int64_t *out);
+
+/* The schedule in order as the device decodes it: side, first index (1-based),
+ * phase (0 spike, 1, 2) and the generation tick of each rotation (spike
+ * rotations get tick -1).  The fold step appears once, in its place, with
+ * side 2, index N-1 and phase 3.  Writes at most cap entries and returns the
+ * total count. */
+int64_t bdu_plan_rotations(int64_t m, int64_t n, int32_t *side, int64_t *idx,
+                           int32_t *phase, int64_t *tick, int64_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

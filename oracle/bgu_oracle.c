@@ -118,6 +118,7 @@ typedef struct {
     double *u, *v;    /* u(1..m), v(1..n) stored at u[i-1], v[j-1] */
     double *Q, *P;
     int64_t ldq, ldp;
+    int64_t qrows, prows; /* rows of Q and P that are rotated */
     int flags;
     int phase;
     orc_rot *trace;
@@ -181,7 +182,7 @@ static void left(bgu *S, int64_t i, double c, double s)
     orc_rot2(c, s, &S->u[i - 1], &S->u[i]);
     if (!(S->flags & ORC_NO_QP) && g_mut != MUT_SKIP_Q) {
         double *qi = S->Q + (i - 1) * S->ldq, *qj = S->Q + i * S->ldq;
-        for (int64_t r = 0; r < S->m; ++r)
+        for (int64_t r = 0; r < S->qrows; ++r)
             orc_rot2(c, s, &qi[r], &qj[r]);
     }
     record(S, 0, i, c, s);
@@ -201,7 +202,7 @@ static void right(bgu *S, int64_t j, double c, double s)
     orc_rot2(c, s, &S->v[j - 1], &S->v[j]);
     if (!(S->flags & ORC_NO_QP)) {
         double *pi = S->P + (j - 1) * S->ldp, *pj = S->P + j * S->ldp;
-        for (int64_t r = 0; r < S->n; ++r)
+        for (int64_t r = 0; r < S->prows; ++r)
             orc_rot2(c, s, &pi[r], &pj[r]);
     }
     record(S, 1, j, c, s);
@@ -288,7 +289,20 @@ int orc_bgu_pass(int64_t m, int64_t n, double *Q, int64_t ldq, double *d,
                  double *e, double *P, int64_t ldp, double *u, double *v,
                  int flags, orc_rot *trace, int64_t trace_cap, int64_t *counts)
 {
-    if (m < n || n < 2 || ldq < m || ldp < n || !d || !e || !u || !v)
+    if (ldq < m || ldp < n)
+        return ORC_EINVAL;
+    return orc_bgu_pass_rows(m, n, Q, m, ldq, d, e, P, n, ldp, u, v, flags,
+                             trace, trace_cap, counts);
+}
+
+int orc_bgu_pass_rows(int64_t m, int64_t n, double *Q, int64_t qrows,
+                      int64_t ldq, double *d, double *e, double *P,
+                      int64_t prows, int64_t ldp, double *u, double *v,
+                      int flags, orc_rot *trace, int64_t trace_cap,
+                      int64_t *counts)
+{
+    if (m < n || n < 2 || qrows < 0 || prows < 0 || ldq < qrows ||
+        ldp < prows || !d || !e || !u || !v)
         return ORC_EINVAL;
     if (!(flags & ORC_NO_QP) && (!Q || !P))
         return ORC_EINVAL;
@@ -303,6 +317,8 @@ int orc_bgu_pass(int64_t m, int64_t n, double *Q, int64_t ldq, double *d,
     S.P = P;
     S.ldq = ldq;
     S.ldp = ldp;
+    S.qrows = qrows;
+    S.prows = prows;
     S.flags = flags;
     S.trace = trace;
     S.trace_cap = trace_cap;

@@ -72,6 +72,16 @@ int orc_bgu_pass(int64_t m, int64_t n, double *Q, int64_t ldq, double *d,
                  double *e, double *P, int64_t ldp, double *u, double *v,
                  int flags, orc_rot *trace, int64_t trace_cap, int64_t *counts);
 
+/* The same pass applied to a subset of rows: Q holds qrows rows of the
+ * m x m factor (leading dimension ldq >= qrows), P holds prows rows of the
+ * n x n factor.  Rotations act on columns, so each row is updated exactly as
+ * in the full pass. */
+int orc_bgu_pass_rows(int64_t m, int64_t n, double *Q, int64_t qrows,
+                      int64_t ldq, double *d, double *e, double *P,
+                      int64_t prows, int64_t ldp, double *u, double *v,
+                      int flags, orc_rot *trace, int64_t trace_cap,
+                      int64_t *counts);
+
 /* Rank-r update A + B C^T (eq. main) as r rank-1 passes (Section 3.1): for
  * column i = 1..r, u = Q^T B(:,i), v = P^T C(:,i) with the current Q, P,
  * then one pass.  B is m x r (ldb), C is n x r (ldc). */

@@ -64,6 +64,10 @@ def lib():
                                    ctypes.c_int, ctypes.POINTER(RotRec), i64,
                                    ctypes.POINTER(ctypes.c_int64)]
         L.orc_bgu_pass.restype = ctypes.c_int
+        L.orc_bgu_pass_rows.argtypes = [i64, i64, dp, i64, i64, dp, dp, dp, i64, i64, dp, dp,
+                                        ctypes.c_int, ctypes.POINTER(RotRec), i64,
+                                        ctypes.POINTER(ctypes.c_int64)]
+        L.orc_bgu_pass_rows.restype = ctypes.c_int
         L.orc_bgu_update.argtypes = [i64, i64, dp, i64, dp, dp, dp, i64, dp, i64,
                                      dp, i64, ctypes.c_int, ctypes.c_int]
         L.orc_bgu_update.restype = ctypes.c_int
@@ -156,6 +160,23 @@ def bgu_pass(st: State, u, v, flags: int = CHECK_PHASES, trace_cap: int = 0,
                          dtype=[("side", "i4"), ("phase", "i4"), ("i", "i8"),
                                 ("c", "f8"), ("s", "f8")])
     return list(counts), trace, status
+
+
+def bgu_pass_rows(m: int, n: int, Qrows, d, e, Prows, u, v, flags: int = 0):
+    """One pass on row subsets Qrows (k x m) and Prows (l x n); returns
+    (Qrows', d', e', Prows') without touching the inputs."""
+    Qr = np.array(Qrows, dtype=np.float64, order="F")
+    Pr = np.array(Prows, dtype=np.float64, order="F")
+    d = np.array(d, dtype=np.float64)
+    e = np.array(e, dtype=np.float64)
+    u = np.array(u, dtype=np.float64)
+    v = np.array(v, dtype=np.float64)
+    kq, kp = Qr.shape[0], Pr.shape[0]
+    status = lib().orc_bgu_pass_rows(m, n, _p(Qr), kq, max(kq, 1), _p(d), _p(e), _p(Pr), kp, max(kp, 1),
+                                     _p(u), _p(v), flags, None, 0, None)
+    if status != ORC_OK:
+        raise RuntimeError(f"orc_bgu_pass_rows failed with status {status}")
+    return Qr, d, e, Pr
 
 
 def bgu_update(st: State, B, C, flags: int = 0) -> int:

@@ -1,0 +1,223 @@
+"""Python binding of the C ABI in include/bdu.h (argument marshalling only).
+
+Every step of an update runs in the gfx950 kernels of libbdu.so; this module
+only passes pointers and sizes.  Arrays may be numpy arrays (host memory) or
+torch tensors on the GPU (device memory); both must be float64 and
+column-major (Fortran order) for matrices.  The library copies its inputs.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbdu.so")
+
+BDU_OK = 0
+BDU_EINVAL = -1
+BDU_ENOMEM = -2
+BDU_EDEVICE = -3
+BDU_EBUSY = -5
+
+
+class BduError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {_strerror(status)} ({status})")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libbdu.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+        L.bdu_create.argtypes = [i64, i64, vp, vp, vp, vp, ctypes.POINTER(vp)]
+        L.bdu_update.argtypes = [vp, vp, vp, i32]
+        L.bdu_update_batched.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                         ctypes.POINTER(i32), i32]
+        L.bdu_update_projected.argtypes = [vp, vp, vp]
+        L.bdu_project.argtypes = [vp, vp, vp, vp, vp]
+        L.bdu_read.argtypes = [vp, vp, vp, vp, vp]
+        L.bdu_last_rotations.argtypes = [vp, vp, vp, vp, vp, i64]
+        L.bdu_last_rotations.restype = i64
+        L.bdu_set_stream.argtypes = [vp, vp]
+        L.bdu_sync.argtypes = [vp]
+        L.bdu_destroy.argtypes = [vp]
+        L.bdu_strerror.argtypes = [i32]
+        L.bdu_strerror.restype = ctypes.c_char_p
+        L.bdu_footprint_bytes.argtypes = [i64, i64]
+        L.bdu_footprint_bytes.restype = i64
+        L.bdu_set_tiling.argtypes = [i32, i32]
+        L.bdu_get_tiling.argtypes = [ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.bdu_plan_stats.argtypes = [i64, i64, ctypes.POINTER(i64)]
+        L.bdu_givens_device.argtypes = [vp, vp, i32, vp, vp, vp, i64]
+        L.bdu_plan_rotations.argtypes = [i64, i64, vp, vp, vp, vp, i64]
+        L.bdu_plan_rotations.restype = i64
+        for f in ("bdu_create", "bdu_update", "bdu_update_batched", "bdu_update_projected", "bdu_project",
+                  "bdu_read", "bdu_set_stream", "bdu_sync", "bdu_destroy", "bdu_set_tiling",
+                  "bdu_get_tiling", "bdu_plan_stats", "bdu_givens_device"):
+            getattr(L, f).restype = i32
+        _lib = L
+    return _lib
+
+
+def _strerror(status: int) -> str:
+    try:
+        return lib().bdu_strerror(status).decode()
+    except Exception:
+        return "unknown"
+
+
+def _check(status: int, what: str) -> int:
+    if status < 0:
+        raise BduError(status, what)
+    return status
+
+
+def _ptr(a, matrix: bool = False):
+    """Data pointer of a float64 numpy array or CUDA tensor (kept alive by the caller)."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        if a.dtype != np.float64:
+            raise TypeError("float64 required")
+        if matrix and a.ndim == 2 and not a.flags["F_CONTIGUOUS"]:
+            raise ValueError("matrices must be column-major (Fortran order)")
+        if not (a.flags["F_CONTIGUOUS"] or a.flags["C_CONTIGUOUS"]):
+            raise ValueError("array must be contiguous")
+        return a.ctypes.data
+    # torch tensor
+    import torch
+    if a.dtype != torch.float64:
+        raise TypeError("float64 required")
+    if matrix and a.dim() == 2 and a.stride(0) != 1:
+        raise ValueError("matrices must be column-major (stride(0) == 1)")
+    return a.data_ptr()
+
+
+def set_tiling(k0: int, nw: int) -> None:
+    _check(lib().bdu_set_tiling(k0, nw), "bdu_set_tiling")
+
+
+def get_tiling():
+    k0, nw = ctypes.c_int(), ctypes.c_int()
+    lib().bdu_get_tiling(ctypes.byref(k0), ctypes.byref(nw))
+    return k0.value, nw.value
+
+
+def footprint_bytes(m: int, n: int) -> int:
+    return _check(lib().bdu_footprint_bytes(m, n), "bdu_footprint_bytes")
+
+
+def givens_device(a: np.ndarray, b: np.ndarray, mode: int):
+    a = np.ascontiguousarray(a, np.float64)
+    b = np.ascontiguousarray(b, np.float64)
+    c, s, r = np.empty_like(a), np.empty_like(a), np.empty_like(a)
+    _check(lib().bdu_givens_device(a.ctypes.data, b.ctypes.data, mode, c.ctypes.data, s.ctypes.data,
+                                   r.ctypes.data, len(a)), "bdu_givens_device")
+    return c, s, r
+
+
+def plan_stats(m: int, n: int) -> dict:
+    out = (ctypes.c_int64 * 8)()
+    _check(lib().bdu_plan_stats(m, n, out), "bdu_plan_stats")
+    keys = ["left", "right", "spike", "chains", "ticks", "left_slots", "right_slots", "gen_threads"]
+    return dict(zip(keys, list(out)))
+
+
+def plan_rotations(m: int, n: int):
+    L = lib()
+    cnt = _check(L.bdu_plan_rotations(m, n, None, None, None, None, 0), "bdu_plan_rotations")
+    side = np.empty(cnt, np.int32)
+    idx = np.empty(cnt, np.int64)
+    ph = np.empty(cnt, np.int32)
+    tick = np.empty(cnt, np.int64)
+    L.bdu_plan_rotations(m, n, side.ctypes.data, idx.ctypes.data, ph.ctypes.data, tick.ctypes.data, cnt)
+    return side, idx, ph, tick
+
+
+class Handle:
+    """One factorization A = Q Bd P^T resident on the GPU."""
+
+    def __init__(self, Q, d, e, P):
+        m, n = Q.shape[0], P.shape[0]
+        h = ctypes.c_void_p()
+        _check(lib().bdu_create(m, n, _ptr(Q, True), _ptr(d), _ptr(e), _ptr(P, True), ctypes.byref(h)),
+               "bdu_create")
+        self._h = h
+        self.m, self.n = m, n
+
+    @property
+    def ptr(self):
+        return self._h
+
+    def update(self, B, C) -> None:
+        r = 1 if B.ndim == 1 else B.shape[1]
+        _check(lib().bdu_update(self._h, _ptr(B, True), _ptr(C, True), r), "bdu_update")
+
+    def update_projected(self, u, v) -> None:
+        _check(lib().bdu_update_projected(self._h, _ptr(u), _ptr(v)), "bdu_update_projected")
+
+    def project(self, b, c):
+        u = np.empty(self.m)
+        v = np.empty(self.n)
+        _check(lib().bdu_project(self._h, _ptr(b), _ptr(c), u.ctypes.data, v.ctypes.data), "bdu_project")
+        return u, v
+
+    def read(self):
+        Q = np.empty((self.m, self.m), order="F")
+        P = np.empty((self.n, self.n), order="F")
+        d = np.empty(self.n)
+        e = np.empty(max(self.n - 1, 1))
+        _check(lib().bdu_read(self._h, Q.ctypes.data, d.ctypes.data, e.ctypes.data, P.ctypes.data), "bdu_read")
+        return Q, d, e[: self.n - 1], P
+
+    def read_into(self, Q=None, d=None, e=None, P=None) -> None:
+        _check(lib().bdu_read(self._h, _ptr(Q, True), _ptr(d), _ptr(e), _ptr(P, True)), "bdu_read")
+
+    def last_rotations(self):
+        L = lib()
+        cnt = _check(L.bdu_last_rotations(self._h, None, None, None, None, 0), "bdu_last_rotations")
+        side = np.empty(cnt, np.int32)
+        idx = np.empty(cnt, np.int64)
+        c = np.empty(cnt)
+        s = np.empty(cnt)
+        L.bdu_last_rotations(self._h, side.ctypes.data, idx.ctypes.data, c.ctypes.data, s.ctypes.data, cnt)
+        return side, idx, c, s
+
+    def set_stream(self, stream) -> None:
+        """stream: a torch.cuda.Stream, a raw hipStream_t (int) or None."""
+        raw = getattr(stream, "cuda_stream", stream)
+        _check(lib().bdu_set_stream(self._h, ctypes.c_void_p(raw) if raw else None), "bdu_set_stream")
+
+    def sync(self) -> None:
+        _check(lib().bdu_sync(self._h), "bdu_sync")
+
+    def close(self) -> None:
+        if self._h:
+            lib().bdu_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def update_batched(handles, Bs, Cs) -> None:
+    """bdu_update_batched over distinct handles; Bs[i] is m_i x r_i, Cs[i] n_i x r_i."""
+    n = len(handles)
+    hp = (ctypes.c_void_p * n)(*[h.ptr.value for h in handles])
+    bp = (ctypes.c_void_p * n)(*[_ptr(B, True) for B in Bs])
+    cp = (ctypes.c_void_p * n)(*[_ptr(C, True) for C in Cs])
+    rs = (ctypes.c_int * n)(*[1 if B.ndim == 1 else B.shape[1] for B in Bs])
+    _check(lib().bdu_update_batched(hp, bp, cp, rs, n), "bdu_update_batched")

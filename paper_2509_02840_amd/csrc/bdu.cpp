@@ -1,0 +1,593 @@
+// bdu.cpp -- host side of the C ABI in include/bdu.h.
+//
+// A handle owns device copies of Q, d, e, P, the projection vectors, staging
+// for update columns and the two rotation streams of its shape's schedule.
+// Schedules (chains, generation ticks, applier blocks) are built once per
+// (m, n, tiling) and shared by every handle of that shape.
+#include "../../include/bdu.h"
+
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "device.h"
+#include "kernels.h"
+#include "plan.h"
+
+using namespace bdu;
+
+namespace {
+
+std::mutex g_mu;
+int g_k0 = 12, g_nw = 1;
+
+struct PlanEntry {
+    std::unique_ptr<Plan> plan;
+    bool uploaded = false;
+};
+std::map<std::tuple<int64_t, int64_t, int, int>, PlanEntry> g_plans;
+
+Plan *get_plan(int64_t m, int64_t n, int k0, int nw, bool upload, hipError_t *err)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto key = std::make_tuple(m, n, k0, nw);
+    auto it = g_plans.find(key);
+    if (it == g_plans.end()) {
+        PlanEntry e;
+        e.plan = build_plan(m, n, k0, nw, kGenThreads);
+        it = g_plans.emplace(key, std::move(e)).first;
+    }
+    Plan *p = it->second.plan.get();
+    if (upload && !it->second.uploaded) {
+        size_t cb = sizeof(GenChain) * p->chains.size();
+        hipError_t e = hipMalloc(&p->d_chains, cb);
+        if (e == hipSuccess) e = hipMemcpy(p->d_chains, p->chains.data(), cb, hipMemcpyHostToDevice);
+        for (int s = 0; s < 2 && e == hipSuccess; ++s) {
+            size_t bb = sizeof(BlockDesc) * p->blocks[s].size();
+            e = hipMalloc(&p->d_blocks[s], bb);
+            if (e == hipSuccess) e = hipMemcpy(p->d_blocks[s], p->blocks[s].data(), bb, hipMemcpyHostToDevice);
+        }
+        if (e != hipSuccess) {
+            *err = e;
+            return nullptr;
+        }
+        it->second.uploaded = true;
+    }
+    *err = hipSuccess;
+    return p;
+}
+
+bool is_device_ptr(const void *p)
+{
+    if (!p) return false;
+    hipPointerAttribute_t a;
+    hipError_t e = hipPointerGetAttributes(&a, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+}  // namespace
+
+struct bdu_ctx {
+    int64_t m = 0, n = 0;
+    Plan *plan = nullptr;
+    HandleDev hd{};
+    HandleDev *d_hd = nullptr;
+    HandleDev **d_self = nullptr;
+    hipStream_t stream = nullptr;
+    bool poisoned = false;
+    int rcap = 0;
+    bool lds_gen = true;
+    std::vector<void *> allocs;
+};
+
+namespace {
+
+#define HIPCHK(h, expr)                      \
+    do {                                     \
+        hipError_t e_ = (expr);              \
+        if (e_ != hipSuccess) {              \
+            if (h) (h)->poisoned = true;     \
+            return BDU_EDEVICE;              \
+        }                                    \
+    } while (0)
+
+template <typename T>
+hipError_t dalloc(bdu_ctx *h, T **p, int64_t count)
+{
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, (size_t)std::max<int64_t>(count, 1) * sizeof(T));
+    if (e == hipSuccess) {
+        h->allocs.push_back(q);
+        *p = (T *)q;
+    }
+    return e;
+}
+
+// Copy `bytes` from src (host or device) to the device buffer dst, in
+// stream order.  Host sources are consumed before returning.
+hipError_t copy_in(void *dst, const void *src, size_t bytes, hipStream_t st)
+{
+    if (bytes == 0) return hipSuccess;
+    if (is_device_ptr(src)) return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st);
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(st);
+}
+
+// Column-major rows x cols matrix with leading dimension ld (doubles) on the
+// device from a packed (leading dimension rows) host or device matrix.
+hipError_t copy_mat_in(double *dst, int64_t ld, const double *src, int64_t rows, int64_t cols, hipStream_t st)
+{
+    bool dev = is_device_ptr(src);
+    hipError_t e = hipMemcpy2DAsync(dst, sizeof(double) * ld, src, sizeof(double) * rows, sizeof(double) * rows,
+                                    cols, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st);
+    if (e != hipSuccess || dev) return e;
+    return hipStreamSynchronize(st);
+}
+
+hipError_t copy_mat_out(double *dst, const double *src, int64_t ld, int64_t rows, int64_t cols, hipStream_t st)
+{
+    if (!dst) return hipSuccess;
+    hipMemcpyKind k = is_device_ptr(dst) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    hipError_t e = hipMemcpy2DAsync(dst, sizeof(double) * rows, src, sizeof(double) * ld, sizeof(double) * rows,
+                                    cols, k, st);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(st);
+}
+
+hipError_t copy_out(void *dst, const void *src, size_t bytes, hipStream_t st)
+{
+    if (bytes == 0 || !dst) return hipSuccess;
+    hipMemcpyKind k = is_device_ptr(dst) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, k, st);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(st);
+}
+
+int ensure_rcap(bdu_ctx *h, int r)
+{
+    if (r <= h->rcap) return BDU_OK;
+    int nr = std::max(r, 2 * h->rcap);
+    double *nb = nullptr, *nc = nullptr;
+    if (hipMalloc(&nb, sizeof(double) * h->m * nr) != hipSuccess) return BDU_ENOMEM;
+    if (hipMalloc(&nc, sizeof(double) * h->n * nr) != hipSuccess) {
+        (void)hipFree(nb);
+        return BDU_ENOMEM;
+    }
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    for (auto &p : h->allocs)
+        if (p == h->hd.bst || p == h->hd.cst) {
+            (void)hipFree(p);
+            p = nullptr;
+        }
+    h->allocs.erase(std::remove(h->allocs.begin(), h->allocs.end(), nullptr), h->allocs.end());
+    h->allocs.push_back(nb);
+    h->allocs.push_back(nc);
+    h->hd.bst = nb;
+    h->hd.cst = nc;
+    h->rcap = nr;
+    HIPCHK(h, hipMemcpy(h->d_hd, &h->hd, sizeof(HandleDev), hipMemcpyHostToDevice));
+    return BDU_OK;
+}
+
+// Rotation stages of one pass (spike, generation, application) for `count`
+// handles listed in the device array hs (all with the same tiling).
+hipError_t run_rotation_stages(HandleDev *const *hs, int count, bool any_spike, int64_t lds_bytes,
+                               bool in_lds, int max_panels, int k0, int nw, hipStream_t st)
+{
+    hipError_t e = hipSuccess;
+    if (any_spike) e = launch_spike(hs, count, st);
+    if (e == hipSuccess) e = launch_gen(hs, count, lds_bytes, in_lds, st);
+    if (e == hipSuccess) e = launch_apply(hs, count, max_panels, k0, nw, st);
+    return e;
+}
+
+int tiles_of(const bdu_ctx *h) { return (int)((h->m + 63) / 64 + (h->n + 63) / 64); }
+
+int pass_single(bdu_ctx *h, int pass, bool project)
+{
+    hipError_t e = hipSuccess;
+    if (project) e = launch_project(h->d_self, 1, tiles_of(h), pass, h->stream);
+    if (e == hipSuccess)
+        e = run_rotation_stages(h->d_self, 1, h->m > h->n, gen_lds_bytes(h->n, h->plan->N), h->lds_gen,
+                                tiles_of(h), h->plan->K0, h->plan->NW, h->stream);
+    if (e != hipSuccess) {
+        h->poisoned = true;
+        return BDU_EDEVICE;
+    }
+    return BDU_OK;
+}
+
+// Slot of a rotation in its side's stream (the layout the generator writes).
+int64_t slot_of(const Plan &P, const GenChain &g, const Rot &r)
+{
+    const int ph = chain_phase(g.type), tg = chain_in_phase(g.type, g.param);
+    const int b = tg / P.K, tin = tg % P.K, w = tin / P.K0, tl = tin % P.K0;
+    const BlockDesc &bd = P.blocks[r.side][(ph == 1 ? 0 : P.nb1) + b];
+    const int lam0 = lam0_of_pair(ph, bd.base, r.i);
+    return bd.off + (int64_t)(lam0 / 3 + tl + w * P.S) * P.K + tin;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *bdu_strerror(int status)
+{
+    switch (status) {
+    case BDU_OK: return "ok";
+    case BDU_EINVAL: return "invalid argument";
+    case BDU_ENOMEM: return "out of device memory";
+    case BDU_EDEVICE: return "device error (handle poisoned)";
+    case BDU_ENONFINITE: return "non-finite input";
+    case BDU_EBUSY: return "queue full";
+    default: return "unknown status";
+    }
+}
+
+int bdu_set_tiling(int k0, int nw)
+{
+    if (!tiling_supported(k0, nw)) return BDU_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_k0 = k0;
+    g_nw = nw;
+    return BDU_OK;
+}
+
+int bdu_get_tiling(int *k0, int *nw)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (k0) *k0 = g_k0;
+    if (nw) *nw = g_nw;
+    return BDU_OK;
+}
+
+int64_t bdu_footprint_bytes(int64_t m, int64_t n)
+{
+    if (m < n || n < 2) return BDU_EINVAL;
+    int k0, nw;
+    bdu_get_tiling(&k0, &nw);
+    hipError_t e;
+    Plan *p = get_plan(m, n, k0, nw, false, &e);
+    int64_t N = p->N;
+    const int64_t ldq = (m + 63) / 64 * 64, ldp = (n + 63) / 64 * 64;
+    int64_t bytes = 8 * (ldq * m + ldp * n + 2 * n + 2 * (m + n) + 2 * (m + n));
+    bytes += 16 * (p->slots[0] + p->slots[1] + std::max<int64_t>(p->nspike, 1));
+    if (gen_lds_bytes(n, N) > kMaxGenLds) bytes += gen_lds_bytes(n, N);
+    return bytes;
+}
+
+int bdu_create(int64_t m, int64_t n, const double *Q, const double *d, const double *e, const double *P,
+               bdu_handle *out)
+{
+    if (!out || !Q || !d || !e || !P || m < n || n < 2 || m > (int64_t)1 << 30) return BDU_EINVAL;
+    *out = nullptr;
+    int k0, nw;
+    bdu_get_tiling(&k0, &nw);
+    hipError_t err;
+    Plan *plan = get_plan(m, n, k0, nw, true, &err);
+    if (!plan) return BDU_EDEVICE;
+    auto h = std::make_unique<bdu_ctx>();
+    h->m = m;
+    h->n = n;
+    h->plan = plan;
+    h->lds_gen = gen_lds_bytes(n, plan->N) <= kMaxGenLds;
+    HandleDev &hd = h->hd;
+    hipError_t a = hipSuccess;
+    auto A = [&](hipError_t x) { if (a == hipSuccess) a = x; };
+    const int64_t ldq = (m + 63) / 64 * 64, ldp = (n + 63) / 64 * 64;
+    A(dalloc(h.get(), &hd.Q, ldq * m));
+    A(dalloc(h.get(), &hd.P, ldp * n));
+    A(dalloc(h.get(), &hd.d, n));
+    A(dalloc(h.get(), &hd.e, n));
+    A(dalloc(h.get(), &hd.u, m));
+    A(dalloc(h.get(), &hd.v, n));
+    A(dalloc(h.get(), &hd.bst, m));
+    A(dalloc(h.get(), &hd.cst, n));
+    A(dalloc(h.get(), &hd.csL, plan->slots[0]));
+    A(dalloc(h.get(), &hd.csR, plan->slots[1]));
+    A(dalloc(h.get(), &hd.csSp, plan->nspike));
+    if (!h->lds_gen) A(dalloc(h.get(), &hd.band, gen_lds_bytes(n, plan->N) / 8));
+    A(dalloc(h.get(), &h->d_hd, 1));
+    A(dalloc(h.get(), &h->d_self, 1));
+    if (a != hipSuccess) {
+        for (void *p : h->allocs) (void)hipFree(p);
+        (void)hipGetLastError();
+        return BDU_ENOMEM;
+    }
+    h->rcap = 1;
+    hd.chains = plan->d_chains;
+    hd.blkL = plan->d_blocks[0];
+    hd.blkR = plan->d_blocks[1];
+    hd.ticks = plan->ticks;
+    hd.m = (int32_t)m;
+    hd.n = (int32_t)n;
+    hd.ldq = (int32_t)ldq;
+    hd.ldp = (int32_t)ldp;
+    hd.N = (int32_t)plan->N;
+    hd.nchains = (int32_t)plan->chains.size();
+    hd.nb1 = plan->nb1;
+    hd.nb2 = plan->nb2;
+    hd.K0 = plan->K0;
+    hd.NW = plan->NW;
+    hd.K = plan->K;
+    hd.S = plan->S;
+    bdu_ctx *hp = h.get();
+    HIPCHK(hp, hipMemsetAsync(hd.Q, 0, sizeof(double) * ldq * m, hp->stream));
+    HIPCHK(hp, hipMemsetAsync(hd.P, 0, sizeof(double) * ldp * n, hp->stream));
+    HIPCHK(hp, copy_mat_in(hd.Q, ldq, Q, m, m, hp->stream));
+    HIPCHK(hp, copy_mat_in(hd.P, ldp, P, n, n, hp->stream));
+    HIPCHK(hp, copy_in(hd.d, d, sizeof(double) * n, hp->stream));
+    HIPCHK(hp, copy_in(hd.e, e, sizeof(double) * (n - 1), hp->stream));
+    HIPCHK(hp, launch_fill_identity(hd.csL, plan->slots[0], hp->stream));
+    HIPCHK(hp, launch_fill_identity(hd.csR, plan->slots[1], hp->stream));
+    HIPCHK(hp, hipMemcpyAsync(h->d_hd, &hd, sizeof(HandleDev), hipMemcpyHostToDevice, hp->stream));
+    HandleDev *self = h->d_hd;
+    HIPCHK(hp, hipMemcpyAsync(h->d_self, &self, sizeof(self), hipMemcpyHostToDevice, hp->stream));
+    HIPCHK(hp, hipStreamSynchronize(hp->stream));
+    *out = h.release();
+    return BDU_OK;
+}
+
+int bdu_set_stream(bdu_handle h, void *stream)
+{
+    if (!h) return BDU_EINVAL;
+    if (h->poisoned) return BDU_EDEVICE;
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->stream = (hipStream_t)stream;
+    return BDU_OK;
+}
+
+int bdu_sync(bdu_handle h)
+{
+    if (!h) return BDU_EINVAL;
+    if (h->poisoned) return BDU_EDEVICE;
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return BDU_OK;
+}
+
+int bdu_update(bdu_handle h, const double *B, const double *C, int r)
+{
+    if (!h || !B || !C || r < 1) return BDU_EINVAL;
+    if (h->poisoned) return BDU_EDEVICE;
+    int st = ensure_rcap(h, r);
+    if (st != BDU_OK) return st;
+    HIPCHK(h, copy_in(h->hd.bst, B, sizeof(double) * h->m * r, h->stream));
+    HIPCHK(h, copy_in(h->hd.cst, C, sizeof(double) * h->n * r, h->stream));
+    for (int p = 0; p < r; ++p) {
+        st = pass_single(h, p, true);
+        if (st != BDU_OK) return st;
+    }
+    return BDU_OK;
+}
+
+int bdu_update_projected(bdu_handle h, const double *u, const double *v)
+{
+    if (!h || !u || !v) return BDU_EINVAL;
+    if (h->poisoned) return BDU_EDEVICE;
+    HIPCHK(h, copy_in(h->hd.u, u, sizeof(double) * h->m, h->stream));
+    HIPCHK(h, copy_in(h->hd.v, v, sizeof(double) * h->n, h->stream));
+    return pass_single(h, 0, false);
+}
+
+int bdu_project(bdu_handle h, const double *b, const double *c, double *u, double *v)
+{
+    if (!h || !b || !c) return BDU_EINVAL;
+    if (h->poisoned) return BDU_EDEVICE;
+    HIPCHK(h, copy_in(h->hd.bst, b, sizeof(double) * h->m, h->stream));
+    HIPCHK(h, copy_in(h->hd.cst, c, sizeof(double) * h->n, h->stream));
+    HIPCHK(h, launch_project(h->d_self, 1, tiles_of(h), 0, h->stream));
+    HIPCHK(h, copy_out(u, h->hd.u, sizeof(double) * h->m, h->stream));
+    HIPCHK(h, copy_out(v, h->hd.v, sizeof(double) * h->n, h->stream));
+    return BDU_OK;
+}
+
+int bdu_read(bdu_handle h, double *Q, double *d, double *e, double *P)
+{
+    if (!h) return BDU_EINVAL;
+    if (h->poisoned) return BDU_EDEVICE;
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    HIPCHK(h, copy_mat_out(Q, h->hd.Q, h->hd.ldq, h->m, h->m, h->stream));
+    HIPCHK(h, copy_out(d, h->hd.d, sizeof(double) * h->n, h->stream));
+    HIPCHK(h, copy_out(e, h->hd.e, sizeof(double) * (h->n - 1), h->stream));
+    HIPCHK(h, copy_mat_out(P, h->hd.P, h->hd.ldp, h->n, h->n, h->stream));
+    return BDU_OK;
+}
+
+int64_t bdu_last_rotations(bdu_handle h, int32_t *side, int64_t *idx, double *c, double *s, int64_t cap)
+{
+    if (!h) return BDU_EINVAL;
+    if (h->poisoned) return BDU_EDEVICE;
+    const Plan &P = *h->plan;
+    std::vector<double2> L(P.slots[0]), R(P.slots[1]), Sp(std::max<int64_t>(P.nspike, 1));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    HIPCHK(h, hipMemcpy(L.data(), h->hd.csL, sizeof(double2) * P.slots[0], hipMemcpyDeviceToHost));
+    HIPCHK(h, hipMemcpy(R.data(), h->hd.csR, sizeof(double2) * P.slots[1], hipMemcpyDeviceToHost));
+    if (P.nspike) HIPCHK(h, hipMemcpy(Sp.data(), h->hd.csSp, sizeof(double2) * P.nspike, hipMemcpyDeviceToHost));
+    int64_t k = 0;
+    auto emit = [&](int sd, int64_t i, double2 v) {
+        if (k < cap) {
+            if (side) side[k] = sd;
+            if (idx) idx[k] = i;
+            if (c) c[k] = v.x;
+            if (s) s[k] = v.y;
+        }
+        ++k;
+    };
+    for (int64_t t = 0; t < P.nspike; ++t) emit(0, P.m - 1 - t, Sp[t]);
+    for (const GenChain &g : P.chains) {
+        if (g.type == CH_FOLD) continue;
+        for (int q = 0; q < g.len; ++q) {
+            Rot r = decode(g.type, g.param, q);
+            int64_t sl = slot_of(P, g, r);
+            emit(r.side, r.i, r.side == 0 ? L[sl] : R[sl]);
+        }
+    }
+    return k;
+}
+
+int bdu_destroy(bdu_handle h)
+{
+    if (!h) return BDU_EINVAL;
+    (void)hipStreamSynchronize(h->stream);
+    for (void *p : h->allocs) (void)hipFree(p);
+    delete h;
+    return BDU_OK;
+}
+
+int bdu_update_batched(const bdu_handle *hs, const double *const *Bs, const double *const *Cs, const int *rs,
+                       int count)
+{
+    if (!hs || !Bs || !Cs || !rs || count < 1) return BDU_EINVAL;
+    for (int i = 0; i < count; ++i) {
+        if (!hs[i] || !Bs[i] || !Cs[i] || rs[i] < 1) return BDU_EINVAL;
+        if (hs[i]->poisoned) return BDU_EDEVICE;
+        for (int j = 0; j < i; ++j)
+            if (hs[j] == hs[i]) return BDU_EINVAL;
+    }
+    hipStream_t st = hs[0]->stream;
+    int maxr = 0;
+    for (int i = 0; i < count; ++i) {
+        bdu_ctx *h = hs[i];
+        int s = ensure_rcap(h, rs[i]);
+        if (s != BDU_OK) return s;
+        if (h->stream != st) HIPCHK(h, hipStreamSynchronize(h->stream));
+        HIPCHK(h, copy_in(h->hd.bst, Bs[i], sizeof(double) * h->m * rs[i], st));
+        HIPCHK(h, copy_in(h->hd.cst, Cs[i], sizeof(double) * h->n * rs[i], st));
+        maxr = std::max(maxr, rs[i]);
+    }
+    // Per pass: the handles still active, grouped by tiling.
+    struct Group {
+        int k0, nw;
+        std::vector<HandleDev *> ptrs;
+        bool spike = false, in_lds = true;
+        int64_t lds = 0;
+        int tiles = 0;
+    };
+    std::vector<std::vector<Group>> passes(maxr);
+    size_t total = 0;
+    for (int p = 0; p < maxr; ++p) {
+        for (int i = 0; i < count; ++i) {
+            if (rs[i] <= p) continue;
+            bdu_ctx *h = hs[i];
+            Group *g = nullptr;
+            for (auto &x : passes[p])
+                if (x.k0 == h->plan->K0 && x.nw == h->plan->NW && x.in_lds == h->lds_gen) g = &x;
+            if (!g) {
+                passes[p].push_back(Group{h->plan->K0, h->plan->NW, {}, false, h->lds_gen, 0, 0});
+                g = &passes[p].back();
+            }
+            g->ptrs.push_back(h->d_hd);
+            g->spike |= h->m > h->n;
+            g->lds = std::max<int64_t>(g->lds, gen_lds_bytes(h->n, h->plan->N));
+            g->tiles = std::max(g->tiles, tiles_of(h));
+        }
+        for (auto &g : passes[p]) total += g.ptrs.size();
+    }
+    std::vector<HandleDev *> flat;
+    flat.reserve(total);
+    for (auto &pp : passes)
+        for (auto &g : pp) flat.insert(flat.end(), g.ptrs.begin(), g.ptrs.end());
+    HandleDev **d_arr = nullptr;
+    if (hipMalloc(&d_arr, sizeof(HandleDev *) * total) != hipSuccess) return BDU_ENOMEM;
+    hipError_t e = hipMemcpyAsync(d_arr, flat.data(), sizeof(HandleDev *) * total, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    size_t off = 0;
+    for (int p = 0; p < maxr && e == hipSuccess; ++p) {
+        for (auto &g : passes[p]) {
+            HandleDev **arr = d_arr + off;
+            int cnt = (int)g.ptrs.size();
+            e = launch_project(arr, cnt, g.tiles, p, st);
+            if (e == hipSuccess)
+                e = run_rotation_stages(arr, cnt, g.spike, g.lds, g.in_lds, g.tiles, g.k0, g.nw, st);
+            off += cnt;
+            if (e != hipSuccess) break;
+        }
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(d_arr);
+    if (e != hipSuccess) {
+        for (int i = 0; i < count; ++i) hs[i]->poisoned = true;
+        return BDU_EDEVICE;
+    }
+    return BDU_OK;
+}
+
+int bdu_givens_device(const double *a, const double *b, int mode, double *c, double *s, double *r, int64_t count)
+{
+    if (!a || !b || !c || !s || !r || count < 0 || (mode != 1 && mode != 2)) return BDU_EINVAL;
+    if (count == 0) return BDU_OK;
+    double *buf = nullptr;
+    if (hipMalloc(&buf, sizeof(double) * 5 * count) != hipSuccess) return BDU_ENOMEM;
+    hipError_t e = hipMemcpy(buf, a, sizeof(double) * count, hipMemcpyDefault);
+    if (e == hipSuccess) e = hipMemcpy(buf + count, b, sizeof(double) * count, hipMemcpyDefault);
+    if (e == hipSuccess) e = launch_givens(buf, buf + count, mode, buf + 2 * count, buf + 3 * count, buf + 4 * count,
+                                           count, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(c, buf + 2 * count, sizeof(double) * count, hipMemcpyDefault);
+    if (e == hipSuccess) e = hipMemcpy(s, buf + 3 * count, sizeof(double) * count, hipMemcpyDefault);
+    if (e == hipSuccess) e = hipMemcpy(r, buf + 4 * count, sizeof(double) * count, hipMemcpyDefault);
+    (void)hipFree(buf);
+    return e == hipSuccess ? BDU_OK : BDU_EDEVICE;
+}
+
+int bdu_plan_stats(int64_t m, int64_t n, int64_t *out)
+{
+    if (!out || m < n || n < 2) return BDU_EINVAL;
+    int k0, nw;
+    bdu_get_tiling(&k0, &nw);
+    hipError_t e;
+    Plan *p = get_plan(m, n, k0, nw, false, &e);
+    out[0] = p->nleft + p->nspike;
+    out[1] = p->nright;
+    out[2] = p->nspike;
+    out[3] = (int64_t)p->chains.size();
+    out[4] = p->ticks;
+    out[5] = p->slots[0];
+    out[6] = p->slots[1];
+    out[7] = p->L;
+    return BDU_OK;
+}
+
+int64_t bdu_plan_rotations(int64_t m, int64_t n, int32_t *side, int64_t *idx, int32_t *phase, int64_t *tick,
+                           int64_t cap)
+{
+    if (m < n || n < 2) return BDU_EINVAL;
+    int k0, nw;
+    bdu_get_tiling(&k0, &nw);
+    hipError_t e;
+    Plan *p = get_plan(m, n, k0, nw, false, &e);
+    int64_t k = 0;
+    auto emit = [&](int sd, int64_t i, int ph, int64_t tk) {
+        if (k < cap) {
+            if (side) side[k] = sd;
+            if (idx) idx[k] = i;
+            if (phase) phase[k] = ph;
+            if (tick) tick[k] = tk;
+        }
+        ++k;
+    };
+    for (int64_t t = 0; t < p->nspike; ++t) emit(0, m - 1 - t, 0, -1);
+    for (const GenChain &g : p->chains) {
+        if (g.type == CH_FOLD) {
+            emit(2, p->N - 1, 3, g.tau0);
+            continue;
+        }
+        for (int q = 0; q < g.len; ++q) {
+            Rot r = decode(g.type, g.param, q);
+            emit(r.side, r.i, chain_phase(g.type), (int64_t)g.tau0 + q);
+        }
+    }
+    return k;
+}
+
+}  // extern "C"

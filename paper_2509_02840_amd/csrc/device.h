@@ -1,0 +1,39 @@
+// device.h -- per-handle device descriptor shared by the host library and
+// the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "schedule.h"
+
+namespace bdu {
+
+// Everything a kernel needs to update one factorization A = Q Bd P^T.
+// Q is m x m and P is n x n, column-major; their leading dimensions ldq, ldp
+// are m and n rounded up to a multiple of 64 (the padding rows are zero).
+struct HandleDev {
+    double *Q, *P, *d, *e;
+    double *u, *v;          // projections u = Q^T b (m), v = P^T c (n)
+    double *bst, *cst;      // staged update columns: B (m x rcap), C (n x rcap)
+    double2 *csL, *csR;     // left / right rotation streams in applier layout
+    double2 *csSp;          // spike rotations, in order
+    double *band;           // global band scratch for large n (else unused)
+    const GenChain *chains; // non-empty chains, schedule order
+    const BlockDesc *blkL, *blkR;
+    int64_t ticks;          // generation ticks
+    int32_t m, n, N, nchains, nb1, nb2;
+    int32_t ldq, ldp;
+    int32_t K0, NW, K, S;
+};
+
+constexpr int kGenThreads = 256;
+
+// LDS bytes the generation kernel needs for n columns and N rows.
+inline int64_t gen_lds_bytes(int64_t n, int64_t N)
+{
+    return 8 * (6 * (N + 8) + (N + 8) + (n + 8) + 2);
+}
+
+constexpr int64_t kMaxGenLds = 160 * 1024;
+
+}  // namespace bdu

@@ -1,0 +1,21 @@
+// kernels.h -- launchers of the device kernels (kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device.h"
+
+namespace bdu {
+
+// Every launcher takes a device array of `count` device pointers to
+// HandleDev.  The projection reads column `pass` of the staged B and C.
+hipError_t launch_project(HandleDev *const *hs, int count, int max_tiles, int pass, hipStream_t st);
+hipError_t launch_spike(HandleDev *const *hs, int count, hipStream_t st);
+hipError_t launch_gen(HandleDev *const *hs, int count, int64_t lds_bytes, bool in_lds, hipStream_t st);
+hipError_t launch_apply(HandleDev *const *hs, int count, int max_panels, int k0, int nw, hipStream_t st);
+hipError_t launch_fill_identity(double2 *p, int64_t count, hipStream_t st);
+bool tiling_supported(int k0, int nw);
+hipError_t launch_givens(const double *a, const double *b, int mode, double *c, double *s, double *r,
+                         int64_t count, hipStream_t st);
+
+}  // namespace bdu

@@ -1,0 +1,586 @@
+// kernels.hip -- gfx950 kernels of the Givens bidiagonal update
+// (Brust & Saunders, Section 3.4, Algorithm 2).  FP64 throughout.
+//
+//  project_kernel  u = Q^T b, v = P^T c (eq. bidiagsubproblem); one lane per
+//                  output, sequential fma over the rows, 64x64 tiles staged
+//                  through LDS so that global reads stay coalesced.
+//  spike_kernel    m > n: the reverse-order rotations that fold u(n+1:m)
+//                  into u(n+1); a dependent chain, one lane.
+//  gen_kernel      generation of phases 1 and 2 on the band held in LDS (or
+//                  global memory for large n): one thread per chain in
+//                  flight, one rotation per tick, ticks separated by barriers.
+//  apply_kernel    accumulates the rotation streams into Q and P
+//                  (eq. bidiagplus): lanes own rows, a register window of
+//                  columns slides along each block of chains, and the
+//                  wavefronts of a workgroup form a pipeline that passes
+//                  finished columns through LDS.
+//
+// Rounding: every operation is rounded on its own (-ffp-contract=off);
+// fma only where written; sqrt and division are IEEE.
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+#include "kernels.h"
+#include "schedule.h"
+
+namespace bdu {
+
+#define GLOBAL __attribute__((address_space(1)))
+#define CONSTANT __attribute__((address_space(4)))
+
+// Pointers read from a descriptor are generic; the kernels know which memory
+// they point to.  Global pointers give global (not flat) memory instructions,
+// constant pointers with a uniform index give scalar loads.
+template <typename T>
+__device__ __forceinline__ GLOBAL T *gptr(T *p)
+{
+    return (GLOBAL T *)(uintptr_t)p;
+}
+template <typename T>
+__device__ __forceinline__ const CONSTANT T *kptr(const T *p)
+{
+    return (const CONSTANT T *)(uintptr_t)p;
+}
+
+__device__ __forceinline__ BlockDesc load_block(const BlockDesc *p, int b)
+{
+    const CONSTANT BlockDesc *q = kptr(p) + b;
+    BlockDesc d;
+    d.base = q->base;
+    d.lmax = q->lmax;
+    d.nfront = q->nfront;
+    d.phase = q->phase;
+    d.off = q->off;
+    return d;
+}
+
+// ---- primitives (eq. giv1) -------------------------------------------------
+
+// Rotation generator: mode 1 gives [c -s; s c][a;b] = [0;r], mode 2 gives
+// [r;0]; r = +sqrt(a^2 + b^2) with an exact power-of-two scaling when the
+// larger magnitude is extreme; identity when the target is already zero.
+__device__ __forceinline__ void givens(double a, double b, int mode, double &c, double &s, double &r)
+{
+    double target = (mode == 1) ? a : b;
+    if (target == 0.0) {
+        c = 1.0;
+        s = 0.0;
+        r = (mode == 1) ? b : a;
+        return;
+    }
+    double fa = fabs(a), fb = fabs(b);
+    double big = fa > fb ? fa : fb;
+    double sc = 1.0, unsc = 1.0;
+    if (big > 0x1p500) {
+        sc = 0x1p-600;
+        unsc = 0x1p600;
+    } else if (big < 0x1p-500) {
+        sc = 0x1p600;
+        unsc = 0x1p-600;
+    }
+    double as = a * sc, bs = b * sc;
+    double rs = sqrt(fma(as, as, bs * bs));
+    if (mode == 1) {
+        c = bs / rs;
+        s = as / rs;
+    } else {
+        c = as / rs;
+        s = -(bs / rs);
+    }
+    r = rs * unsc;
+}
+
+__device__ __forceinline__ void rot(double c, double s, double &x, double &y)
+{
+    double x0 = x, y0 = y;
+    x = fma(c, x0, -(s * y0));
+    y = fma(s, x0, c * y0);
+}
+
+// ---- projection ---------------------------------------------------------------
+
+// grid (tiles, handles), 64 threads.  Tile t < ceil(m/64) projects with Q,
+// the rest with P.  Lane l of tile t owns output column 64 t + l.
+__global__ __launch_bounds__(64) void project_kernel(HandleDev *const *hs, int pass)
+{
+    const CONSTANT HandleDev *h = kptr(hs[blockIdx.y]);
+    const int m = h->m, n = h->n;
+    const int qt = (m + 63) / 64, pt = (n + 63) / 64;
+    int tile = blockIdx.x;
+    if (tile >= qt + pt) return;
+    const GLOBAL double *A;
+    const GLOBAL double *x;
+    GLOBAL double *out;
+    int rows, ld;
+    if (tile < qt) {
+        A = gptr(h->Q); x = gptr(h->bst) + (int64_t)pass * m; out = gptr(h->u); rows = m; ld = h->ldq;
+    } else {
+        tile -= qt;
+        A = gptr(h->P); x = gptr(h->cst) + (int64_t)pass * n; out = gptr(h->v); rows = n; ld = h->ldp;
+    }
+    const int cols = rows;
+    __shared__ double tileA[64 * 65];
+    __shared__ double xs[64];
+    const int lane = threadIdx.x;
+    const int col0 = tile * 64;
+    double acc = 0.0;
+    for (int j0 = 0; j0 < rows; j0 += 64) {
+        const int jn = rows - j0 < 64 ? rows - j0 : 64;
+        // coalesced: lane reads row j0+lane of each of the tile's 64 columns
+        // (rows past the end are padding inside the leading dimension)
+#pragma unroll 16
+        for (int c = 0; c < 64; ++c) {
+            const int col = col0 + c < cols ? col0 + c : cols - 1;
+            tileA[c * 65 + lane] = A[(int64_t)col * ld + j0 + lane];
+        }
+        xs[lane] = lane < jn ? x[j0 + lane] : 0.0;
+        __syncthreads();
+        for (int j = 0; j < jn; ++j) acc = fma(tileA[lane * 65 + j], xs[j], acc);
+        __syncthreads();
+    }
+    if (col0 + lane < cols) out[col0 + lane] = acc;
+}
+
+// ---- spike (m > n) -----------------------------------------------------------------
+
+// grid (handles), 64 threads.  For j = m..n+2 the pair (u_{j-1}, u_j) is
+// rotated onto u_{j-1} (mode 2).  Rows n+1.. of the band are zero, so only u
+// and the rotation list change.
+__global__ __launch_bounds__(64) void spike_kernel(HandleDev *const *hs)
+{
+    const CONSTANT HandleDev *h = kptr(hs[blockIdx.x]);
+    if (h->m <= h->n) return;
+    const int m = h->m, n = h->n;
+    __shared__ double chunk[64];
+    double *u = h->u;
+    double surv = u[m - 1];  // u_m
+    int j = m;               // next pair is (u_{j-1}, u_j)
+    while (j >= n + 2) {
+        const int lo = (j - 64 > n + 1) ? j - 64 : n + 1;  // 1-based u indices lo..j-1
+        const int cnt = j - lo;
+        if ((int)threadIdx.x < cnt) chunk[threadIdx.x] = u[lo - 1 + threadIdx.x];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int q = cnt - 1; q >= 0; --q) {  // pair (u_{lo+q}, u_{lo+q+1})
+                double c, s, r;
+                givens(chunk[q], surv, 2, c, s, r);
+                h->csSp[m - (lo + q + 1)] = make_double2(c, s);
+                chunk[q] = r;
+                surv = r;
+            }
+        }
+        __syncthreads();
+        j = lo;
+    }
+    if (threadIdx.x == 0) {
+        u[n] = surv;  // u_{n+1}
+        for (int i = n + 1; i < m; ++i) u[i] = 0.0;
+    }
+}
+
+// ---- generation -------------------------------------------------------------------
+
+// Band storage: row r (1-based, -3..N+4) at (r+3)*6, the entry in column c
+// at offset c - r in [-2, 3].  Entries outside that band read as zero and are
+// never written: the schedule keeps them zero.
+struct Band {
+    double *s;
+    __device__ __forceinline__ int cell(int r, int c) const
+    {
+        int o = c - r;
+        return (o < -2 || o > 3) ? -1 : (r + 3) * 6 + (o + 2);
+    }
+};
+
+template <bool IN_LDS>
+__global__ __launch_bounds__(kGenThreads) void gen_kernel(HandleDev *const *hs)
+{
+    extern __shared__ double smem[];
+    const CONSTANT HandleDev *h = kptr(hs[blockIdx.x]);
+    const int n = h->n, N = h->N;
+    double *S = IN_LDS ? smem : h->band;
+    double *U = S + 6 * (N + 8);  // u_i at U[i+3]
+    double *V = U + (N + 8);      // v_j at V[j+3]
+    const int tid = threadIdx.x;
+    const int nt = blockDim.x;
+    const int total = 6 * (N + 8) + (N + 8) + (n + 8);
+    for (int k = tid; k < total; k += nt) S[k] = 0.0;
+    __syncthreads();
+    Band band{S};
+    for (int i = 1 + tid; i <= n; i += nt) {
+        S[band.cell(i, i)] = h->d[i - 1];
+        if (i < n) S[band.cell(i, i + 1)] = h->e[i - 1];
+        V[i + 3] = h->v[i - 1];
+    }
+    for (int i = 1 + tid; i <= N; i += nt) U[i + 3] = h->u[i - 1];
+    __syncthreads();
+
+    const int K = h->K, K0 = h->K0, SS = h->S, nb1 = h->nb1;
+    int ci = tid;
+    GenChain g, gn;
+    g.len = 0;
+    if (ci < h->nchains) g = h->chains[ci];
+    if (ci + nt < h->nchains) gn = h->chains[ci + nt];
+    const int64_t ticks = h->ticks;
+    for (int64_t t = 0; t < ticks; ++t) {
+        if (ci < h->nchains) {
+            const int s = (int)(t - g.tau0);
+            if (s >= 0) {
+                if (g.type == CH_FOLD) {
+                    // u v^T now touches only (N-1, n) and (N, n)
+                    const int a = band.cell(N - 1, n), b = band.cell(N, n);
+                    S[a] = fma(U[N - 1 + 3], V[n + 3], S[a]);
+                    S[b] = fma(U[N + 3], V[n + 3], S[b]);
+                } else {
+                    const Rot r = decode(g.type, g.param, s);
+                    int ga, gb;
+                    if (r.gvec) {
+                        double *vec = r.side == 0 ? U : V;
+                        ga = (int)(vec - S) + r.i + 3;
+                        gb = ga + 1;
+                    } else {
+                        ga = band.cell(r.gr0, r.gc0);
+                        gb = band.cell(r.gr1, r.gc1);
+                    }
+                    double c, sn, rr;
+                    givens(S[ga], S[gb], r.mode, c, sn, rr);
+                    // rotate the seven band pairs of the window and the vector pair
+                    int ax[8], ay[8];
+                    #pragma unroll
+                    for (int q = 0; q < 7; ++q) {
+                        if (r.side == 0) {
+                            ax[q] = band.cell(r.i, r.i - 2 + q);
+                            ay[q] = band.cell(r.i + 1, r.i - 2 + q);
+                        } else {
+                            ax[q] = band.cell(r.i - 3 + q, r.i);
+                            ay[q] = band.cell(r.i - 3 + q, r.i + 1);
+                        }
+                    }
+                    const bool ph1 = g.type <= CH_P1B;
+                    if (ph1) {
+                        double *vec = r.side == 0 ? U : V;
+                        ax[7] = (int)(vec - S) + r.i + 3;
+                        ay[7] = ax[7] + 1;
+                    } else {
+                        ax[7] = -1;
+                        ay[7] = -1;
+                    }
+                    double xv[8], yv[8];
+                    #pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        xv[q] = ax[q] >= 0 ? S[ax[q]] : 0.0;
+                        yv[q] = ay[q] >= 0 ? S[ay[q]] : 0.0;
+                    }
+                    #pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        rot(c, sn, xv[q], yv[q]);
+                        if (ax[q] >= 0) S[ax[q]] = xv[q];
+                        if (ay[q] >= 0) S[ay[q]] = yv[q];
+                    }
+                    if (r.mode == 1) {
+                        S[ga] = 0.0;
+                        S[gb] = rr;
+                    } else {
+                        S[ga] = rr;
+                        S[gb] = 0.0;
+                    }
+                    // slot of this rotation in the applier layout
+                    const int ph = chain_phase(g.type);
+                    const int tg = chain_in_phase(g.type, g.param);
+                    const int b = tg / K, tin = tg - b * K;
+                    const int w = tin / K0, tl = tin - w * K0;
+                    const BlockDesc *blk = (r.side == 0 ? h->blkL : h->blkR) + (ph == 1 ? 0 : nb1) + b;
+                    const int lam0 = lam0_of_pair(ph, blk->base, r.i);
+                    const int64_t F = lam0 / 3 + tl + w * SS;
+                    double2 *cs = r.side == 0 ? h->csL : h->csR;
+                    cs[blk->off + F * K + tin] = make_double2(c, sn);
+                }
+                if (s == g.len - 1) {
+                    ci += nt;
+                    g = gn;
+                    if (ci + nt < h->nchains) gn = h->chains[ci + nt];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    for (int i = 1 + tid; i <= n; i += nt) {
+        h->d[i - 1] = S[band.cell(i, i)];
+        if (i < n) h->e[i - 1] = S[band.cell(i, i + 1)];
+    }
+}
+
+// ---- application ----------------------------------------------------------------
+
+// Residue mod 3 of the lower local column of chain t's pairs in a block of
+// K chains (K0 a multiple of 6 keeps it the same in every wavefront).
+// mode 0: phase 1 left, 1: phase 1 right, 2: phase 2 left, 3: phase 2 right.
+__host__ __device__ constexpr int rho_of(int mode, int K, int t)
+{
+    int i = t >> 1, h = t & 1;
+    int v = mode == 0 ? K / 2 - i + h : mode == 1 ? K / 2 + 1 - i + h : mode == 2 ? i + 2 * h : i + 2 - h;
+    return ((v % 3) + 3) % 3;
+}
+
+__host__ __device__ constexpr int pmod(int a, int b) { return ((a % b) + b) % b; }
+
+// Sweep one block of K = K0*NW chains over this workgroup's 64 rows.
+// Wavefront w holds local columns [3(f-K0+1), 3f+9] of its rows in registers
+// (f = its local front), applies chains w*K0 .. w*K0+K0-1 at each front, and
+// hands finished columns to wavefront w+1 through an LDS ring (the last
+// wavefront writes them back to memory).  Every front of the loop has a slot
+// per chain (identity where the chain has no rotation), so the body has no
+// data-dependent branches around the rotations.  Columns outside the block
+// are loaded from a clamped address and never stored: an identity rotation
+// leaves a finite partner unchanged, and real rotations never touch them.
+template <int K0, int NW, int MODE>
+__device__ __forceinline__ void sweep(GLOBAL double *__restrict__ X, int ld, int ncols, int row,
+                                      const CONSTANT double *__restrict__ cs, const BlockDesc bd,
+                                      double *ring, int w, int lane)
+{
+    constexpr int U = K0 + 3, WSZ = 3 * U, S = U, K = K0 * NW;
+    constexpr bool DESC = MODE < 2;
+    constexpr int DIR = DESC ? -1 : 1;
+    const int lmax = bd.lmax;
+    if (lmax < 0) return;
+    const int nfront = bd.nfront;
+    const int base = bd.base;
+    // local columns lam in [lam_lo, lam_hi] exist in this block and matrix
+    const int lam_hi = lmax + 1;
+    const int lam_lo = DESC ? (base - ncols > 0 ? base - ncols : 0) : 0;
+    const int col0 = base - 1;  // 0-based matrix column of local column 0
+    double buf[WSZ];
+#pragma unroll
+    for (int i = 0; i < WSZ; ++i) buf[i] = 0.0;
+
+    auto gload = [&](int lam) -> double {
+        int c = col0 + DIR * lam;
+        c = c < 0 ? 0 : (c >= ncols ? ncols - 1 : c);
+        return X[(int64_t)c * ld + row];
+    };
+    // ring slot of local column lam is lam mod WSZ, the same as its register
+    double *rin = ring + (w > 0 ? w - 1 : 0) * WSZ * 64 + lane;
+    double *rout = ring + w * WSZ * 64 + lane;
+
+    if (w == 0) {
+#pragma unroll
+        for (int k = 0; k <= 6; ++k) buf[k] = gload(k);
+    }
+    for (int F0 = 0; F0 < nfront; F0 += U) {
+#pragma unroll
+        for (int phi = 0; phi < U; ++phi) {
+            const int F = F0 + phi;
+            const int f = F - w * S;
+            // new columns: from memory (first wavefront, two fronts ahead) or
+            // from the previous wavefront's ring
+            if (w == 0) {
+#pragma unroll
+                for (int k = 7; k <= 9; ++k) buf[pmod(3 * phi + k, WSZ)] = gload(3 * f + k);
+            } else {
+                if (phi == 0 && f == 0) buf[0] = rin[0];
+#pragma unroll
+                for (int k = 1; k <= 3; ++k) buf[pmod(3 * phi + k, WSZ)] = rin[pmod(3 * phi + k, WSZ) * 64];
+            }
+            // this wavefront's K0 rotations at front F.  The empty asm makes
+            // the coefficient address opaque, so their scalar loads are issued
+            // here and not hoisted over the whole unrolled sweep.
+            // Coefficients come in groups of G rotations; the next group's
+            // address is released one group early so its loads overlap.
+            constexpr int G = 6;
+            const CONSTANT double *csF = cs + 2 * ((int64_t)F * K + w * K0);
+            const CONSTANT double *pg = csF;
+            asm volatile("" : "+s"(pg));
+#pragma unroll
+            for (int g = 0; g < K0 / G; ++g) {
+                const CONSTANT double *pn = csF + 2 * G * (g + 1);
+                if (g + 1 < K0 / G) asm volatile("" : "+s"(pn));
+#pragma unroll
+                for (int q = 0; q < G; ++q) {
+                    const int t = g * G + q;
+                    const int l0 = 3 * (phi - t) + rho_of(MODE, K, t);
+                    const int sx = pmod(l0 + (DESC ? 1 : 0), WSZ);
+                    const int sy = pmod(l0 + (DESC ? 0 : 1), WSZ);
+                    rot(pg[2 * q], pg[2 * q + 1], buf[sx], buf[sy]);
+                }
+                pg = pn;
+            }
+            // finished columns leave the window
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int lam = 3 * (f - K0 + 1) + k;
+                const int sl = pmod(3 * (phi - K0 + 1) + k, WSZ);
+                if (w == NW - 1) {
+                    if (lam >= lam_lo && lam <= lam_hi) X[(int64_t)(col0 + DIR * lam) * ld + row] = buf[sl];
+                } else {
+                    rout[sl * 64] = buf[sl];
+                }
+            }
+            if (NW > 1) __syncthreads();
+            // keep fronts in order: the window is materialised here, so the
+            // scheduler cannot interleave two fronts (and their coefficients)
+#pragma unroll
+            for (int i = 0; i < WSZ; ++i) asm volatile("" : "+v"(buf[i]));
+        }
+    }
+}
+
+// Spike rotations on Q columns (j-1, j), j = m..n+2, for this lane's row:
+// a running carry keeps column j between consecutive rotations.
+__device__ void spike_apply(GLOBAL double *Q, int ld, int m, int n, int row, const CONSTANT double *cs)
+{
+    double carry = Q[(int64_t)(m - 1) * ld + row];
+    for (int t = 0; t < m - n - 1; ++t) {
+        const int xc = m - 2 - t;  // 0-based column of the pair's first entry
+        double x = Q[(int64_t)xc * ld + row];
+        rot(cs[2 * t], cs[2 * t + 1], x, carry);
+        Q[(int64_t)(xc + 1) * ld + row] = carry;
+        carry = x;
+    }
+    Q[(int64_t)n * ld + row] = carry;
+}
+
+// grid (panels, handles): panels [0, ceil(m/64)) update Q, the rest P.  Q
+// and P have leading dimensions padded to a multiple of 64 rows.
+template <int K0, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(1, 2))) void apply_kernel(
+    HandleDev *const *hs)
+{
+    const CONSTANT HandleDev *h = kptr(hs[blockIdx.y]);
+    const int m = h->m, n = h->n;
+    const int qp = (m + 63) / 64, pp = (n + 63) / 64;
+    const int pid = blockIdx.x;
+    if (pid >= qp + pp) return;
+    constexpr int WSZ = 3 * (K0 + 3);
+    __shared__ double ring[(NW > 1 ? NW - 1 : 1) * WSZ * 64];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    // the ring starts finite (stale slots may meet identity rotations)
+    for (int i = threadIdx.x; i < (NW > 1 ? NW - 1 : 1) * WSZ * 64; i += 64 * NW) ring[i] = 0.0;
+    const int nb1 = h->nb1, nb2 = h->nb2;
+    if (pid < qp) {
+        const int row = pid * 64 + lane;
+        GLOBAL double *Q = gptr(h->Q);
+        if (m > n && w == 0) spike_apply(Q, h->ldq, m, n, row, kptr((const double *)h->csSp));
+        __syncthreads();
+        for (int b = 0; b < nb1; ++b) {
+            const BlockDesc bd = load_block(h->blkL, b);
+            sweep<K0, NW, 0>(Q, h->ldq, m, row, kptr((const double *)h->csL) + 2 * bd.off, bd, ring, w, lane);
+            __syncthreads();
+        }
+        for (int b = nb1; b < nb1 + nb2; ++b) {
+            const BlockDesc bd = load_block(h->blkL, b);
+            sweep<K0, NW, 2>(Q, h->ldq, m, row, kptr((const double *)h->csL) + 2 * bd.off, bd, ring, w, lane);
+            __syncthreads();
+        }
+    } else {
+        const int row = (pid - qp) * 64 + lane;
+        GLOBAL double *P = gptr(h->P);
+        for (int b = 0; b < nb1; ++b) {
+            const BlockDesc bd = load_block(h->blkR, b);
+            sweep<K0, NW, 1>(P, h->ldp, n, row, kptr((const double *)h->csR) + 2 * bd.off, bd, ring, w, lane);
+            __syncthreads();
+        }
+        for (int b = nb1; b < nb1 + nb2; ++b) {
+            const BlockDesc bd = load_block(h->blkR, b);
+            sweep<K0, NW, 3>(P, h->ldp, n, row, kptr((const double *)h->csR) + 2 * bd.off, bd, ring, w, lane);
+            __syncthreads();
+        }
+    }
+}
+
+// The rotation primitive on arrays (checks the device arithmetic against the
+// reference bit for bit).
+__global__ void givens_kernel(const double *a, const double *b, int mode, double *c, double *s, double *r,
+                              int64_t count)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double cc, ss, rr;
+        givens(a[i], b[i], mode, cc, ss, rr);
+        c[i] = cc;
+        s[i] = ss;
+        r[i] = rr;
+    }
+}
+
+hipError_t launch_givens(const double *a, const double *b, int mode, double *c, double *s, double *r,
+                         int64_t count, hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(givens_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a, b, mode, c, s, r, count);
+    return hipGetLastError();
+}
+
+// Fill rotation streams with the identity (c, s) = (1, 0).
+__global__ void fill_identity_kernel(double2 *p, int64_t count)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = make_double2(1.0, 0.0);
+}
+
+// ---- launchers ---------------------------------------------------------------------
+
+hipError_t launch_project(HandleDev *const *hs, int count, int max_tiles, int pass, hipStream_t st)
+{
+    hipLaunchKernelGGL(project_kernel, dim3(max_tiles, count), dim3(64), 0, st, hs, pass);
+    return hipGetLastError();
+}
+
+hipError_t launch_spike(HandleDev *const *hs, int count, hipStream_t st)
+{
+    hipLaunchKernelGGL(spike_kernel, dim3(count), dim3(64), 0, st, hs);
+    return hipGetLastError();
+}
+
+hipError_t launch_gen(HandleDev *const *hs, int count, int64_t lds_bytes, bool in_lds, hipStream_t st)
+{
+    if (in_lds) {
+        static bool attr = false;
+        if (!attr) {
+            hipError_t e = hipFuncSetAttribute((const void *)gen_kernel<true>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxGenLds);
+            if (e != hipSuccess) return e;
+            attr = true;
+        }
+        hipLaunchKernelGGL(gen_kernel<true>, dim3(count), dim3(kGenThreads), (size_t)lds_bytes, st, hs);
+    } else {
+        hipLaunchKernelGGL(gen_kernel<false>, dim3(count), dim3(kGenThreads), 0, st, hs);
+    }
+    return hipGetLastError();
+}
+
+template <int K0, int NW>
+static hipError_t launch_apply_t(HandleDev *const *hs, int count, int max_panels, hipStream_t st)
+{
+    hipLaunchKernelGGL((apply_kernel<K0, NW>), dim3(max_panels, count), dim3(64 * NW), 0, st, hs);
+    return hipGetLastError();
+}
+
+bool tiling_supported(int k0, int nw)
+{
+    return (k0 == 6 || k0 == 12) && (nw == 1 || nw == 2 || nw == 4);
+}
+
+hipError_t launch_apply(HandleDev *const *hs, int count, int max_panels, int k0, int nw, hipStream_t st)
+{
+#define BDU_APPLY_CASE(A, B) \
+    if (k0 == A && nw == B) return launch_apply_t<A, B>(hs, count, max_panels, st);
+    BDU_APPLY_CASE(6, 1) BDU_APPLY_CASE(6, 2) BDU_APPLY_CASE(6, 4)
+    BDU_APPLY_CASE(12, 1) BDU_APPLY_CASE(12, 2) BDU_APPLY_CASE(12, 4)
+#undef BDU_APPLY_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_fill_identity(double2 *p, int64_t count, hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(fill_identity_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p, count);
+    return hipGetLastError();
+}
+
+}  // namespace bdu

@@ -1,0 +1,46 @@
+// plan.h -- host-side rotation schedule for one shape (m, n) and applier tiling.
+#pragma once
+#include <stdint.h>
+
+#include <memory>
+#include <vector>
+
+#include "schedule.h"
+
+namespace bdu {
+
+struct Plan {
+    int64_t m = 0, n = 0, N = 0;
+    int K0 = 0, NW = 0, K = 0, S = 0;
+    int L = 0;                      // generation threads
+    std::vector<GenChain> chains;   // non-empty chains in schedule order (with the fold)
+    int64_t ticks = 0;              // generation ticks
+    int64_t nleft = 0, nright = 0;  // rotations of phases 1 and 2 per side
+    int64_t nspike = 0;             // spike rotations (m > n)
+    std::vector<BlockDesc> blocks[2];  // per side: phase-1 blocks, then phase-2 blocks
+    int nb1 = 0, nb2 = 0;
+    int64_t slots[2] = {0, 0};
+
+    // device copies (owned by the plan cache, freed at unload)
+    GenChain *d_chains = nullptr;
+    BlockDesc *d_blocks[2] = {nullptr, nullptr};
+};
+
+// Build (no device work).  gen_threads is the number of generation threads.
+std::unique_ptr<Plan> build_plan(int64_t m, int64_t n, int K0, int NW, int gen_threads);
+
+// Footprint of a rotation on the band-row line (conservative): left rotation
+// L(i) touches rows i, i+1 (and u_i, u_{i+1}); right rotation R(j) touches
+// rows j-3..j+3 of columns j, j+1 (and v_j, v_{j+1}).
+inline void footprint(const Rot &r, int *lo, int *hi)
+{
+    if (r.side == 0) {
+        *lo = r.i;
+        *hi = r.i + 1;
+    } else {
+        *lo = r.i - 3;
+        *hi = r.i + 3;
+    }
+}
+
+}  // namespace bdu

@@ -1,0 +1,111 @@
+"""Host-side logic of the GPU library (no device needed).
+
+- The schedule the device decodes in closed form is the oracle's rotation
+  sequence, rotation for rotation (side, index, phase).
+- The generation ticks respect every data dependency: two rotations that
+  touch a common entry of the working matrix, of u or of v run at ticks in
+  schedule order.  Entry sets are derived here from the rotation windows,
+  independently of the library's conservative row intervals.
+- The library exports every function its header declares.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2509_02840_amd import bdu
+from paper_2509_02840_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+SHAPES = [(2, 2), (3, 2), (3, 3), (4, 3), (5, 5), (7, 4), (12, 12), (14, 12), (13, 12), (30, 20),
+          (31, 31), (45, 40), (64, 64), (65, 64), (100, 37)]
+
+
+@pytest.mark.parametrize("m,n", SHAPES)
+def test_decoded_schedule_is_the_oracle_sequence(oracle, m, n):
+    side, idx, ph, tick = bdu.plan_rotations(m, n)
+    f = W.factorization(m, n, 1)
+    st = oracle.State(f.Q, f.d, f.e, f.P)
+    rng = np.random.default_rng(3)
+    cnt, tr, _ = oracle.bgu_pass(st, rng.standard_normal(m), rng.standard_normal(n),
+                                 flags=oracle.NO_QP, trace_cap=10 ** 6)
+    keep = side != 2
+    assert np.count_nonzero(side == 2) == 1  # the fold
+    assert np.array_equal(side[keep], tr["side"])
+    assert np.array_equal(idx[keep], tr["i"])
+    assert np.array_equal(ph[keep], tr["phase"])
+    stats = bdu.plan_stats(m, n)
+    assert stats["left"] == cnt[0] and stats["right"] == cnt[1] and stats["spike"] == cnt[2]
+
+
+def _cells(side, i, m, n, N):
+    """Entries a step reads and writes: ('W', r, c), ('u', i), ('v', j)."""
+    out = []
+    if side == 0:  # left rotation on rows i, i+1; columns i-2..i+4 of the band window
+        for c in range(max(1, i - 2), min(n, i + 4) + 1):
+            if i + 1 <= N:
+                out += [("W", i, c), ("W", i + 1, c)]
+        out += [("u", i), ("u", i + 1)]
+    elif side == 1:  # right rotation on columns i, i+1; rows i-3..i+3
+        for r in range(max(1, i - 3), min(N, i + 3) + 1):
+            out += [("W", r, i), ("W", r, i + 1)]
+        out += [("v", i), ("v", i + 1)]
+    else:  # fold: (N-1, n), (N, n), u_{N-1}, u_N, v_n
+        out = [("W", N - 1, n), ("W", N, n), ("u", N - 1), ("u", N), ("v", n)]
+    return out
+
+
+@pytest.mark.parametrize("m,n", [(12, 12), (14, 12), (31, 31), (45, 40), (64, 64), (100, 37), (90, 90)])
+def test_generation_ticks_respect_dependencies(m, n):
+    side, idx, ph, tick = bdu.plan_rotations(m, n)
+    N = n if m == n else n + 1
+    last = {}
+    for s, i, p, t in zip(side, idx, ph, tick):
+        if p == 0:
+            assert t == -1  # the spike runs before generation
+            continue
+        for cell in _cells(int(s), int(i), m, n, N):
+            prev = last.get(cell, -1)
+            assert t > prev, (s, i, p, t, cell, prev)
+            last[cell] = t
+
+
+def test_ticks_are_parallel():
+    """Generation runs many chains at once: far fewer ticks than rotations."""
+    st = bdu.plan_stats(2048, 2048)
+    assert st["ticks"] * 50 < st["left"] + st["right"]
+
+
+def test_library_exports_every_declared_function():
+    hdr = open(os.path.join(ROOT, "include", "bdu.h")).read()
+    names = re.findall(r"^\w[\w\s\*]*?\b(bdu_\w+)\s*\(", hdr, flags=re.M)
+    assert len(names) >= 15
+    L = bdu.lib()
+    for nm in names:
+        assert hasattr(L, nm), nm
+
+
+def test_invalid_arguments_fail_without_a_device():
+    import ctypes
+    L = bdu.lib()
+    h = ctypes.c_void_p()
+    one = np.ones(4)
+    assert L.bdu_create(2, 3, one.ctypes.data, one.ctypes.data, one.ctypes.data, one.ctypes.data,
+                        ctypes.byref(h)) == bdu.BDU_EINVAL  # m < n
+    assert L.bdu_create(1, 1, one.ctypes.data, one.ctypes.data, one.ctypes.data, one.ctypes.data,
+                        ctypes.byref(h)) == bdu.BDU_EINVAL  # n < 2
+    assert L.bdu_create(4, 4, None, one.ctypes.data, one.ctypes.data, one.ctypes.data,
+                        ctypes.byref(h)) == bdu.BDU_EINVAL
+    assert L.bdu_update(None, one.ctypes.data, one.ctypes.data, 1) == bdu.BDU_EINVAL
+    assert L.bdu_update_batched(None, None, None, None, 0) == bdu.BDU_EINVAL
+    assert L.bdu_set_tiling(7, 1) == bdu.BDU_EINVAL
+    assert L.bdu_plan_stats(3, 4, None) == bdu.BDU_EINVAL
+    assert bdu.lib().bdu_strerror(bdu.BDU_ENOMEM) == b"out of device memory"
+
+
+def test_footprint_grows_with_size():
+    a, b = bdu.footprint_bytes(512, 512), bdu.footprint_bytes(1024, 1024)
+    assert 3.5 * a < b < 4.5 * a
+    assert b > 16 * 1024 * 1024  # Q and P alone
