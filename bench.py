@@ -1,0 +1,199 @@
+"""Benchmark: FP64 rank-1 bidiagonal updates per second on one MI355X.
+
+Workload (square streams, m = n = 2048, the tiny-config construction at
+that size): Q0, P0 are Householder-QR factors of N(0,1) matrices, d ~ U(1,10),
+e ~ U(0,1); every update is b ~ N(0,1)/sqrt(m), c ~ N(0,1)/sqrt(n).
+
+- batched (the reported value): S streams; one step is one rank-1 update of
+  every stream in one bdu_update_batched call.  value = S * steps / time.
+- plain: one stream, one bdu_update per rank-1 update, timed beside it.
+
+A step runs the whole path: projection, generation, and accumulation into Q
+and P.  Inputs are resident in device memory before the timed region.  The
+applier (the dominant kernel) is timed live with HIP events on the stream it
+runs on; its roofline figure is the FP64 vector ALU peak.  The CPU baseline
+is the test oracle on a bounded sample (one rank-1 update of one stream).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FP64 rank-1 updates/sec + p50/p99 latency, batched vs plain, n=2048"
+FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CUs x 128 FP64 flop/clk x 2.4 GHz
+
+
+def make_stream(torch, gen, n: int):
+    """Q0, d0, e0, P0 on the device (Householder QR of N(0,1) on the GPU)."""
+    dev = torch.device("cuda:0")
+    G1 = torch.randn((n, n), generator=gen, dtype=torch.float64, device=dev)
+    G2 = torch.randn((n, n), generator=gen, dtype=torch.float64, device=dev)
+    Q, _ = torch.linalg.qr(G1)
+    P, _ = torch.linalg.qr(G2)
+    Q = Q.T.contiguous().T  # column-major
+    P = P.T.contiguous().T
+    d = 1.0 + 9.0 * torch.rand(n, generator=gen, dtype=torch.float64, device=dev)
+    e = torch.rand(n - 1, generator=gen, dtype=torch.float64, device=dev)
+    return Q, d, e, P
+
+
+def make_updates(torch, gen, n: int, count: int):
+    dev = torch.device("cuda:0")
+    b = torch.randn((count, n), generator=gen, dtype=torch.float64, device=dev) / math.sqrt(n)
+    c = torch.randn((count, n), generator=gen, dtype=torch.float64, device=dev) / math.sqrt(n)
+    return b, c
+
+
+def applier_flops(bdu, m: int, n: int) -> float:
+    """Algorithmic flops of one rank-1 accumulation: 6 per rotation per row."""
+    st = bdu.plan_stats(m, n)
+    return 6.0 * (m * st["left"] + n * st["right"])
+
+
+def cpu_baseline(n: int, seed: int) -> dict:
+    """The oracle, as it stands, on one rank-1 update of one n x n stream."""
+    from oracle import oracle as O
+    from paper_2509_02840_amd import workloads as W
+
+    f = W.factorization(n, n, seed)
+    (B, C), = W.gaussian_updates(n, n, 1, seed + 1)
+    st = O.State(f.Q, f.d, f.e, f.P)
+    t0 = time.perf_counter()
+    O.bgu_update(st, B, C)
+    dt = time.perf_counter() - t0
+    return {"value": 1.0 / dt, "unit": "rank-1 updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"one rank-1 update of one {n}x{n} stream, single thread ({dt:.1f} s)"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=2048)
+    ap.add_argument("--streams", type=int, default=64)
+    ap.add_argument("--plain-steps", type=int, default=20)
+    ap.add_argument("--seed", type=int, default=5000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(streams shard across GPUs with no communication; see the design notes)",
+              file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2509_02840_amd import bdu
+
+    torch.cuda.set_device(0)
+    n = args.n
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(args.seed)
+
+    # ---- plain: one stream, one update per call --------------------------
+    Q, d, e, P = make_stream(torch, gen, n)
+    h = bdu.Handle(Q, d, e, P)
+    del Q, P
+    pb, pc = make_updates(torch, gen, n, args.warmup + args.plain_steps)
+    torch.cuda.synchronize()
+    for k in range(args.warmup):
+        h.update(pb[k], pc[k])
+    h.sync()
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.warmup, args.warmup + args.plain_steps):
+        ta = time.perf_counter()
+        h.update(pb[k], pc[k])
+        h.sync()
+        lat.append(time.perf_counter() - ta)
+    torch.cuda.synchronize()
+    plain_time = time.perf_counter() - t0
+    plain_ups = args.plain_steps / plain_time
+    h.close()
+    del pb, pc
+
+    # ---- batched: S streams, one update of every stream per step -----------
+    S = args.streams
+    hs = []
+    for _ in range(S):
+        Q, d, e, P = make_stream(torch, gen, n)
+        hs.append(bdu.Handle(Q, d, e, P))
+        del Q, P
+    torch.cuda.empty_cache()
+    steps = args.warmup + args.steps
+    ub = [make_updates(torch, gen, n, steps) for _ in range(S)]
+    torch.cuda.synchronize()
+    for k in range(args.warmup):
+        bdu.update_batched(hs, [ub[s][0][k] for s in range(S)], [ub[s][1][k] for s in range(S)])
+    for x in hs:
+        x.sync()
+    bdu.timing_enable(True)
+    step_lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.warmup, steps):
+        ta = time.perf_counter()
+        bdu.update_batched(hs, [ub[s][0][k] for s in range(S)], [ub[s][1][k] for s in range(S)])
+        step_lat.append(time.perf_counter() - ta)
+    for x in hs:
+        x.sync()
+    torch.cuda.synchronize()
+    batched_time = time.perf_counter() - t0
+    stages = bdu.timing_read()
+    bdu.timing_enable(False)
+    for x in hs:
+        x.close()
+
+    value = S * args.steps / batched_time
+    apply_ms, apply_launches = stages["apply"]
+    avg_apply_s = apply_ms / 1e3 / max(apply_launches, 1)
+    flops_per_launch = S * applier_flops(bdu, n, n)
+    achieved = flops_per_launch / avg_apply_s / 1e12
+    k0, nw = bdu.get_tiling()
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "rank-1 updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * batched_time / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"batched BGU rank-1 updates, {S} square streams m=n={n}, "
+                               f"one update per stream per step; plain = 1 stream",
+                   "m": n, "n": n, "streams": S, "rank": 1, "tiling": [k0, nw]},
+        "plain_updates_per_s": plain_ups,
+        "batched_over_plain": value / plain_ups,
+        "p50_ms": 1e3 * float(np.percentile(step_lat, 50)),
+        "p99_ms": 1e3 * float(np.percentile(step_lat, 99)),
+        "plain_p50_ms": 1e3 * float(np.percentile(lat, 50)),
+        "plain_p99_ms": 1e3 * float(np.percentile(lat, 99)),
+        "stage_ms_per_step": {k: v[0] / args.steps for k, v in stages.items()},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "apply_kernel", "flops_per_launch": flops_per_launch,
+                     "avg_launch_ms": avg_apply_s * 1e3},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(n, args.seed)
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -108,6 +108,14 @@ int64_t bdu_footprint_bytes(int64_t m, int64_t n);
 int bdu_set_tiling(int k0, int nw);
 int bdu_get_tiling(int *k0, int *nw);
 
+/* Stage timing.  bdu_timing_enable(1) clears the log and brackets every
+ * later kernel launch with HIP events on the stream the kernel runs on;
+ * bdu_timing_enable(0) stops it.  bdu_timing_read waits for the logged events
+ * and returns, per stage (0 projection, 1 spike, 2 generation, 3 application),
+ * the summed milliseconds ms[4] and the number of launches launches[4]. */
+int bdu_timing_enable(int on);
+int bdu_timing_read(double *ms, int64_t *launches);
+
 /* The device rotation generator of eq. (giv1) on count pairs (a[i], b[i]):
  * mode 1 annihilates a, mode 2 annihilates b; outputs c, s and the
  * survivor r.  Host or device pointers.  For checking the device arithmetic

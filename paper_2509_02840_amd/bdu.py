@@ -59,11 +59,14 @@ def lib():
         L.bdu_get_tiling.argtypes = [ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.bdu_plan_stats.argtypes = [i64, i64, ctypes.POINTER(i64)]
         L.bdu_givens_device.argtypes = [vp, vp, i32, vp, vp, vp, i64]
+        L.bdu_timing_enable.argtypes = [i32]
+        L.bdu_timing_read.argtypes = [vp, vp]
         L.bdu_plan_rotations.argtypes = [i64, i64, vp, vp, vp, vp, i64]
         L.bdu_plan_rotations.restype = i64
         for f in ("bdu_create", "bdu_update", "bdu_update_batched", "bdu_update_projected", "bdu_project",
                   "bdu_read", "bdu_set_stream", "bdu_sync", "bdu_destroy", "bdu_set_tiling",
-                  "bdu_get_tiling", "bdu_plan_stats", "bdu_givens_device"):
+                  "bdu_get_tiling", "bdu_plan_stats", "bdu_givens_device", "bdu_timing_enable",
+                  "bdu_timing_read"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -124,6 +127,21 @@ def givens_device(a: np.ndarray, b: np.ndarray, mode: int):
     _check(lib().bdu_givens_device(a.ctypes.data, b.ctypes.data, mode, c.ctypes.data, s.ctypes.data,
                                    r.ctypes.data, len(a)), "bdu_givens_device")
     return c, s, r
+
+
+STAGES = ("project", "spike", "generate", "apply")
+
+
+def timing_enable(on: bool = True) -> None:
+    _check(lib().bdu_timing_enable(1 if on else 0), "bdu_timing_enable")
+
+
+def timing_read() -> dict:
+    """{stage: (milliseconds summed over launches, launches)} since timing_enable(True)."""
+    ms = np.zeros(4)
+    cnt = np.zeros(4, np.int64)
+    _check(lib().bdu_timing_read(ms.ctypes.data, cnt.ctypes.data), "bdu_timing_read")
+    return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(STAGES)}
 
 
 def plan_stats(m: int, n: int) -> dict:

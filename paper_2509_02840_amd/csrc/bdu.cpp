@@ -75,6 +75,56 @@ bool is_device_ptr(const void *p)
     return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
 }
 
+// ---- stage timing --------------------------------------------------------
+// When enabled, each kernel launch is bracketed by a pair of HIP events on
+// the stream it runs on; reading sums the elapsed times per stage.
+enum Stage { ST_PROJECT = 0, ST_SPIKE = 1, ST_GEN = 2, ST_APPLY = 3, ST_COUNT = 4 };
+std::mutex g_tmu;
+bool g_timing = false;
+struct EvPair {
+    int stage;
+    hipEvent_t a, b;
+};
+std::vector<EvPair> g_events;
+std::vector<hipEvent_t> g_pool;
+
+hipEvent_t pool_get()
+{
+    if (!g_pool.empty()) {
+        hipEvent_t e = g_pool.back();
+        g_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Launch `fn` as stage `stage` on stream st, timed when timing is on.
+template <typename Fn>
+hipError_t timed(int stage, hipStream_t st, Fn fn)
+{
+    bool on;
+    {
+        std::lock_guard<std::mutex> lk(g_tmu);
+        on = g_timing;
+    }
+    if (!on) return fn();
+    hipEvent_t a, b;
+    {
+        std::lock_guard<std::mutex> lk(g_tmu);
+        a = pool_get();
+        b = pool_get();
+    }
+    if (!a || !b) return fn();
+    hipError_t e = hipEventRecord(a, st);
+    if (e == hipSuccess) e = fn();
+    if (e == hipSuccess) e = hipEventRecord(b, st);
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_events.push_back(EvPair{stage, a, b});
+    return e;
+}
+
 }  // namespace
 
 struct bdu_ctx {
@@ -186,9 +236,10 @@ hipError_t run_rotation_stages(HandleDev *const *hs, int count, bool any_spike, 
                                bool in_lds, int max_panels, int k0, int nw, hipStream_t st)
 {
     hipError_t e = hipSuccess;
-    if (any_spike) e = launch_spike(hs, count, st);
-    if (e == hipSuccess) e = launch_gen(hs, count, lds_bytes, in_lds, st);
-    if (e == hipSuccess) e = launch_apply(hs, count, max_panels, k0, nw, st);
+    if (any_spike) e = timed(ST_SPIKE, st, [&] { return launch_spike(hs, count, st); });
+    if (e == hipSuccess) e = timed(ST_GEN, st, [&] { return launch_gen(hs, count, lds_bytes, in_lds, st); });
+    if (e == hipSuccess)
+        e = timed(ST_APPLY, st, [&] { return launch_apply(hs, count, max_panels, k0, nw, st); });
     return e;
 }
 
@@ -197,7 +248,8 @@ int tiles_of(const bdu_ctx *h) { return (int)((h->m + 63) / 64 + (h->n + 63) / 6
 int pass_single(bdu_ctx *h, int pass, bool project)
 {
     hipError_t e = hipSuccess;
-    if (project) e = launch_project(h->d_self, 1, tiles_of(h), pass, h->stream);
+    if (project)
+        e = timed(ST_PROJECT, h->stream, [&] { return launch_project(h->d_self, 1, tiles_of(h), pass, h->stream); });
     if (e == hipSuccess)
         e = run_rotation_stages(h->d_self, 1, h->m > h->n, gen_lds_bytes(h->n, h->plan->N), h->lds_gen,
                                 tiles_of(h), h->plan->K0, h->plan->NW, h->stream);
@@ -507,7 +559,7 @@ int bdu_update_batched(const bdu_handle *hs, const double *const *Bs, const doub
         for (auto &g : passes[p]) {
             HandleDev **arr = d_arr + off;
             int cnt = (int)g.ptrs.size();
-            e = launch_project(arr, cnt, g.tiles, p, st);
+            e = timed(ST_PROJECT, st, [&] { return launch_project(arr, cnt, g.tiles, p, st); });
             if (e == hipSuccess)
                 e = run_rotation_stages(arr, cnt, g.spike, g.lds, g.in_lds, g.tiles, g.k0, g.nw, st);
             off += cnt;
@@ -519,6 +571,37 @@ int bdu_update_batched(const bdu_handle *hs, const double *const *Bs, const doub
     if (e != hipSuccess) {
         for (int i = 0; i < count; ++i) hs[i]->poisoned = true;
         return BDU_EDEVICE;
+    }
+    return BDU_OK;
+}
+
+int bdu_timing_enable(int on)
+{
+    std::lock_guard<std::mutex> lk(g_tmu);
+    for (auto &p : g_events) {
+        (void)hipEventSynchronize(p.b);
+        g_pool.push_back(p.a);
+        g_pool.push_back(p.b);
+    }
+    g_events.clear();
+    g_timing = on != 0;
+    return BDU_OK;
+}
+
+int bdu_timing_read(double *ms, int64_t *launches)
+{
+    if (!ms || !launches) return BDU_EINVAL;
+    std::lock_guard<std::mutex> lk(g_tmu);
+    for (int i = 0; i < ST_COUNT; ++i) {
+        ms[i] = 0.0;
+        launches[i] = 0;
+    }
+    for (auto &p : g_events) {
+        if (hipEventSynchronize(p.b) != hipSuccess) return BDU_EDEVICE;
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, p.a, p.b) != hipSuccess) return BDU_EDEVICE;
+        ms[p.stage] += t;
+        launches[p.stage] += 1;
     }
     return BDU_OK;
 }
