@@ -84,6 +84,7 @@ def main() -> int:
     ap.add_argument("--plain-steps", type=int, default=20)
     ap.add_argument("--seed", type=int, default=5000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tiling", type=str, default=None, help="applier tiling K0,NW,RPL (default: library default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -95,6 +96,8 @@ def main() -> int:
     from paper_2509_02840_amd import bdu
 
     torch.cuda.set_device(0)
+    if args.tiling:
+        bdu.set_tiling(*[int(x) for x in args.tiling.split(",")])
     n = args.n
     gen = torch.Generator(device="cuda:0")
     gen.manual_seed(args.seed)
@@ -159,7 +162,7 @@ def main() -> int:
     avg_apply_s = apply_ms / 1e3 / max(apply_launches, 1)
     flops_per_launch = S * applier_flops(bdu, n, n)
     achieved = flops_per_launch / avg_apply_s / 1e12
-    k0, nw = bdu.get_tiling()
+    k0, nw, rpl = bdu.get_tiling()
 
     out = {
         "metric": METRIC,
@@ -176,7 +179,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"batched BGU rank-1 updates, {S} square streams m=n={n}, "
                                f"one update per stream per step; plain = 1 stream",
-                   "m": n, "n": n, "streams": S, "rank": 1, "tiling": [k0, nw]},
+                   "m": n, "n": n, "streams": S, "rank": 1, "tiling": [k0, nw, rpl]},
         "plain_updates_per_s": plain_ups,
         "batched_over_plain": value / plain_ups,
         "p50_ms": 1e3 * float(np.percentile(step_lat, 50)),

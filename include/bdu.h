@@ -102,11 +102,12 @@ const char *bdu_strerror(int status);
  * rotation streams), for admission control. */
 int64_t bdu_footprint_bytes(int64_t m, int64_t n);
 
-/* Applier tiling (chains per wavefront k0 in {6, 12}, wavefronts per
- * workgroup nw in {1, 2, 4}); applies to handles created afterwards.
- * Results do not depend on it. */
-int bdu_set_tiling(int k0, int nw);
-int bdu_get_tiling(int *k0, int *nw);
+/* Applier tiling: chains per wavefront k0 in {6, 12}, wavefronts per
+ * workgroup nw in {1, 2, 4, 8}, matrix rows per lane rpl in {1, 2} (except
+ * k0 = 6, nw = 8, rpl = 2).  Applies to handles created afterwards.  Results
+ * do not depend on it. */
+int bdu_set_tiling(int k0, int nw, int rpl);
+int bdu_get_tiling(int *k0, int *nw, int *rpl);
 
 /* Stage timing.  bdu_timing_enable(1) clears the log and brackets every
  * later kernel launch with HIP events on the stream the kernel runs on;

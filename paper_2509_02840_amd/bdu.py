@@ -55,8 +55,8 @@ def lib():
         L.bdu_strerror.restype = ctypes.c_char_p
         L.bdu_footprint_bytes.argtypes = [i64, i64]
         L.bdu_footprint_bytes.restype = i64
-        L.bdu_set_tiling.argtypes = [i32, i32]
-        L.bdu_get_tiling.argtypes = [ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.bdu_set_tiling.argtypes = [i32, i32, i32]
+        L.bdu_get_tiling.argtypes = [ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.bdu_plan_stats.argtypes = [i64, i64, ctypes.POINTER(i64)]
         L.bdu_givens_device.argtypes = [vp, vp, i32, vp, vp, vp, i64]
         L.bdu_timing_enable.argtypes = [i32]
@@ -106,14 +106,14 @@ def _ptr(a, matrix: bool = False):
     return a.data_ptr()
 
 
-def set_tiling(k0: int, nw: int) -> None:
-    _check(lib().bdu_set_tiling(k0, nw), "bdu_set_tiling")
+def set_tiling(k0: int, nw: int, rpl: int = 2) -> None:
+    _check(lib().bdu_set_tiling(k0, nw, rpl), "bdu_set_tiling")
 
 
 def get_tiling():
-    k0, nw = ctypes.c_int(), ctypes.c_int()
-    lib().bdu_get_tiling(ctypes.byref(k0), ctypes.byref(nw))
-    return k0.value, nw.value
+    k0, nw, rpl = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    lib().bdu_get_tiling(ctypes.byref(k0), ctypes.byref(nw), ctypes.byref(rpl))
+    return k0.value, nw.value, rpl.value
 
 
 def footprint_bytes(m: int, n: int) -> int:

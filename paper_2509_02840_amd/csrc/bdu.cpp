@@ -25,7 +25,7 @@ using namespace bdu;
 namespace {
 
 std::mutex g_mu;
-int g_k0 = 12, g_nw = 1;
+int g_k0 = 12, g_nw = 4, g_rpl = 2;
 
 struct PlanEntry {
     std::unique_ptr<Plan> plan;
@@ -136,6 +136,7 @@ struct bdu_ctx {
     hipStream_t stream = nullptr;
     bool poisoned = false;
     int rcap = 0;
+    int rpl = 1;  // rows per lane in the applier
     bool lds_gen = true;
     std::vector<void *> allocs;
 };
@@ -233,17 +234,22 @@ int ensure_rcap(bdu_ctx *h, int r)
 // Rotation stages of one pass (spike, generation, application) for `count`
 // handles listed in the device array hs (all with the same tiling).
 hipError_t run_rotation_stages(HandleDev *const *hs, int count, bool any_spike, int64_t lds_bytes,
-                               bool in_lds, int max_panels, int k0, int nw, hipStream_t st)
+                               bool in_lds, int max_panels, int k0, int nw, int rpl, hipStream_t st)
 {
     hipError_t e = hipSuccess;
     if (any_spike) e = timed(ST_SPIKE, st, [&] { return launch_spike(hs, count, st); });
     if (e == hipSuccess) e = timed(ST_GEN, st, [&] { return launch_gen(hs, count, lds_bytes, in_lds, st); });
     if (e == hipSuccess)
-        e = timed(ST_APPLY, st, [&] { return launch_apply(hs, count, max_panels, k0, nw, st); });
+        e = timed(ST_APPLY, st, [&] { return launch_apply(hs, count, max_panels, k0, nw, rpl, st); });
     return e;
 }
 
 int tiles_of(const bdu_ctx *h) { return (int)((h->m + 63) / 64 + (h->n + 63) / 64); }
+int panels_of(const bdu_ctx *h)
+{
+    const int64_t ph = 64 * h->rpl;
+    return (int)((h->m + ph - 1) / ph + (h->n + ph - 1) / ph);
+}
 
 int pass_single(bdu_ctx *h, int pass, bool project)
 {
@@ -252,7 +258,7 @@ int pass_single(bdu_ctx *h, int pass, bool project)
         e = timed(ST_PROJECT, h->stream, [&] { return launch_project(h->d_self, 1, tiles_of(h), pass, h->stream); });
     if (e == hipSuccess)
         e = run_rotation_stages(h->d_self, 1, h->m > h->n, gen_lds_bytes(h->n, h->plan->N), h->lds_gen,
-                                tiles_of(h), h->plan->K0, h->plan->NW, h->stream);
+                                panels_of(h), h->plan->K0, h->plan->NW, h->rpl, h->stream);
     if (e != hipSuccess) {
         h->poisoned = true;
         return BDU_EDEVICE;
@@ -287,20 +293,22 @@ const char *bdu_strerror(int status)
     }
 }
 
-int bdu_set_tiling(int k0, int nw)
+int bdu_set_tiling(int k0, int nw, int rpl)
 {
-    if (!tiling_supported(k0, nw)) return BDU_EINVAL;
+    if (!tiling_supported(k0, nw, rpl)) return BDU_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
     g_k0 = k0;
     g_nw = nw;
+    g_rpl = rpl;
     return BDU_OK;
 }
 
-int bdu_get_tiling(int *k0, int *nw)
+int bdu_get_tiling(int *k0, int *nw, int *rpl)
 {
     std::lock_guard<std::mutex> lk(g_mu);
     if (k0) *k0 = g_k0;
     if (nw) *nw = g_nw;
+    if (rpl) *rpl = g_rpl;
     return BDU_OK;
 }
 
@@ -308,11 +316,11 @@ int64_t bdu_footprint_bytes(int64_t m, int64_t n)
 {
     if (m < n || n < 2) return BDU_EINVAL;
     int k0, nw;
-    bdu_get_tiling(&k0, &nw);
+    bdu_get_tiling(&k0, &nw, nullptr);
     hipError_t e;
     Plan *p = get_plan(m, n, k0, nw, false, &e);
     int64_t N = p->N;
-    const int64_t ldq = (m + 63) / 64 * 64, ldp = (n + 63) / 64 * 64;
+    const int64_t ldq = (m + 127) / 128 * 128, ldp = (n + 127) / 128 * 128;
     int64_t bytes = 8 * (ldq * m + ldp * n + 2 * n + 2 * (m + n) + 2 * (m + n));
     bytes += 16 * (p->slots[0] + p->slots[1] + std::max<int64_t>(p->nspike, 1));
     if (gen_lds_bytes(n, N) > kMaxGenLds) bytes += gen_lds_bytes(n, N);
@@ -324,8 +332,8 @@ int bdu_create(int64_t m, int64_t n, const double *Q, const double *d, const dou
 {
     if (!out || !Q || !d || !e || !P || m < n || n < 2 || m > (int64_t)1 << 30) return BDU_EINVAL;
     *out = nullptr;
-    int k0, nw;
-    bdu_get_tiling(&k0, &nw);
+    int k0, nw, rpl;
+    bdu_get_tiling(&k0, &nw, &rpl);
     hipError_t err;
     Plan *plan = get_plan(m, n, k0, nw, true, &err);
     if (!plan) return BDU_EDEVICE;
@@ -333,11 +341,12 @@ int bdu_create(int64_t m, int64_t n, const double *Q, const double *d, const dou
     h->m = m;
     h->n = n;
     h->plan = plan;
+    h->rpl = rpl;
     h->lds_gen = gen_lds_bytes(n, plan->N) <= kMaxGenLds;
     HandleDev &hd = h->hd;
     hipError_t a = hipSuccess;
     auto A = [&](hipError_t x) { if (a == hipSuccess) a = x; };
-    const int64_t ldq = (m + 63) / 64 * 64, ldp = (n + 63) / 64 * 64;
+    const int64_t ldq = (m + 127) / 128 * 128, ldp = (n + 127) / 128 * 128;
     A(dalloc(h.get(), &hd.Q, ldq * m));
     A(dalloc(h.get(), &hd.P, ldp * n));
     A(dalloc(h.get(), &hd.d, n));
@@ -482,6 +491,7 @@ int64_t bdu_last_rotations(bdu_handle h, int32_t *side, int64_t *idx, double *c,
         for (int q = 0; q < g.len; ++q) {
             Rot r = decode(g.type, g.param, q);
             int64_t sl = slot_of(P, g, r);
+            if (sl != g.slot[r.side] + (int64_t)(q >> 1) * P.K) return BDU_EDEVICE;  // layout invariant
             emit(r.side, r.i, r.side == 0 ? L[sl] : R[sl]);
         }
     }
@@ -520,11 +530,11 @@ int bdu_update_batched(const bdu_handle *hs, const double *const *Bs, const doub
     }
     // Per pass: the handles still active, grouped by tiling.
     struct Group {
-        int k0, nw;
+        int k0, nw, rpl;
         std::vector<HandleDev *> ptrs;
         bool spike = false, in_lds = true;
         int64_t lds = 0;
-        int tiles = 0;
+        int tiles = 0, panels = 0;
     };
     std::vector<std::vector<Group>> passes(maxr);
     size_t total = 0;
@@ -534,15 +544,17 @@ int bdu_update_batched(const bdu_handle *hs, const double *const *Bs, const doub
             bdu_ctx *h = hs[i];
             Group *g = nullptr;
             for (auto &x : passes[p])
-                if (x.k0 == h->plan->K0 && x.nw == h->plan->NW && x.in_lds == h->lds_gen) g = &x;
+                if (x.k0 == h->plan->K0 && x.nw == h->plan->NW && x.rpl == h->rpl && x.in_lds == h->lds_gen)
+                    g = &x;
             if (!g) {
-                passes[p].push_back(Group{h->plan->K0, h->plan->NW, {}, false, h->lds_gen, 0, 0});
+                passes[p].push_back(Group{h->plan->K0, h->plan->NW, h->rpl, {}, false, h->lds_gen, 0, 0, 0});
                 g = &passes[p].back();
             }
             g->ptrs.push_back(h->d_hd);
             g->spike |= h->m > h->n;
             g->lds = std::max<int64_t>(g->lds, gen_lds_bytes(h->n, h->plan->N));
             g->tiles = std::max(g->tiles, tiles_of(h));
+            g->panels = std::max(g->panels, panels_of(h));
         }
         for (auto &g : passes[p]) total += g.ptrs.size();
     }
@@ -561,7 +573,7 @@ int bdu_update_batched(const bdu_handle *hs, const double *const *Bs, const doub
             int cnt = (int)g.ptrs.size();
             e = timed(ST_PROJECT, st, [&] { return launch_project(arr, cnt, g.tiles, p, st); });
             if (e == hipSuccess)
-                e = run_rotation_stages(arr, cnt, g.spike, g.lds, g.in_lds, g.tiles, g.k0, g.nw, st);
+                e = run_rotation_stages(arr, cnt, g.spike, g.lds, g.in_lds, g.panels, g.k0, g.nw, g.rpl, st);
             off += cnt;
             if (e != hipSuccess) break;
         }
@@ -627,7 +639,7 @@ int bdu_plan_stats(int64_t m, int64_t n, int64_t *out)
 {
     if (!out || m < n || n < 2) return BDU_EINVAL;
     int k0, nw;
-    bdu_get_tiling(&k0, &nw);
+    bdu_get_tiling(&k0, &nw, nullptr);
     hipError_t e;
     Plan *p = get_plan(m, n, k0, nw, false, &e);
     out[0] = p->nleft + p->nspike;
@@ -646,7 +658,7 @@ int64_t bdu_plan_rotations(int64_t m, int64_t n, int32_t *side, int64_t *idx, in
 {
     if (m < n || n < 2) return BDU_EINVAL;
     int k0, nw;
-    bdu_get_tiling(&k0, &nw);
+    bdu_get_tiling(&k0, &nw, nullptr);
     hipError_t e;
     Plan *p = get_plan(m, n, k0, nw, false, &e);
     int64_t k = 0;

@@ -12,9 +12,10 @@ namespace bdu {
 hipError_t launch_project(HandleDev *const *hs, int count, int max_tiles, int pass, hipStream_t st);
 hipError_t launch_spike(HandleDev *const *hs, int count, hipStream_t st);
 hipError_t launch_gen(HandleDev *const *hs, int count, int64_t lds_bytes, bool in_lds, hipStream_t st);
-hipError_t launch_apply(HandleDev *const *hs, int count, int max_panels, int k0, int nw, hipStream_t st);
+hipError_t launch_apply(HandleDev *const *hs, int count, int max_panels, int k0, int nw, int rpl,
+                        hipStream_t st);
 hipError_t launch_fill_identity(double2 *p, int64_t count, hipStream_t st);
-bool tiling_supported(int k0, int nw);
+bool tiling_supported(int k0, int nw, int rpl);
 hipError_t launch_givens(const double *a, const double *b, int mode, double *c, double *s, double *r,
                          int64_t count, hipStream_t st);
 

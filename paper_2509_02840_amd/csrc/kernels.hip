@@ -215,7 +215,7 @@ __global__ __launch_bounds__(kGenThreads) void gen_kernel(HandleDev *const *hs)
     for (int i = 1 + tid; i <= N; i += nt) U[i + 3] = h->u[i - 1];
     __syncthreads();
 
-    const int K = h->K, K0 = h->K0, SS = h->S, nb1 = h->nb1;
+    const int K = h->K;
     int ci = tid;
     GenChain g, gn;
     g.len = 0;
@@ -285,15 +285,8 @@ __global__ __launch_bounds__(kGenThreads) void gen_kernel(HandleDev *const *hs)
                         S[gb] = 0.0;
                     }
                     // slot of this rotation in the applier layout
-                    const int ph = chain_phase(g.type);
-                    const int tg = chain_in_phase(g.type, g.param);
-                    const int b = tg / K, tin = tg - b * K;
-                    const int w = tin / K0, tl = tin - w * K0;
-                    const BlockDesc *blk = (r.side == 0 ? h->blkL : h->blkR) + (ph == 1 ? 0 : nb1) + b;
-                    const int lam0 = lam0_of_pair(ph, blk->base, r.i);
-                    const int64_t F = lam0 / 3 + tl + w * SS;
                     double2 *cs = r.side == 0 ? h->csL : h->csR;
-                    cs[blk->off + F * K + tin] = make_double2(c, sn);
+                    cs[g.slot[r.side] + (int64_t)(s >> 1) * K] = make_double2(c, sn);
                 }
                 if (s == g.len - 1) {
                     ci += nt;
@@ -324,17 +317,27 @@ __host__ __device__ constexpr int rho_of(int mode, int K, int t)
 
 __host__ __device__ constexpr int pmod(int a, int b) { return ((a % b) + b) % b; }
 
-// Sweep one block of K = K0*NW chains over this workgroup's 64 rows.
-// Wavefront w holds local columns [3(f-K0+1), 3f+9] of its rows in registers
-// (f = its local front), applies chains w*K0 .. w*K0+K0-1 at each front, and
-// hands finished columns to wavefront w+1 through an LDS ring (the last
-// wavefront writes them back to memory).  Every front of the loop has a slot
-// per chain (identity where the chain has no rotation), so the body has no
-// data-dependent branches around the rotations.  Columns outside the block
-// are loaded from a clamped address and never stored: an identity rotation
-// leaves a finite partner unchanged, and real rotations never touch them.
-template <int K0, int NW, int MODE>
-__device__ __forceinline__ void sweep(GLOBAL double *__restrict__ X, int ld, int ncols, int row,
+// Columns in the LDS ring between two wavefronts: at most 14 columns are live
+// (written but not yet read), and 3 r with r | (K0 + 3) keeps slots static.
+__host__ __device__ constexpr int ring_cols(int K0)
+{
+    int U = K0 + 3, r = 5;
+    while (U % r) ++r;
+    return 3 * r;
+}
+
+// Sweep one block of K = K0*NW chains over this workgroup's 64*R rows (lane l
+// owns rows l, l+64, ..., l+64(R-1) of the panel).  Wavefront w holds local
+// columns [3(f-K0+1), 3f+9] of its rows in registers (f = its local front),
+// applies chains w*K0 .. w*K0+K0-1 at each front, and hands finished columns
+// to wavefront w+1 through an LDS ring (the last wavefront writes them back to
+// memory).  Every front of the loop has a slot per chain (identity where the
+// chain has no rotation), so the body has no data-dependent branches around
+// the rotations.  Columns outside the block are loaded from a clamped address
+// and never stored: an identity rotation leaves a finite partner unchanged,
+// and real rotations never touch them.  Each coefficient pair serves R rows.
+template <int K0, int NW, int R, int MODE>
+__device__ __forceinline__ void sweep(GLOBAL double *__restrict__ X, int ld, int ncols, int row0,
                                       const CONSTANT double *__restrict__ cs, const BlockDesc bd,
                                       double *ring, int w, int lane)
 {
@@ -349,22 +352,31 @@ __device__ __forceinline__ void sweep(GLOBAL double *__restrict__ X, int ld, int
     const int lam_hi = lmax + 1;
     const int lam_lo = DESC ? (base - ncols > 0 ? base - ncols : 0) : 0;
     const int col0 = base - 1;  // 0-based matrix column of local column 0
-    double buf[WSZ];
+    double buf[R][WSZ];
 #pragma unroll
-    for (int i = 0; i < WSZ; ++i) buf[i] = 0.0;
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int i = 0; i < WSZ; ++i) buf[r][i] = 0.0;
 
-    auto gload = [&](int lam) -> double {
+    // column base address is uniform; the lane adds its row
+    auto colptr = [&](int lam) -> const GLOBAL double * {
         int c = col0 + DIR * lam;
         c = c < 0 ? 0 : (c >= ncols ? ncols - 1 : c);
-        return X[(int64_t)c * ld + row];
+        return X + (int64_t)c * ld;
     };
-    // ring slot of local column lam is lam mod WSZ, the same as its register
-    double *rin = ring + (w > 0 ? w - 1 : 0) * WSZ * 64 + lane;
-    double *rout = ring + w * WSZ * 64 + lane;
+    // ring slot of local column lam is lam mod RC (RC = ring_cols(K0) divides
+    // WSZ, so the slot is a compile-time constant in the unrolled loop)
+    constexpr int RC = ring_cols(K0);
+    double *rin = ring + (w > 0 ? w - 1 : 0) * RC * 64 * R + lane;
+    double *rout = ring + w * RC * 64 * R + lane;
 
     if (w == 0) {
 #pragma unroll
-        for (int k = 0; k <= 6; ++k) buf[k] = gload(k);
+        for (int k = 0; k <= 6; ++k) {
+            const GLOBAL double *cp = colptr(k);
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[r][k] = cp[row0 + 64 * r];
+        }
     }
     for (int F0 = 0; F0 < nfront; F0 += U) {
 #pragma unroll
@@ -375,11 +387,21 @@ __device__ __forceinline__ void sweep(GLOBAL double *__restrict__ X, int ld, int
             // from the previous wavefront's ring
             if (w == 0) {
 #pragma unroll
-                for (int k = 7; k <= 9; ++k) buf[pmod(3 * phi + k, WSZ)] = gload(3 * f + k);
-            } else {
-                if (phi == 0 && f == 0) buf[0] = rin[0];
+                for (int k = 7; k <= 9; ++k) {
+                    const GLOBAL double *cp = colptr(3 * f + k);
 #pragma unroll
-                for (int k = 1; k <= 3; ++k) buf[pmod(3 * phi + k, WSZ)] = rin[pmod(3 * phi + k, WSZ) * 64];
+                    for (int r = 0; r < R; ++r) buf[r][pmod(3 * phi + k, WSZ)] = cp[row0 + 64 * r];
+                }
+            } else {
+                if (phi == 0 && f == 0) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) buf[r][0] = rin[64 * r];
+                }
+#pragma unroll
+                for (int k = 1; k <= 3; ++k)
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        buf[r][pmod(3 * phi + k, WSZ)] = rin[(pmod(3 * phi + k, RC) * R + r) * 64];
             }
             // this wavefront's K0 rotations at front F.  The empty asm makes
             // the coefficient address opaque, so their scalar loads are issued
@@ -400,7 +422,9 @@ __device__ __forceinline__ void sweep(GLOBAL double *__restrict__ X, int ld, int
                     const int l0 = 3 * (phi - t) + rho_of(MODE, K, t);
                     const int sx = pmod(l0 + (DESC ? 1 : 0), WSZ);
                     const int sy = pmod(l0 + (DESC ? 0 : 1), WSZ);
-                    rot(pg[2 * q], pg[2 * q + 1], buf[sx], buf[sy]);
+                    const double c = pg[2 * q], sn = pg[2 * q + 1];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) rot(c, sn, buf[r][sx], buf[r][sy]);
                 }
                 pg = pn;
             }
@@ -410,22 +434,29 @@ __device__ __forceinline__ void sweep(GLOBAL double *__restrict__ X, int ld, int
                 const int lam = 3 * (f - K0 + 1) + k;
                 const int sl = pmod(3 * (phi - K0 + 1) + k, WSZ);
                 if (w == NW - 1) {
-                    if (lam >= lam_lo && lam <= lam_hi) X[(int64_t)(col0 + DIR * lam) * ld + row] = buf[sl];
+                    if (lam >= lam_lo && lam <= lam_hi) {
+                        GLOBAL double *cp = X + (int64_t)(col0 + DIR * lam) * ld;
+#pragma unroll
+                        for (int r = 0; r < R; ++r) cp[row0 + 64 * r] = buf[r][sl];
+                    }
                 } else {
-                    rout[sl * 64] = buf[sl];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) rout[(pmod(3 * (phi - K0 + 1) + k, RC) * R + r) * 64] = buf[r][sl];
                 }
             }
             if (NW > 1) __syncthreads();
             // keep fronts in order: the window is materialised here, so the
             // scheduler cannot interleave two fronts (and their coefficients)
 #pragma unroll
-            for (int i = 0; i < WSZ; ++i) asm volatile("" : "+v"(buf[i]));
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int i = 0; i < WSZ; ++i) asm volatile("" : "+v"(buf[r][i]));
         }
     }
 }
 
-// Spike rotations on Q columns (j-1, j), j = m..n+2, for this lane's row:
-// a running carry keeps column j between consecutive rotations.
+// Spike rotations on Q columns (j-1, j), j = m..n+2, for one row: a running
+// carry keeps column j between consecutive rotations.
 __device__ void spike_apply(GLOBAL double *Q, int ld, int m, int n, int row, const CONSTANT double *cs)
 {
     double carry = Q[(int64_t)(m - 1) * ld + row];
@@ -439,50 +470,54 @@ __device__ void spike_apply(GLOBAL double *Q, int ld, int m, int n, int row, con
     Q[(int64_t)n * ld + row] = carry;
 }
 
-// grid (panels, handles): panels [0, ceil(m/64)) update Q, the rest P.  Q
-// and P have leading dimensions padded to a multiple of 64 rows.
-template <int K0, int NW>
+// grid (panels, handles): panels [0, ceil(m/(64R))) update Q, the rest P.  Q
+// and P have leading dimensions padded to a multiple of 128 rows.
+template <int K0, int NW, int R>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(1, 2))) void apply_kernel(
     HandleDev *const *hs)
 {
     const CONSTANT HandleDev *h = kptr(hs[blockIdx.y]);
     const int m = h->m, n = h->n;
-    const int qp = (m + 63) / 64, pp = (n + 63) / 64;
+    constexpr int PH = 64 * R;
+    const int qp = (m + PH - 1) / PH, pp = (n + PH - 1) / PH;
     const int pid = blockIdx.x;
     if (pid >= qp + pp) return;
-    constexpr int WSZ = 3 * (K0 + 3);
-    __shared__ double ring[(NW > 1 ? NW - 1 : 1) * WSZ * 64];
+    constexpr int RING = (NW > 1 ? NW - 1 : 1) * ring_cols(K0) * 64 * R;
+    __shared__ double ring[RING];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     // the ring starts finite (stale slots may meet identity rotations)
-    for (int i = threadIdx.x; i < (NW > 1 ? NW - 1 : 1) * WSZ * 64; i += 64 * NW) ring[i] = 0.0;
+    for (int i = threadIdx.x; i < RING; i += 64 * NW) ring[i] = 0.0;
     const int nb1 = h->nb1, nb2 = h->nb2;
     if (pid < qp) {
-        const int row = pid * 64 + lane;
+        const int row0 = pid * PH + lane;
         GLOBAL double *Q = gptr(h->Q);
-        if (m > n && w == 0) spike_apply(Q, h->ldq, m, n, row, kptr((const double *)h->csSp));
+        if (m > n && w == 0) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) spike_apply(Q, h->ldq, m, n, row0 + 64 * r, kptr((const double *)h->csSp));
+        }
         __syncthreads();
         for (int b = 0; b < nb1; ++b) {
             const BlockDesc bd = load_block(h->blkL, b);
-            sweep<K0, NW, 0>(Q, h->ldq, m, row, kptr((const double *)h->csL) + 2 * bd.off, bd, ring, w, lane);
+            sweep<K0, NW, R, 0>(Q, h->ldq, m, row0, kptr((const double *)h->csL) + 2 * bd.off, bd, ring, w, lane);
             __syncthreads();
         }
         for (int b = nb1; b < nb1 + nb2; ++b) {
             const BlockDesc bd = load_block(h->blkL, b);
-            sweep<K0, NW, 2>(Q, h->ldq, m, row, kptr((const double *)h->csL) + 2 * bd.off, bd, ring, w, lane);
+            sweep<K0, NW, R, 2>(Q, h->ldq, m, row0, kptr((const double *)h->csL) + 2 * bd.off, bd, ring, w, lane);
             __syncthreads();
         }
     } else {
-        const int row = (pid - qp) * 64 + lane;
+        const int row0 = (pid - qp) * PH + lane;
         GLOBAL double *P = gptr(h->P);
         for (int b = 0; b < nb1; ++b) {
             const BlockDesc bd = load_block(h->blkR, b);
-            sweep<K0, NW, 1>(P, h->ldp, n, row, kptr((const double *)h->csR) + 2 * bd.off, bd, ring, w, lane);
+            sweep<K0, NW, R, 1>(P, h->ldp, n, row0, kptr((const double *)h->csR) + 2 * bd.off, bd, ring, w, lane);
             __syncthreads();
         }
         for (int b = nb1; b < nb1 + nb2; ++b) {
             const BlockDesc bd = load_block(h->blkR, b);
-            sweep<K0, NW, 3>(P, h->ldp, n, row, kptr((const double *)h->csR) + 2 * bd.off, bd, ring, w, lane);
+            sweep<K0, NW, R, 3>(P, h->ldp, n, row0, kptr((const double *)h->csR) + 2 * bd.off, bd, ring, w, lane);
             __syncthreads();
         }
     }
@@ -552,24 +587,27 @@ hipError_t launch_gen(HandleDev *const *hs, int count, int64_t lds_bytes, bool i
     return hipGetLastError();
 }
 
-template <int K0, int NW>
+template <int K0, int NW, int R>
 static hipError_t launch_apply_t(HandleDev *const *hs, int count, int max_panels, hipStream_t st)
 {
-    hipLaunchKernelGGL((apply_kernel<K0, NW>), dim3(max_panels, count), dim3(64 * NW), 0, st, hs);
+    hipLaunchKernelGGL((apply_kernel<K0, NW, R>), dim3(max_panels, count), dim3(64 * NW), 0, st, hs);
     return hipGetLastError();
 }
 
-bool tiling_supported(int k0, int nw)
+bool tiling_supported(int k0, int nw, int rpl)
 {
-    return (k0 == 6 || k0 == 12) && (nw == 1 || nw == 2 || nw == 4);
+    if (k0 == 6 && nw == 8 && rpl == 2) return false;  // its LDS ring exceeds 160 KB
+    return (k0 == 6 || k0 == 12) && (nw == 1 || nw == 2 || nw == 4 || nw == 8) && (rpl == 1 || rpl == 2);
 }
 
-hipError_t launch_apply(HandleDev *const *hs, int count, int max_panels, int k0, int nw, hipStream_t st)
+hipError_t launch_apply(HandleDev *const *hs, int count, int max_panels, int k0, int nw, int rpl, hipStream_t st)
 {
-#define BDU_APPLY_CASE(A, B) \
-    if (k0 == A && nw == B) return launch_apply_t<A, B>(hs, count, max_panels, st);
-    BDU_APPLY_CASE(6, 1) BDU_APPLY_CASE(6, 2) BDU_APPLY_CASE(6, 4)
-    BDU_APPLY_CASE(12, 1) BDU_APPLY_CASE(12, 2) BDU_APPLY_CASE(12, 4)
+#define BDU_APPLY_CASE(A, B, C) \
+    if (k0 == A && nw == B && rpl == C) return launch_apply_t<A, B, C>(hs, count, max_panels, st);
+    BDU_APPLY_CASE(6, 1, 1) BDU_APPLY_CASE(6, 2, 1) BDU_APPLY_CASE(6, 4, 1) BDU_APPLY_CASE(6, 8, 1)
+    BDU_APPLY_CASE(12, 1, 1) BDU_APPLY_CASE(12, 2, 1) BDU_APPLY_CASE(12, 4, 1) BDU_APPLY_CASE(12, 8, 1)
+    BDU_APPLY_CASE(6, 1, 2) BDU_APPLY_CASE(6, 2, 2) BDU_APPLY_CASE(6, 4, 2)
+    BDU_APPLY_CASE(12, 1, 2) BDU_APPLY_CASE(12, 2, 2) BDU_APPLY_CASE(12, 4, 2) BDU_APPLY_CASE(12, 8, 2)
 #undef BDU_APPLY_CASE
     return hipErrorInvalidValue;
 }

@@ -124,6 +124,19 @@ std::unique_ptr<Plan> build_plan(int64_t m, int64_t n, int K0, int NW, int gen_t
         }
         P->slots[side] = pos;
     }
+    // first slot of each chain on each side (same formula the applier reads)
+    for (GenChain &g : ch) {
+        g.slot[0] = g.slot[1] = -1;
+        if (g.type == CH_FOLD) continue;
+        const int ph = chain_phase(g.type), tg = chain_in_phase(g.type, g.param);
+        const int b = tg / K, tin = tg % K, w = tin / K0, tl = tin % K0;
+        for (int s = 0; s < g.len && s < 2; ++s) {
+            const Rot r = decode(g.type, g.param, s);
+            const BlockDesc &bd = P->blocks[r.side][(ph == 1 ? 0 : P->nb1) + b];
+            const int lam0 = lam0_of_pair(ph, bd.base, r.i);
+            g.slot[r.side] = bd.off + (int64_t)(lam0 / 3 + tl + w * S) * K + tin;
+        }
+    }
     return P;
 }
 

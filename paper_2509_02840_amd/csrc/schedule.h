@@ -157,11 +157,16 @@ BDU_HD int lam0_of_pair(int phase, int base, int i)
     return phase == 1 ? base - i - 1 : i - base;
 }
 
+// A chain's rotations alternate sides; consecutive rotations on one side
+// move three columns along the chain, i.e. one front, so rotation s lands in
+// slot slot[side(s)] + (s >> 1) * K of its side's stream, side(s) =
+// side(0) xor (s & 1).
 struct GenChain {
     int32_t type;
     int32_t param;
     int32_t len;
-    int32_t tau0;  // generation tick of the chain's first rotation
+    int32_t tau0;     // generation tick of the chain's first rotation
+    int64_t slot[2];  // slot of the chain's first left / right rotation
 };
 
 struct BlockDesc {

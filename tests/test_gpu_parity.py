@@ -125,16 +125,16 @@ def test_tiling_does_not_change_results(bdu):
     f = W.factorization(m, n, 47)
     (B, C), = W.gaussian_updates(m, n, 1, 48, r=2)
     outs = []
-    k0, nw = bdu.get_tiling()
+    saved = bdu.get_tiling()
     try:
-        for tk in [(6, 1), (12, 1), (12, 2), (12, 4), (6, 4)]:
+        for tk in [(6, 1, 1), (12, 1, 1), (12, 2, 2), (12, 4, 2), (6, 4, 1), (12, 8, 2), (6, 8, 1), (12, 4, 1)]:
             bdu.set_tiling(*tk)
             h = bdu.Handle(f.Q, f.d, f.e, f.P)
             h.update(B, C)
             outs.append(h.read())
             h.close()
     finally:
-        bdu.set_tiling(k0, nw)
+        bdu.set_tiling(*saved)
     for o in outs[1:]:
         for x, y in zip(o, outs[0]):
             _eq("tiling", x, y)

@@ -100,12 +100,13 @@ def test_invalid_arguments_fail_without_a_device():
                         ctypes.byref(h)) == bdu.BDU_EINVAL
     assert L.bdu_update(None, one.ctypes.data, one.ctypes.data, 1) == bdu.BDU_EINVAL
     assert L.bdu_update_batched(None, None, None, None, 0) == bdu.BDU_EINVAL
-    assert L.bdu_set_tiling(7, 1) == bdu.BDU_EINVAL
+    assert L.bdu_set_tiling(7, 1, 1) == bdu.BDU_EINVAL
+    assert L.bdu_set_tiling(12, 4, 3) == bdu.BDU_EINVAL
     assert L.bdu_plan_stats(3, 4, None) == bdu.BDU_EINVAL
     assert bdu.lib().bdu_strerror(bdu.BDU_ENOMEM) == b"out of device memory"
 
 
 def test_footprint_grows_with_size():
     a, b = bdu.footprint_bytes(512, 512), bdu.footprint_bytes(1024, 1024)
-    assert 3.5 * a < b < 4.5 * a
+    assert 3.0 * a < b < 4.5 * a
     assert b > 16 * 1024 * 1024  # Q and P alone
