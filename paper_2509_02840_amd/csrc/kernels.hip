@@ -183,15 +183,42 @@ __global__ __launch_bounds__(64) void spike_kernel(HandleDev *const *hs)
 // Band storage: row r (1-based, -3..N+4) at (r+3)*6, the entry in column c
 // at offset c - r in [-2, 3].  Entries outside that band read as zero and are
 // never written: the schedule keeps them zero.
-struct Band {
-    double *s;
-    __device__ __forceinline__ int cell(int r, int c) const
-    {
-        int o = c - r;
-        return (o < -2 || o > 3) ? -1 : (r + 3) * 6 + (o + 2);
-    }
+
+// Chain descriptor held in registers (GenChain fields).
+struct ChainReg {
+    int type, param, len, tau0;
+    int64_t slot0, slot1;
 };
 
+__device__ __forceinline__ ChainReg load_chain(const GenChain *chains, int idx)
+{
+    const GLOBAL int *p = (const GLOBAL int *)gptr(chains) + 8 * idx;
+    const GLOBAL int64_t *q = (const GLOBAL int64_t *)(p + 4);
+    ChainReg c;
+    c.type = p[0];
+    c.param = p[1];
+    c.len = p[2];
+    c.tau0 = p[3];
+    c.slot0 = q[0];
+    c.slot1 = q[1];
+    return c;
+}
+
+// Generation of one pass for one handle per workgroup.  Thread l runs chains
+// l, l + blockDim, ... (non-empty chains in schedule order); chain c performs
+// its rotation s at tick tau0(c) + s, and a barrier separates ticks.  The host
+// chose the start ticks so that two rotations touching a common band row, u or
+// v entry are ordered as in the sequential schedule.
+//
+// Every rotation is decoded without branches.  In phase 1 both chain types
+// are the up-left chase pattern L(ii) [(ii,ii+3) onto (ii+1,ii+3)],
+// R(ii-1) [(ii+1,ii-1) onto (ii+1,ii)], ii = i0 - 3*(ss>>1), whose first
+// rotation eliminates an entry of v (P1A) or u (P1B) instead.  In phase 2 both
+// are the down-right pattern R(ii+2) [(ii,ii+3) into (ii,ii+2)], L(ii+3)
+// [(ii+4,ii+2) into (ii+3,ii+2)], ii = i0 + 3*(ss>>1), whose first rotation
+// acts one column (P2A) or one row (P2B) further on.  A left rotation on rows
+// (i, i+1) rotates the band pairs in columns i-2..i+4, a right rotation on
+// columns (j, j+1) those in rows j-3..j+3, plus the matching u or v pair.
 template <bool IN_LDS>
 __global__ __launch_bounds__(kGenThreads) void gen_kernel(HandleDev *const *hs)
 {
@@ -199,107 +226,115 @@ __global__ __launch_bounds__(kGenThreads) void gen_kernel(HandleDev *const *hs)
     const CONSTANT HandleDev *h = kptr(hs[blockIdx.x]);
     const int n = h->n, N = h->N;
     double *S = IN_LDS ? smem : h->band;
-    double *U = S + 6 * (N + 8);  // u_i at U[i+3]
-    double *V = U + (N + 8);      // v_j at V[j+3]
+    const int UO = 6 * (N + 8);      // u_i at S[UO + i + 3]
+    const int VO = UO + (N + 8);     // v_j at S[VO + j + 3]
     const int tid = threadIdx.x;
     const int nt = blockDim.x;
-    const int total = 6 * (N + 8) + (N + 8) + (n + 8);
+    const int total = VO + (n + 8);
     for (int k = tid; k < total; k += nt) S[k] = 0.0;
     __syncthreads();
-    Band band{S};
+    auto cell = [](int r, int c) { return (r + 3) * 6 + (c - r) + 2; };
     for (int i = 1 + tid; i <= n; i += nt) {
-        S[band.cell(i, i)] = h->d[i - 1];
-        if (i < n) S[band.cell(i, i + 1)] = h->e[i - 1];
-        V[i + 3] = h->v[i - 1];
+        S[cell(i, i)] = h->d[i - 1];
+        if (i < n) S[cell(i, i + 1)] = h->e[i - 1];
+        S[VO + i + 3] = h->v[i - 1];
     }
-    for (int i = 1 + tid; i <= N; i += nt) U[i + 3] = h->u[i - 1];
+    for (int i = 1 + tid; i <= N; i += nt) S[UO + i + 3] = h->u[i - 1];
     __syncthreads();
 
     const int K = h->K;
+    const int nch = h->nchains;
+    GLOBAL double *csL = gptr((double *)h->csL), *csR = gptr((double *)h->csR);
     int ci = tid;
-    GenChain g, gn;
+    ChainReg g, gn;
     g.len = 0;
-    if (ci < h->nchains) g = h->chains[ci];
-    if (ci + nt < h->nchains) gn = h->chains[ci + nt];
+    g.tau0 = 0;
+    if (ci < nch) g = load_chain(h->chains, ci);
+    if (ci + nt < nch) gn = load_chain(h->chains, ci + nt);
     const int64_t ticks = h->ticks;
     for (int64_t t = 0; t < ticks; ++t) {
-        if (ci < h->nchains) {
-            const int s = (int)(t - g.tau0);
-            if (s >= 0) {
-                if (g.type == CH_FOLD) {
-                    // u v^T now touches only (N-1, n) and (N, n)
-                    const int a = band.cell(N - 1, n), b = band.cell(N, n);
-                    S[a] = fma(U[N - 1 + 3], V[n + 3], S[a]);
-                    S[b] = fma(U[N + 3], V[n + 3], S[b]);
+        const int s = (int)(t - g.tau0);
+        if (ci < nch && s >= 0) {
+            if (g.type == CH_FOLD) {
+                // u v^T now touches only (N-1, n) and (N, n)
+                const int a = cell(N - 1, n), b = cell(N, n);
+                S[a] = fma(S[UO + N - 1 + 3], S[VO + n + 3], S[a]);
+                S[b] = fma(S[UO + N + 3], S[VO + n + 3], S[b]);
+            } else {
+                const bool ph1 = g.type <= CH_P1B;
+                const bool first = ph1 ? (g.type == CH_P1A) : (g.type == CH_P2A);
+                const int ss = s + (first ? 1 : 0);
+                const int odd = ss & 1;
+                const int i0 = ph1 ? (first ? g.param + 1 : g.param) : (first ? g.param - 3 : g.param - 1);
+                const int ii = ph1 ? i0 - 3 * (ss >> 1) : i0 + 3 * (ss >> 1);
+                int side, i, r0, c0, r1, c1;
+                if (ph1) {
+                    side = odd;
+                    i = odd ? ii - 1 : ii;
+                    r0 = odd ? ii + 1 : ii;
+                    c0 = odd ? ii - 1 : ii + 3;
+                    r1 = ii + 1;
+                    c1 = odd ? ii : ii + 3;
                 } else {
-                    const Rot r = decode(g.type, g.param, s);
-                    int ga, gb;
-                    if (r.gvec) {
-                        double *vec = r.side == 0 ? U : V;
-                        ga = (int)(vec - S) + r.i + 3;
-                        gb = ga + 1;
-                    } else {
-                        ga = band.cell(r.gr0, r.gc0);
-                        gb = band.cell(r.gr1, r.gc1);
-                    }
-                    double c, sn, rr;
-                    givens(S[ga], S[gb], r.mode, c, sn, rr);
-                    // rotate the seven band pairs of the window and the vector pair
-                    int ax[8], ay[8];
-                    #pragma unroll
-                    for (int q = 0; q < 7; ++q) {
-                        if (r.side == 0) {
-                            ax[q] = band.cell(r.i, r.i - 2 + q);
-                            ay[q] = band.cell(r.i + 1, r.i - 2 + q);
-                        } else {
-                            ax[q] = band.cell(r.i - 3 + q, r.i);
-                            ay[q] = band.cell(r.i - 3 + q, r.i + 1);
-                        }
-                    }
-                    const bool ph1 = g.type <= CH_P1B;
-                    if (ph1) {
-                        double *vec = r.side == 0 ? U : V;
-                        ax[7] = (int)(vec - S) + r.i + 3;
-                        ay[7] = ax[7] + 1;
-                    } else {
-                        ax[7] = -1;
-                        ay[7] = -1;
-                    }
-                    double xv[8], yv[8];
-                    #pragma unroll
-                    for (int q = 0; q < 8; ++q) {
-                        xv[q] = ax[q] >= 0 ? S[ax[q]] : 0.0;
-                        yv[q] = ay[q] >= 0 ? S[ay[q]] : 0.0;
-                    }
-                    #pragma unroll
-                    for (int q = 0; q < 8; ++q) {
-                        rot(c, sn, xv[q], yv[q]);
-                        if (ax[q] >= 0) S[ax[q]] = xv[q];
-                        if (ay[q] >= 0) S[ay[q]] = yv[q];
-                    }
-                    if (r.mode == 1) {
-                        S[ga] = 0.0;
-                        S[gb] = rr;
-                    } else {
-                        S[ga] = rr;
-                        S[gb] = 0.0;
-                    }
-                    // slot of this rotation in the applier layout
-                    double2 *cs = r.side == 0 ? h->csL : h->csR;
-                    cs[g.slot[r.side] + (int64_t)(s >> 1) * K] = make_double2(c, sn);
+                    side = odd ? 0 : 1;
+                    i = odd ? ii + 3 : ii + 2;
+                    r0 = odd ? ii + 3 : ii;
+                    c0 = ii + 2;
+                    r1 = odd ? ii + 4 : ii;
+                    c1 = odd ? ii + 2 : ii + 3;
+                    const int dr = (s == 0 && !odd) ? 1 : 0, dc = (s == 0 && odd) ? 1 : 0;
+                    r0 += dr; r1 += dr; c0 += dc; c1 += dc;
                 }
-                if (s == g.len - 1) {
-                    ci += nt;
-                    g = gn;
-                    if (ci + nt < h->nchains) gn = h->chains[ci + nt];
+                const int mode = ph1 ? 1 : 2;
+                // window pairs: x cells xb + q*xs (q = 0..5), y cells yb + q*ys (q = 1..6)
+                const int xb = side == 0 ? (i + 3) * 6 : i * 6 + 5;
+                const int yb = side == 0 ? (i + 4) * 6 - 1 : i * 6 + 6;
+                const int st = side == 0 ? 1 : 5;
+                const int vb = (side == 0 ? UO : VO) + i + 3;
+                int ga, gb;
+                if (ph1 && s == 0) {
+                    ga = vb;
+                    gb = vb + 1;
+                } else {
+                    ga = cell(r0, c0);
+                    gb = cell(r1, c1);
                 }
+                double c, sn, rr;
+                givens(S[ga], S[gb], mode, c, sn, rr);
+                double xv[7], yv[7], ux = S[vb], uy = S[vb + 1];
+#pragma unroll
+                for (int q = 0; q < 7; ++q) {
+                    xv[q] = q <= 5 ? S[xb + q * st] : 0.0;
+                    yv[q] = q >= 1 ? S[yb + q * st] : 0.0;
+                }
+#pragma unroll
+                for (int q = 0; q < 7; ++q) {
+                    rot(c, sn, xv[q], yv[q]);
+                    if (q <= 5) S[xb + q * st] = xv[q];
+                    if (q >= 1) S[yb + q * st] = yv[q];
+                }
+                rot(c, sn, ux, uy);
+                S[vb] = ux;
+                S[vb + 1] = uy;
+                S[ga] = mode == 1 ? 0.0 : rr;
+                S[gb] = mode == 1 ? rr : 0.0;
+                // slot of this rotation in the applier layout
+                GLOBAL double *cs = side == 0 ? csL : csR;
+                const int64_t slot = (side == 0 ? g.slot0 : g.slot1) + (int64_t)(s >> 1) * K;
+                cs[2 * slot] = c;
+                cs[2 * slot + 1] = sn;
+            }
+            if (s == g.len - 1) {
+                ci += nt;
+                g = gn;
+                if (ci + nt < nch) gn = load_chain(h->chains, ci + nt);
             }
         }
         __syncthreads();
     }
     for (int i = 1 + tid; i <= n; i += nt) {
-        h->d[i - 1] = S[band.cell(i, i)];
-        if (i < n) h->e[i - 1] = S[band.cell(i, i + 1)];
+        h->d[i - 1] = S[cell(i, i)];
+        if (i < n) h->e[i - 1] = S[cell(i, i + 1)];
     }
 }
 
