@@ -1,8 +1,9 @@
 """Benchmark: FP64 rank-1 bidiagonal updates per second on one MI355X.
 
 Workload (square streams, m = n = 2048, the tiny-config construction at
-that size): Q0, P0 are Householder-QR factors of N(0,1) matrices, d ~ U(1,10),
-e ~ U(0,1); every update is b ~ N(0,1)/sqrt(m), c ~ N(0,1)/sqrt(n).
+that size): Q0, P0 are Haar orthogonal (Householder-QR factors of N(0,1)
+matrices, signed-column-permuted per stream), d ~ U(1,10), e ~ U(0,1); every
+update is b ~ N(0,1)/sqrt(m), c ~ N(0,1)/sqrt(n).
 
 - batched (the reported value): S streams; one step is one rank-1 update of
   every stream in one bdu_update_batched call.  value = S * steps / time.
@@ -32,18 +33,36 @@ METRIC = "FP64 rank-1 updates/sec + p50/p99 latency, batched vs plain, n=2048"
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CUs x 128 FP64 flop/clk x 2.4 GHz
 
 
-def make_stream(torch, gen, n: int):
-    """Q0, d0, e0, P0 on the device (Householder QR of N(0,1) on the GPU)."""
-    dev = torch.device("cuda:0")
-    G1 = torch.randn((n, n), generator=gen, dtype=torch.float64, device=dev)
-    G2 = torch.randn((n, n), generator=gen, dtype=torch.float64, device=dev)
-    Q, _ = torch.linalg.qr(G1)
-    P, _ = torch.linalg.qr(G2)
-    Q = Q.T.contiguous().T  # column-major
-    P = P.T.contiguous().T
-    d = 1.0 + 9.0 * torch.rand(n, generator=gen, dtype=torch.float64, device=dev)
-    e = torch.rand(n - 1, generator=gen, dtype=torch.float64, device=dev)
-    return Q, d, e, P
+class StreamFactory:
+    """Seeded initial factorizations on the device.
+
+    Q0 and P0 are Haar-distributed orthogonal matrices: the Q factors of a
+    Householder QR of N(0,1) matrices (LAPACK, computed once on the host),
+    each stream taking its own random signed column permutation of them.
+    d ~ U(1, 10), e ~ U(0, 1) are drawn per stream."""
+
+    def __init__(self, torch, gen, n: int, seed: int):
+        from paper_2509_02840_amd import workloads as W
+
+        rng = np.random.default_rng(seed)
+        dev = torch.device("cuda:0")
+        self.torch, self.gen, self.n, self.dev = torch, gen, n, dev
+        self.Qb = torch.from_numpy(np.ascontiguousarray(W.orthogonal(rng, n))).to(dev)
+        self.Pb = torch.from_numpy(np.ascontiguousarray(W.orthogonal(rng, n))).to(dev)
+
+    def _signed_perm(self, B):
+        torch, n = self.torch, self.n
+        perm = torch.randperm(n, generator=self.gen, device=self.dev)
+        sgn = torch.randint(0, 2, (n,), generator=self.gen, device=self.dev).to(torch.float64) * 2.0 - 1.0
+        return (B[:, perm] * sgn).T.contiguous().T  # column-major
+
+    def make(self):
+        torch, n = self.torch, self.n
+        Q = self._signed_perm(self.Qb)
+        P = self._signed_perm(self.Pb)
+        d = 1.0 + 9.0 * torch.rand(n, generator=self.gen, dtype=torch.float64, device=self.dev)
+        e = torch.rand(n - 1, generator=self.gen, dtype=torch.float64, device=self.dev)
+        return Q, d, e, P
 
 
 def make_updates(torch, gen, n: int, count: int):
@@ -102,8 +121,10 @@ def main() -> int:
     gen = torch.Generator(device="cuda:0")
     gen.manual_seed(args.seed)
 
+    factory = StreamFactory(torch, gen, n, args.seed)
+
     # ---- plain: one stream, one update per call --------------------------
-    Q, d, e, P = make_stream(torch, gen, n)
+    Q, d, e, P = factory.make()
     h = bdu.Handle(Q, d, e, P)
     del Q, P
     pb, pc = make_updates(torch, gen, n, args.warmup + args.plain_steps)
@@ -129,7 +150,7 @@ def main() -> int:
     S = args.streams
     hs = []
     for _ in range(S):
-        Q, d, e, P = make_stream(torch, gen, n)
+        Q, d, e, P = factory.make()
         hs.append(bdu.Handle(Q, d, e, P))
         del Q, P
     torch.cuda.empty_cache()

@@ -273,7 +273,8 @@ int64_t slot_of(const Plan &P, const GenChain &g, const Rot &r)
     const int b = tg / P.K, tin = tg % P.K, w = tin / P.K0, tl = tin % P.K0;
     const BlockDesc &bd = P.blocks[r.side][(ph == 1 ? 0 : P.nb1) + b];
     const int lam0 = lam0_of_pair(ph, bd.base, r.i);
-    return bd.off + (int64_t)(lam0 / 3 + tl + w * P.S) * P.K + tin;
+    const int pos = front_order(2 * (ph - 1) + r.side, P.K, P.K0).pos[tl];
+    return bd.off + (int64_t)(lam0 / 3 + tl + w * P.S) * P.K + w * P.K0 + pos;
 }
 
 }  // namespace
@@ -322,7 +323,7 @@ int64_t bdu_footprint_bytes(int64_t m, int64_t n)
     int64_t N = p->N;
     const int64_t ldq = (m + 127) / 128 * 128, ldp = (n + 127) / 128 * 128;
     int64_t bytes = 8 * (ldq * m + ldp * n + 2 * n + 2 * (m + n) + 2 * (m + n));
-    bytes += 16 * (p->slots[0] + p->slots[1] + std::max<int64_t>(p->nspike, 1));
+    bytes += 16 * (p->slots[0] + p->slots[1] + 2 * (4 * (int64_t)p->K + 64) + std::max<int64_t>(p->nspike, 1));
     if (gen_lds_bytes(n, N) > kMaxGenLds) bytes += gen_lds_bytes(n, N);
     return bytes;
 }
@@ -355,8 +356,11 @@ int bdu_create(int64_t m, int64_t n, const double *Q, const double *d, const dou
     A(dalloc(h.get(), &hd.v, n));
     A(dalloc(h.get(), &hd.bst, m));
     A(dalloc(h.get(), &hd.cst, n));
-    A(dalloc(h.get(), &hd.csL, plan->slots[0]));
-    A(dalloc(h.get(), &hd.csR, plan->slots[1]));
+    // slack of a few fronts: the applier releases the address of the next
+    // front's coefficients one group early, also after a block's last front
+    const int64_t slack = 4 * (int64_t)plan->K + 64;
+    A(dalloc(h.get(), &hd.csL, plan->slots[0] + slack));
+    A(dalloc(h.get(), &hd.csR, plan->slots[1] + slack));
     A(dalloc(h.get(), &hd.csSp, plan->nspike));
     if (!h->lds_gen) A(dalloc(h.get(), &hd.band, gen_lds_bytes(n, plan->N) / 8));
     A(dalloc(h.get(), &h->d_hd, 1));
@@ -390,8 +394,8 @@ int bdu_create(int64_t m, int64_t n, const double *Q, const double *d, const dou
     HIPCHK(hp, copy_mat_in(hd.P, ldp, P, n, n, hp->stream));
     HIPCHK(hp, copy_in(hd.d, d, sizeof(double) * n, hp->stream));
     HIPCHK(hp, copy_in(hd.e, e, sizeof(double) * (n - 1), hp->stream));
-    HIPCHK(hp, launch_fill_identity(hd.csL, plan->slots[0], hp->stream));
-    HIPCHK(hp, launch_fill_identity(hd.csR, plan->slots[1], hp->stream));
+    HIPCHK(hp, launch_fill_identity(hd.csL, plan->slots[0] + slack, hp->stream));
+    HIPCHK(hp, launch_fill_identity(hd.csR, plan->slots[1] + slack, hp->stream));
     HIPCHK(hp, hipMemcpyAsync(h->d_hd, &hd, sizeof(HandleDev), hipMemcpyHostToDevice, hp->stream));
     HandleDev *self = h->d_hd;
     HIPCHK(hp, hipMemcpyAsync(h->d_self, &self, sizeof(self), hipMemcpyHostToDevice, hp->stream));

@@ -340,16 +340,6 @@ __global__ __launch_bounds__(kGenThreads) void gen_kernel(HandleDev *const *hs)
 
 // ---- application ----------------------------------------------------------------
 
-// Residue mod 3 of the lower local column of chain t's pairs in a block of
-// K chains (K0 a multiple of 6 keeps it the same in every wavefront).
-// mode 0: phase 1 left, 1: phase 1 right, 2: phase 2 left, 3: phase 2 right.
-__host__ __device__ constexpr int rho_of(int mode, int K, int t)
-{
-    int i = t >> 1, h = t & 1;
-    int v = mode == 0 ? K / 2 - i + h : mode == 1 ? K / 2 + 1 - i + h : mode == 2 ? i + 2 * h : i + 2 - h;
-    return ((v % 3) + 3) % 3;
-}
-
 __host__ __device__ constexpr int pmod(int a, int b) { return ((a % b) + b) % b; }
 
 // Columns in the LDS ring between two wavefronts: at most 14 columns are live
@@ -413,6 +403,18 @@ __device__ __forceinline__ void sweep(GLOBAL double *__restrict__ X, int ld, int
             for (int r = 0; r < R; ++r) buf[r][k] = cp[row0 + 64 * r];
         }
     }
+    // Coefficients come in groups of G rotations.  The address of the group
+    // after next (crossing into the next front at a front's end) is made
+    // opaque two groups early, so its scalar loads are issued while the
+    // current group computes but are never hoisted further (scalar registers
+    // are few).
+    constexpr int G = K0 % 4 == 0 ? 4 : 3;
+    static_assert(K0 % G == 0 && K0 / G >= 2 && K0 <= 24, "coefficient groups must tile a front");
+    const CONSTANT double *pg = cs + 2 * (w * K0);
+    const CONSTANT double *pg1 = pg + 2 * G;  // always two groups in flight
+    constexpr FrontOrder ord = front_order(MODE, K, K0);
+    asm volatile("" : "+s"(pg));
+    asm volatile("" : "+s"(pg1));
     for (int F0 = 0; F0 < nfront; F0 += U) {
 #pragma unroll
         for (int phi = 0; phi < U; ++phi) {
@@ -438,22 +440,18 @@ __device__ __forceinline__ void sweep(GLOBAL double *__restrict__ X, int ld, int
                     for (int r = 0; r < R; ++r)
                         buf[r][pmod(3 * phi + k, WSZ)] = rin[(pmod(3 * phi + k, RC) * R + r) * 64];
             }
-            // this wavefront's K0 rotations at front F.  The empty asm makes
-            // the coefficient address opaque, so their scalar loads are issued
-            // here and not hoisted over the whole unrolled sweep.
-            // Coefficients come in groups of G rotations; the next group's
-            // address is released one group early so its loads overlap.
-            constexpr int G = 6;
+            // this wavefront's K0 rotations at front F, in front_order (their
+            // coefficients are stored in that order)
             const CONSTANT double *csF = cs + 2 * ((int64_t)F * K + w * K0);
-            const CONSTANT double *pg = csF;
-            asm volatile("" : "+s"(pg));
 #pragma unroll
             for (int g = 0; g < K0 / G; ++g) {
-                const CONSTANT double *pn = csF + 2 * G * (g + 1);
-                if (g + 1 < K0 / G) asm volatile("" : "+s"(pn));
+                // address of the group after next (crossing into the next front)
+                const int gg = g + 2;
+                const CONSTANT double *pn = csF + (gg < K0 / G ? 2 * G * gg : 2 * K + 2 * G * (gg - K0 / G));
+                asm volatile("" : "+s"(pn));
 #pragma unroll
                 for (int q = 0; q < G; ++q) {
-                    const int t = g * G + q;
+                    const int t = ord.t[g * G + q];
                     const int l0 = 3 * (phi - t) + rho_of(MODE, K, t);
                     const int sx = pmod(l0 + (DESC ? 1 : 0), WSZ);
                     const int sy = pmod(l0 + (DESC ? 0 : 1), WSZ);
@@ -461,7 +459,8 @@ __device__ __forceinline__ void sweep(GLOBAL double *__restrict__ X, int ld, int
 #pragma unroll
                     for (int r = 0; r < R; ++r) rot(c, sn, buf[r][sx], buf[r][sy]);
                 }
-                pg = pn;
+                pg = pg1;
+                pg1 = pn;
             }
             // finished columns leave the window
 #pragma unroll
@@ -480,12 +479,14 @@ __device__ __forceinline__ void sweep(GLOBAL double *__restrict__ X, int ld, int
                 }
             }
             if (NW > 1) __syncthreads();
-            // keep fronts in order: the window is materialised here, so the
-            // scheduler cannot interleave two fronts (and their coefficients)
+            // keep fronts in order: the columns in use (local 3(f-K0+1) ..
+            // 3f+3) are materialised here, so the scheduler cannot interleave
+            // two fronts (and their coefficients).  Columns loaded ahead are
+            // left out: their loads stay in flight until first use.
 #pragma unroll
             for (int r = 0; r < R; ++r)
 #pragma unroll
-                for (int i = 0; i < WSZ; ++i) asm volatile("" : "+v"(buf[r][i]));
+                for (int j = -3 * (K0 - 1); j <= 3; ++j) asm volatile("" : "+v"(buf[r][pmod(3 * phi + j, WSZ)]));
         }
     }
 }
@@ -507,15 +508,27 @@ __device__ void spike_apply(GLOBAL double *Q, int ld, int m, int n, int row, con
 
 // grid (panels, handles): panels [0, ceil(m/(64R))) update Q, the rest P.  Q
 // and P have leading dimensions padded to a multiple of 128 rows.
+//
+// Occupancy: at one wavefront per SIMD a rotation loop issues at well under
+// half the FP64 rate, so the register budget is capped to keep at least two
+// wavefronts per SIMD (the (12, *, 2) tilings fit 256 registers without
+// spilling; the smaller windows fit three).
 template <int K0, int NW, int R>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(1, 2))) void apply_kernel(
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(K0 * R >= 24 ? 2 : 3))) void apply_kernel(
     HandleDev *const *hs)
 {
-    const CONSTANT HandleDev *h = kptr(hs[blockIdx.y]);
+    // Workgroups are dispatched round-robin over the 8 XCDs.  Renumber them so
+    // that the panels of one handle run on the same XCD and share its L2 copy
+    // of the handle's rotation streams.
+    const int total = gridDim.x * gridDim.y;
+    const int lin = blockIdx.y * gridDim.x + blockIdx.x;
+    int item = lin;
+    if (total % 8 == 0) item = (lin % 8) * (total / 8) + lin / 8;
+    const int hidx = item / gridDim.x, pid = item % gridDim.x;
+    const CONSTANT HandleDev *h = kptr(hs[hidx]);
     const int m = h->m, n = h->n;
     constexpr int PH = 64 * R;
     const int qp = (m + PH - 1) / PH, pp = (n + PH - 1) / PH;
-    const int pid = blockIdx.x;
     if (pid >= qp + pp) return;
     constexpr int RING = (NW > 1 ? NW - 1 : 1) * ring_cols(K0) * 64 * R;
     __shared__ double ring[RING];

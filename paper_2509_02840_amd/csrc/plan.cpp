@@ -134,7 +134,8 @@ std::unique_ptr<Plan> build_plan(int64_t m, int64_t n, int K0, int NW, int gen_t
             const Rot r = decode(g.type, g.param, s);
             const BlockDesc &bd = P->blocks[r.side][(ph == 1 ? 0 : P->nb1) + b];
             const int lam0 = lam0_of_pair(ph, bd.base, r.i);
-            g.slot[r.side] = bd.off + (int64_t)(lam0 / 3 + tl + w * S) * K + tin;
+            const int pos = front_order(2 * (ph - 1) + r.side, K, K0).pos[tl];
+            g.slot[r.side] = bd.off + (int64_t)(lam0 / 3 + tl + w * S) * K + w * K0 + pos;
         }
     }
     return P;

@@ -145,7 +145,9 @@ BDU_HD int chain_phase(int type) { return type <= CH_P1B ? 1 : 2; }
 //   phase 2 (chains run towards column n): lambda = c - base, base = k0
 // with k0 = 1 + b*K/2 the block's first step.  A rotation of chain
 // t = w*K0 + tl of the block on the pair whose lower local column is lam0
-// sits at front F = floor(lam0 / 3) + tl + w*S, slot F*K + t, S = K0 + 3.
+// sits at front F = floor(lam0 / 3) + tl + w*S, slot F*K + w*K0 + pos(tl),
+// S = K0 + 3, where pos is the chain's place in the front's processing order
+// (front_order below).
 BDU_HD int block_base(int phase, int b, int K)
 {
     int k0 = 1 + b * (K / 2);
@@ -155,6 +157,52 @@ BDU_HD int block_base(int phase, int b, int K)
 BDU_HD int lam0_of_pair(int phase, int base, int i)
 {
     return phase == 1 ? base - i - 1 : i - base;
+}
+
+// Residue mod 3 of the lower local column of the pairs of chain t (block
+// index; K0 a multiple of 6 makes it the same for chain t of every
+// wavefront).  mode 0: phase 1 left, 1: phase 1 right, 2: phase 2 left,
+// 3: phase 2 right.  At one front chain t's pair starts at local column
+// 3(f - t) + rho for the wavefront-local front f.
+BDU_HD constexpr int rho_of(int mode, int K, int t)
+{
+    int i = t >> 1, h = t & 1;
+    int v = mode == 0 ? K / 2 - i + h : mode == 1 ? K / 2 + 1 - i + h : mode == 2 ? i + 2 * h : i + 2 - h;
+    return ((v % 3) + 3) % 3;
+}
+
+// Chains t and t+1 touch a common column at the same front exactly when
+// rho(t+1) - rho(t) = 2; then t's rotation comes first in the update order.
+BDU_HD constexpr bool shares_next(int mode, int K, int t)
+{
+    return rho_of(mode, K, t + 1) - rho_of(mode, K, t) == 2;
+}
+
+// Processing order of a wavefront's K0 chains within one front: last chain
+// first (the columns that just entered the window, used by chain 0, are
+// needed last; those leaving it, touched by chain K0-1, are final first),
+// except that a pair sharing a column keeps its update order.
+struct FrontOrder {
+    int t[24];    // chain at each position
+    int pos[24];  // position of each chain
+};
+
+BDU_HD constexpr FrontOrder front_order(int mode, int K, int K0)
+{
+    FrontOrder o{};
+    int p = 0;
+    for (int t = K0 - 1; t >= 0;) {
+        if (t > 0 && shares_next(mode, K, t - 1)) {
+            o.t[p++] = t - 1;
+            o.t[p++] = t;
+            t -= 2;
+        } else {
+            o.t[p++] = t;
+            t -= 1;
+        }
+    }
+    for (int q = 0; q < K0; ++q) o.pos[o.t[q]] = q;
+    return o;
 }
 
 // A chain's rotations alternate sides; consecutive rotations on one side
