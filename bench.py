@@ -32,6 +32,31 @@ sys.path.insert(0, ROOT)
 METRIC = "FP64 rank-1 updates/sec + p50/p99 latency, batched vs plain, n=2048"
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CUs x 128 FP64 flop/clk x 2.4 GHz
 
+# HBM bytes of one applier launch, from rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE runs of this script (profiles/apply_kernel_n2048_s64_traffic.md),
+# each scaled by what the counter reads for a plain 1 GiB device copy
+# (bench.py --copy-probe).  Valid only for the sources with this digest and
+# the workload named; otherwise the traffic is reported as null.
+TRAFFIC_SOURCES = ["paper_2509_02840_amd/csrc/kernels.hip", "paper_2509_02840_amd/csrc/schedule.h",
+                   "paper_2509_02840_amd/csrc/device.h", "paper_2509_02840_amd/csrc/plan.cpp"]
+MEASURED_TRAFFIC = {"sha256": None, "n": 2048, "streams": 64, "tiling": (12, 8, 1), "bytes": None}
+
+
+def sources_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(n: int, streams: int, tiling) -> float | None:
+    t = MEASURED_TRAFFIC
+    if t["bytes"] is None or (n, streams, tuple(tiling)) != (t["n"], t["streams"], t["tiling"]):
+        return None
+    return t["bytes"] if sources_digest() == t["sha256"] else None
+
 
 class StreamFactory:
     """Seeded initial factorizations on the device.
@@ -93,6 +118,21 @@ def cpu_baseline(n: int, seed: int) -> dict:
             "sample": f"one rank-1 update of one {n}x{n} stream, single thread ({dt:.1f} s)"}
 
 
+def copy_probe(torch) -> int:
+    """A plain device copy of known size: under the FETCH_SIZE / WRITE_SIZE
+    counters it gives the factor between counted and true HBM bytes."""
+    n = 1 << 27  # 2^27 doubles = 1 GiB
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read_per_launch": 8 * n, "copy_probe_bytes_written_per_launch": 8 * n,
+                      "launches": 3}))
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +144,8 @@ def main() -> int:
     ap.add_argument("--seed", type=int, default=5000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tiling", type=str, default=None, help="applier tiling K0,NW,RPL (default: library default)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy three times (scale for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -112,6 +154,9 @@ def main() -> int:
         return 2
 
     import torch
+
+    if args.copy_probe:
+        return copy_probe(torch)
     from paper_2509_02840_amd import bdu
 
     torch.cuda.set_device(0)
@@ -209,7 +254,8 @@ def main() -> int:
         "plain_p99_ms": 1e3 * float(np.percentile(lat, 99)),
         "stage_ms_per_step": {k: v[0] / args.steps for k, v in stages.items()},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+                     "traffic": measured_traffic(n, S, (k0, nw, rpl)),
                      "kernel": "apply_kernel", "flops_per_launch": flops_per_launch,
                      "avg_launch_ms": avg_apply_s * 1e3},
     }

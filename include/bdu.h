@@ -104,8 +104,8 @@ int64_t bdu_footprint_bytes(int64_t m, int64_t n);
 
 /* Applier tiling: chains per wavefront k0 in {6, 12}, wavefronts per
  * workgroup nw in {1, 2, 4, 8}, matrix rows per lane rpl in {1, 2} (except
- * k0 = 6, nw = 8, rpl = 2).  Applies to handles created afterwards.  Results
- * do not depend on it. */
+ * k0 = 6, nw = 8, rpl = 2); default (12, 8, 1).  Applies to handles created
+ * afterwards.  Results do not depend on it. */
 int bdu_set_tiling(int k0, int nw, int rpl);
 int bdu_get_tiling(int *k0, int *nw, int *rpl);
 

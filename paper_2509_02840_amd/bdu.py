@@ -106,7 +106,7 @@ def _ptr(a, matrix: bool = False):
     return a.data_ptr()
 
 
-def set_tiling(k0: int, nw: int, rpl: int = 2) -> None:
+def set_tiling(k0: int, nw: int, rpl: int = 1) -> None:
     _check(lib().bdu_set_tiling(k0, nw, rpl), "bdu_set_tiling")
 
 

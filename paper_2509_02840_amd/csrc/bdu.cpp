@@ -25,7 +25,7 @@ using namespace bdu;
 namespace {
 
 std::mutex g_mu;
-int g_k0 = 12, g_nw = 4, g_rpl = 2;
+int g_k0 = 12, g_nw = 8, g_rpl = 1;
 
 struct PlanEntry {
     std::unique_ptr<Plan> plan;

@@ -409,13 +409,27 @@ __device__ __forceinline__ void sweep(GLOBAL double *__restrict__ X, int ld, int
     // current group computes but are never hoisted further (scalar registers
     // are few).
     constexpr int G = K0 % 4 == 0 ? 4 : 3;
-    static_assert(K0 % G == 0 && K0 / G >= 2 && K0 <= 24, "coefficient groups must tile a front");
-    const CONSTANT double *pg = cs + 2 * (w * K0);
-    const CONSTANT double *pg1 = pg + 2 * G;  // always two groups in flight
+    constexpr int NG = K0 / G;
+    static_assert(K0 % G == 0 && NG >= 2 && K0 <= 24, "coefficient groups must tile a front");
     constexpr FrontOrder ord = front_order(MODE, K, K0);
-    asm volatile("" : "+s"(pg));
-    asm volatile("" : "+s"(pg1));
-    for (int F0 = 0; F0 < nfront; F0 += U) {
+    // Chunks of U = S fronts where this wavefront meets only identity
+    // rotations (pipeline fill, local fronts f < 0; drain, after its last
+    // column has left the window) only keep the workgroup's barriers.
+    // Live chunks are F0 = w S + c U, c = 0 .. ceil((flush_end + 1) / U) - 1.
+    const int flush_end = lam_hi / 3 + K0 - 1;
+    const int nchunk = nfront / U;
+    int live_end = w + (flush_end + U) / U;  // one past the last live chunk
+    live_end = live_end < nchunk ? live_end : nchunk;
+    auto idle = [&](int chunks) {
+        if (NW > 1)
+            for (int c = 0; c < chunks * U; ++c) __syncthreads();
+    };
+    idle(w);
+    for (int F0 = w * S; F0 < live_end * U; F0 += U) {
+        const CONSTANT double *pg = cs + 2 * ((int64_t)F0 * K + w * K0);
+        const CONSTANT double *pg1 = pg + 2 * G;  // always two groups in flight
+        asm volatile("" : "+s"(pg));
+        asm volatile("" : "+s"(pg1));
 #pragma unroll
         for (int phi = 0; phi < U; ++phi) {
             const int F = F0 + phi;
@@ -444,10 +458,10 @@ __device__ __forceinline__ void sweep(GLOBAL double *__restrict__ X, int ld, int
             // coefficients are stored in that order)
             const CONSTANT double *csF = cs + 2 * ((int64_t)F * K + w * K0);
 #pragma unroll
-            for (int g = 0; g < K0 / G; ++g) {
+            for (int g = 0; g < NG; ++g) {
                 // address of the group after next (crossing into the next front)
                 const int gg = g + 2;
-                const CONSTANT double *pn = csF + (gg < K0 / G ? 2 * G * gg : 2 * K + 2 * G * (gg - K0 / G));
+                const CONSTANT double *pn = csF + (gg < NG ? 2 * G * gg : 2 * K + 2 * G * (gg - NG));
                 asm volatile("" : "+s"(pn));
 #pragma unroll
                 for (int q = 0; q < G; ++q) {
@@ -489,6 +503,7 @@ __device__ __forceinline__ void sweep(GLOBAL double *__restrict__ X, int ld, int
                 for (int j = -3 * (K0 - 1); j <= 3; ++j) asm volatile("" : "+v"(buf[r][pmod(3 * phi + j, WSZ)]));
         }
     }
+    idle(nchunk - (live_end > w ? live_end : w));
 }
 
 // Spike rotations on Q columns (j-1, j), j = m..n+2, for one row: a running
