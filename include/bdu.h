@@ -37,6 +37,7 @@ extern "C" {
 #endif
 
 typedef struct bdu_ctx *bdu_handle;
+typedef struct bdu_batch_ctx *bdu_batch;
 
 enum {
     BDU_OK = 0,
@@ -63,10 +64,33 @@ int bdu_update(bdu_handle h, const double *B, const double *C, int r);
 
 /* Same as bdu_update on each handle in turn (results are bit-identical to
  * that loop), but every stage of every handle is issued as one launch over
- * all handles.  Handles must be distinct and share no stream requirement; the
- * work runs on the first handle's stream.  rs[i] >= 1. */
+ * all handles (one per applier tiling present).  Handles must be distinct
+ * (else BDU_EINVAL); shapes may differ.  The work runs on the first handle's
+ * stream and the call returns when it is done.  rs[i] >= 1. */
 int bdu_update_batched(const bdu_handle *hs, const double *const *Bs,
                        const double *const *Cs, const int *rs, int count);
+
+/* Batches: the batched form of the update for a fixed set of streams
+ * updated step after step (the many-stream use of Section 3.4's update).
+ * bdu_batch_create takes `count` distinct handles (shapes may differ) and the
+ * largest rank a step will carry; the batch keeps the handles, builds the
+ * launch lists once and owns a HIP stream.  bdu_batch_update queues one step:
+ * handle i takes the rank-rs[i] update B_i C_i^T (0 <= rs[i] <= max_rank;
+ * 0 = no update this step; Bs[i], Cs[i] host or device as in bdu_update).
+ * Results are bit-identical to bdu_update on each handle.  From the second
+ * step on, a step's launches are captured once in a HIP graph and replayed
+ * (not while stage timing is on).  The call returns once host inputs are
+ * consumed; bdu_batch_sync waits for the batch stream.  Later calls on a
+ * member handle are ordered after the batch's last step.  The handles must
+ * outlive the batch, and must not be destroyed or used by another thread
+ * while a step is being queued.  bdu_batch_info fills out[5] = {handles,
+ * max_rank, launch groups, graph captured (0/1), steps queued}. */
+int bdu_batch_create(const bdu_handle *hs, int count, int max_rank, bdu_batch *out);
+int bdu_batch_update(bdu_batch b, const double *const *Bs, const double *const *Cs,
+                     const int *rs);
+int bdu_batch_sync(bdu_batch b);
+int bdu_batch_info(bdu_batch b, int64_t *out);
+int bdu_batch_destroy(bdu_batch b);
 
 /* One rank-1 pass from already projected vectors u = Q^T b (m doubles) and
  * v = P^T c (n doubles) (eq. bidiagsubproblem, the right-hand side).  Useful

@@ -63,10 +63,16 @@ def lib():
         L.bdu_timing_read.argtypes = [vp, vp]
         L.bdu_plan_rotations.argtypes = [i64, i64, vp, vp, vp, vp, i64]
         L.bdu_plan_rotations.restype = i64
+        L.bdu_batch_create.argtypes = [ctypes.POINTER(vp), i32, i32, ctypes.POINTER(vp)]
+        L.bdu_batch_update.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i32)]
+        L.bdu_batch_sync.argtypes = [vp]
+        L.bdu_batch_info.argtypes = [vp, ctypes.POINTER(i64)]
+        L.bdu_batch_destroy.argtypes = [vp]
         for f in ("bdu_create", "bdu_update", "bdu_update_batched", "bdu_update_projected", "bdu_project",
                   "bdu_read", "bdu_set_stream", "bdu_sync", "bdu_destroy", "bdu_set_tiling",
                   "bdu_get_tiling", "bdu_plan_stats", "bdu_givens_device", "bdu_timing_enable",
-                  "bdu_timing_read"):
+                  "bdu_timing_read", "bdu_batch_create", "bdu_batch_update", "bdu_batch_sync",
+                  "bdu_batch_info", "bdu_batch_destroy"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -239,3 +245,43 @@ def update_batched(handles, Bs, Cs) -> None:
     cp = (ctypes.c_void_p * n)(*[_ptr(C, True) for C in Cs])
     rs = (ctypes.c_int * n)(*[1 if B.ndim == 1 else B.shape[1] for B in Bs])
     _check(lib().bdu_update_batched(hp, bp, cp, rs, n), "bdu_update_batched")
+
+
+class Batch:
+    """bdu_batch: a fixed set of distinct handles updated together, step after step."""
+
+    def __init__(self, handles, max_rank: int = 1):
+        n = len(handles)
+        self.handles = list(handles)  # the batch keeps them alive
+        hp = (ctypes.c_void_p * n)(*[h.ptr.value for h in handles])
+        b = ctypes.c_void_p()
+        _check(lib().bdu_batch_create(hp, n, max_rank, ctypes.byref(b)), "bdu_batch_create")
+        self._b = b
+
+    def update(self, Bs, Cs, ranks=None) -> None:
+        """Bs[i] is m_i x r_i (or a vector for r_i = 1), None for no update of handle i."""
+        n = len(self.handles)
+        rs = ranks if ranks is not None else [0 if B is None else (1 if B.ndim == 1 else B.shape[1]) for B in Bs]
+        bp = (ctypes.c_void_p * n)(*[None if B is None else _ptr(B, True) for B in Bs])
+        cp = (ctypes.c_void_p * n)(*[None if C is None else _ptr(C, True) for C in Cs])
+        ra = (ctypes.c_int * n)(*rs)
+        _check(lib().bdu_batch_update(self._b, bp, cp, ra), "bdu_batch_update")
+
+    def sync(self) -> None:
+        _check(lib().bdu_batch_sync(self._b), "bdu_batch_sync")
+
+    def info(self) -> dict:
+        out = (ctypes.c_int64 * 5)()
+        _check(lib().bdu_batch_info(self._b, out), "bdu_batch_info")
+        return dict(zip(["handles", "max_rank", "groups", "graph", "steps"], list(out)))
+
+    def close(self) -> None:
+        if self._b:
+            lib().bdu_batch_destroy(self._b)
+            self._b = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -13,6 +13,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <set>
 #include <tuple>
 #include <vector>
 
@@ -100,6 +101,12 @@ hipEvent_t pool_get()
     return e;
 }
 
+bool timing_on()
+{
+    std::lock_guard<std::mutex> lk(g_tmu);
+    return g_timing;
+}
+
 // Launch `fn` as stage `stage` on stream st, timed when timing is on.
 template <typename Fn>
 hipError_t timed(int stage, hipStream_t st, Fn fn)
@@ -138,6 +145,8 @@ struct bdu_ctx {
     int rcap = 0;
     int rpl = 1;  // rows per lane in the applier
     bool lds_gen = true;
+    hipEvent_t ev = nullptr;   // marks this handle's own stream work for a batch to wait on
+    hipEvent_t dep = nullptr;  // completion of the last batch step this handle was in
     std::vector<void *> allocs;
 };
 
@@ -151,6 +160,12 @@ namespace {
             return BDU_EDEVICE;              \
         }                                    \
     } while (0)
+
+// Order the handle's stream after the last batch step that updated it.
+hipError_t wait_dep(bdu_ctx *h)
+{
+    return h->dep ? hipStreamWaitEvent(h->stream, h->dep, 0) : hipSuccess;
+}
 
 template <typename T>
 hipError_t dalloc(bdu_ctx *h, T **p, int64_t count)
@@ -234,13 +249,13 @@ int ensure_rcap(bdu_ctx *h, int r)
 // Rotation stages of one pass (spike, generation, application) for `count`
 // handles listed in the device array hs (all with the same tiling).
 hipError_t run_rotation_stages(HandleDev *const *hs, int count, bool any_spike, int64_t lds_bytes,
-                               bool in_lds, int max_panels, int k0, int nw, int rpl, hipStream_t st)
+                               bool in_lds, int max_panels, int k0, int nw, int rpl, Gate gate, hipStream_t st)
 {
     hipError_t e = hipSuccess;
-    if (any_spike) e = timed(ST_SPIKE, st, [&] { return launch_spike(hs, count, st); });
-    if (e == hipSuccess) e = timed(ST_GEN, st, [&] { return launch_gen(hs, count, lds_bytes, in_lds, st); });
+    if (any_spike) e = timed(ST_SPIKE, st, [&] { return launch_spike(hs, count, gate, st); });
+    if (e == hipSuccess) e = timed(ST_GEN, st, [&] { return launch_gen(hs, count, lds_bytes, in_lds, gate, st); });
     if (e == hipSuccess)
-        e = timed(ST_APPLY, st, [&] { return launch_apply(hs, count, max_panels, k0, nw, rpl, st); });
+        e = timed(ST_APPLY, st, [&] { return launch_apply(hs, count, max_panels, k0, nw, rpl, gate, st); });
     return e;
 }
 
@@ -255,10 +270,11 @@ int pass_single(bdu_ctx *h, int pass, bool project)
 {
     hipError_t e = hipSuccess;
     if (project)
-        e = timed(ST_PROJECT, h->stream, [&] { return launch_project(h->d_self, 1, tiles_of(h), pass, h->stream); });
+        e = timed(ST_PROJECT, h->stream,
+                  [&] { return launch_project(h->d_self, 1, tiles_of(h), Gate{nullptr, pass}, h->stream); });
     if (e == hipSuccess)
         e = run_rotation_stages(h->d_self, 1, h->m > h->n, gen_lds_bytes(h->n, h->plan->N), h->lds_gen,
-                                panels_of(h), h->plan->K0, h->plan->NW, h->rpl, h->stream);
+                                panels_of(h), h->plan->K0, h->plan->NW, h->rpl, Gate{nullptr, pass}, h->stream);
     if (e != hipSuccess) {
         h->poisoned = true;
         return BDU_EDEVICE;
@@ -275,6 +291,133 @@ int64_t slot_of(const Plan &P, const GenChain &g, const Rot &r)
     const int lam0 = lam0_of_pair(ph, bd.base, r.i);
     const int pos = front_order(2 * (ph - 1) + r.side, P.K, P.K0).pos[tl];
     return bd.off + (int64_t)(lam0 / 3 + tl + w * P.S) * P.K + w * P.K0 + pos;
+}
+
+}  // namespace
+
+// A fixed set of distinct handles updated together (see bdu_batch_create).
+struct bdu_batch_ctx {
+    std::vector<bdu_ctx *> hs;  // caller's order
+    std::vector<int> pos;       // position of hs[i] in the launch arrays
+    int maxr = 1;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    struct Group {
+        int k0, nw, rpl;
+        bool spike, in_lds;
+        int64_t lds;
+        int tiles, panels, off, cnt;
+    };
+    std::vector<Group> groups;  // handles of one applier tiling, contiguous in the arrays
+    HandleDev **d_ptrs = nullptr;
+    int32_t *d_ranks = nullptr;
+    int32_t *h_ranks = nullptr;  // pinned staging of the ranks
+    hipEvent_t ranks_copied = nullptr, done = nullptr;
+    bool use_graph = false;
+    int64_t steps = 0;
+    hipGraphExec_t exec = nullptr;
+    bool poisoned = false;
+};
+
+namespace {
+
+void batch_free(bdu_batch b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->d_ptrs) (void)hipFree(b->d_ptrs);
+    if (b->d_ranks) (void)hipFree(b->d_ranks);
+    if (b->h_ranks) (void)hipHostFree(b->h_ranks);
+    if (b->ranks_copied) (void)hipEventDestroy(b->ranks_copied);
+    if (b->done) (void)hipEventDestroy(b->done);
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+int batch_build(const bdu_handle *hs, int count, int maxr, bool graph, bdu_batch *out)
+{
+    if (!hs || count < 1 || maxr < 1) return BDU_EINVAL;
+    std::set<bdu_ctx *> seen;
+    for (int i = 0; i < count; ++i) {
+        if (!hs[i] || !seen.insert(hs[i]).second) return BDU_EINVAL;  // NULL or repeated handle
+        if (hs[i]->poisoned) return BDU_EDEVICE;
+    }
+    for (int i = 0; i < count; ++i) {
+        int s = ensure_rcap(hs[i], maxr);
+        if (s != BDU_OK) return s;
+    }
+    auto b = new bdu_batch_ctx;
+    b->hs.assign(hs, hs + count);
+    b->maxr = maxr;
+    b->use_graph = graph;
+    hipError_t e = hipSuccess;
+    if (graph) {
+        e = hipStreamCreate(&b->stream);
+        b->own_stream = e == hipSuccess;
+    } else {
+        b->stream = hs[0]->stream;
+    }
+    // group by tiling (and generation placement)
+    std::vector<std::vector<int>> members;
+    for (int i = 0; i < count; ++i) {
+        bdu_ctx *h = hs[i];
+        size_t g = 0;
+        for (; g < b->groups.size(); ++g) {
+            auto &x = b->groups[g];
+            if (x.k0 == h->plan->K0 && x.nw == h->plan->NW && x.rpl == h->rpl && x.in_lds == h->lds_gen) break;
+        }
+        if (g == b->groups.size()) {
+            b->groups.push_back({h->plan->K0, h->plan->NW, h->rpl, false, h->lds_gen, 0, 0, 0, 0, 0});
+            members.emplace_back();
+        }
+        auto &x = b->groups[g];
+        members[g].push_back(i);
+        x.spike |= h->m > h->n;
+        x.lds = std::max<int64_t>(x.lds, gen_lds_bytes(h->n, h->plan->N));
+        x.tiles = std::max(x.tiles, tiles_of(h));
+        x.panels = std::max(x.panels, panels_of(h));
+    }
+    std::vector<HandleDev *> flat;
+    b->pos.assign(count, 0);
+    for (size_t g = 0; g < b->groups.size(); ++g) {
+        b->groups[g].off = (int)flat.size();
+        b->groups[g].cnt = (int)members[g].size();
+        for (int i : members[g]) {
+            b->pos[i] = (int)flat.size();
+            flat.push_back(hs[i]->d_hd);
+        }
+    }
+    if (e == hipSuccess) e = hipMalloc(&b->d_ptrs, sizeof(HandleDev *) * count);
+    if (e == hipSuccess) e = hipMalloc(&b->d_ranks, sizeof(int32_t) * count);
+    if (e == hipSuccess) e = hipHostMalloc(&b->h_ranks, sizeof(int32_t) * count, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ranks_copied, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
+    if (e == hipSuccess) e = prepare_kernels();
+    if (e == hipSuccess) e = hipMemcpy(b->d_ptrs, flat.data(), sizeof(HandleDev *) * count, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        batch_free(b);
+        return e == hipErrorOutOfMemory ? BDU_ENOMEM : BDU_EDEVICE;
+    }
+    *out = b;
+    return BDU_OK;
+}
+
+// One step's launches: for each pass, every tiling group (handles whose rank
+// this step is at most the pass leave at once).
+hipError_t batch_launch(bdu_batch b)
+{
+    hipStream_t st = b->stream;
+    for (int p = 0; p < b->maxr; ++p) {
+        for (auto &g : b->groups) {
+            HandleDev **arr = b->d_ptrs + g.off;
+            const Gate gate{b->d_ranks + g.off, p};
+            hipError_t e = timed(ST_PROJECT, st, [&] { return launch_project(arr, g.cnt, g.tiles, gate, st); });
+            if (e == hipSuccess)
+                e = run_rotation_stages(arr, g.cnt, g.spike, g.lds, g.in_lds, g.panels, g.k0, g.nw, g.rpl, gate, st);
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
 }
 
 }  // namespace
@@ -400,6 +543,10 @@ int bdu_create(int64_t m, int64_t n, const double *Q, const double *d, const dou
     HandleDev *self = h->d_hd;
     HIPCHK(hp, hipMemcpyAsync(h->d_self, &self, sizeof(self), hipMemcpyHostToDevice, hp->stream));
     HIPCHK(hp, hipStreamSynchronize(hp->stream));
+    if (hipEventCreateWithFlags(&hp->ev, hipEventDisableTiming) != hipSuccess) {
+        for (void *p : h->allocs) (void)hipFree(p);
+        return BDU_EDEVICE;
+    }
     *out = h.release();
     return BDU_OK;
 }
@@ -408,6 +555,7 @@ int bdu_set_stream(bdu_handle h, void *stream)
 {
     if (!h) return BDU_EINVAL;
     if (h->poisoned) return BDU_EDEVICE;
+    HIPCHK(h, wait_dep(h));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     h->stream = (hipStream_t)stream;
     return BDU_OK;
@@ -417,6 +565,7 @@ int bdu_sync(bdu_handle h)
 {
     if (!h) return BDU_EINVAL;
     if (h->poisoned) return BDU_EDEVICE;
+    HIPCHK(h, wait_dep(h));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     return BDU_OK;
 }
@@ -425,6 +574,7 @@ int bdu_update(bdu_handle h, const double *B, const double *C, int r)
 {
     if (!h || !B || !C || r < 1) return BDU_EINVAL;
     if (h->poisoned) return BDU_EDEVICE;
+    HIPCHK(h, wait_dep(h));
     int st = ensure_rcap(h, r);
     if (st != BDU_OK) return st;
     HIPCHK(h, copy_in(h->hd.bst, B, sizeof(double) * h->m * r, h->stream));
@@ -440,6 +590,7 @@ int bdu_update_projected(bdu_handle h, const double *u, const double *v)
 {
     if (!h || !u || !v) return BDU_EINVAL;
     if (h->poisoned) return BDU_EDEVICE;
+    HIPCHK(h, wait_dep(h));
     HIPCHK(h, copy_in(h->hd.u, u, sizeof(double) * h->m, h->stream));
     HIPCHK(h, copy_in(h->hd.v, v, sizeof(double) * h->n, h->stream));
     return pass_single(h, 0, false);
@@ -449,9 +600,10 @@ int bdu_project(bdu_handle h, const double *b, const double *c, double *u, doubl
 {
     if (!h || !b || !c) return BDU_EINVAL;
     if (h->poisoned) return BDU_EDEVICE;
+    HIPCHK(h, wait_dep(h));
     HIPCHK(h, copy_in(h->hd.bst, b, sizeof(double) * h->m, h->stream));
     HIPCHK(h, copy_in(h->hd.cst, c, sizeof(double) * h->n, h->stream));
-    HIPCHK(h, launch_project(h->d_self, 1, tiles_of(h), 0, h->stream));
+    HIPCHK(h, launch_project(h->d_self, 1, tiles_of(h), Gate{nullptr, 0}, h->stream));
     HIPCHK(h, copy_out(u, h->hd.u, sizeof(double) * h->m, h->stream));
     HIPCHK(h, copy_out(v, h->hd.v, sizeof(double) * h->n, h->stream));
     return BDU_OK;
@@ -461,6 +613,7 @@ int bdu_read(bdu_handle h, double *Q, double *d, double *e, double *P)
 {
     if (!h) return BDU_EINVAL;
     if (h->poisoned) return BDU_EDEVICE;
+    HIPCHK(h, wait_dep(h));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     HIPCHK(h, copy_mat_out(Q, h->hd.Q, h->hd.ldq, h->m, h->m, h->stream));
     HIPCHK(h, copy_out(d, h->hd.d, sizeof(double) * h->n, h->stream));
@@ -473,6 +626,7 @@ int64_t bdu_last_rotations(bdu_handle h, int32_t *side, int64_t *idx, double *c,
 {
     if (!h) return BDU_EINVAL;
     if (h->poisoned) return BDU_EDEVICE;
+    HIPCHK(h, wait_dep(h));
     const Plan &P = *h->plan;
     std::vector<double2> L(P.slots[0]), R(P.slots[1]), Sp(std::max<int64_t>(P.nspike, 1));
     HIPCHK(h, hipStreamSynchronize(h->stream));
@@ -505,8 +659,10 @@ int64_t bdu_last_rotations(bdu_handle h, int32_t *side, int64_t *idx, double *c,
 int bdu_destroy(bdu_handle h)
 {
     if (!h) return BDU_EINVAL;
+    (void)wait_dep(h);
     (void)hipStreamSynchronize(h->stream);
     for (void *p : h->allocs) (void)hipFree(p);
+    if (h->ev) (void)hipEventDestroy(h->ev);
     delete h;
     return BDU_OK;
 }
@@ -515,79 +671,112 @@ int bdu_update_batched(const bdu_handle *hs, const double *const *Bs, const doub
                        int count)
 {
     if (!hs || !Bs || !Cs || !rs || count < 1) return BDU_EINVAL;
-    for (int i = 0; i < count; ++i) {
-        if (!hs[i] || !Bs[i] || !Cs[i] || rs[i] < 1) return BDU_EINVAL;
-        if (hs[i]->poisoned) return BDU_EDEVICE;
-        for (int j = 0; j < i; ++j)
-            if (hs[j] == hs[i]) return BDU_EINVAL;
-    }
-    hipStream_t st = hs[0]->stream;
     int maxr = 0;
     for (int i = 0; i < count; ++i) {
-        bdu_ctx *h = hs[i];
-        int s = ensure_rcap(h, rs[i]);
-        if (s != BDU_OK) return s;
-        if (h->stream != st) HIPCHK(h, hipStreamSynchronize(h->stream));
-        HIPCHK(h, copy_in(h->hd.bst, Bs[i], sizeof(double) * h->m * rs[i], st));
-        HIPCHK(h, copy_in(h->hd.cst, Cs[i], sizeof(double) * h->n * rs[i], st));
+        if (rs[i] < 1) return BDU_EINVAL;
         maxr = std::max(maxr, rs[i]);
     }
-    // Per pass: the handles still active, grouped by tiling.
-    struct Group {
-        int k0, nw, rpl;
-        std::vector<HandleDev *> ptrs;
-        bool spike = false, in_lds = true;
-        int64_t lds = 0;
-        int tiles = 0, panels = 0;
+    bdu_batch b = nullptr;
+    int st = batch_build(hs, count, maxr, false, &b);
+    if (st != BDU_OK) return st;
+    st = bdu_batch_update(b, Bs, Cs, rs);
+    if (st == BDU_OK) st = bdu_batch_sync(b);
+    int st2 = bdu_batch_destroy(b);
+    return st != BDU_OK ? st : st2;
+}
+
+int bdu_batch_create(const bdu_handle *hs, int count, int max_rank, bdu_batch *out)
+{
+    if (!out) return BDU_EINVAL;
+    *out = nullptr;
+    return batch_build(hs, count, max_rank, true, out);
+}
+
+int bdu_batch_update(bdu_batch b, const double *const *Bs, const double *const *Cs, const int *rs)
+{
+    if (!b || !rs) return BDU_EINVAL;
+    if (b->poisoned) return BDU_EDEVICE;
+    const int count = (int)b->hs.size();
+    for (int i = 0; i < count; ++i) {
+        if (rs[i] < 0 || rs[i] > b->maxr) return BDU_EINVAL;
+        if (rs[i] > 0 && (!Bs || !Cs || !Bs[i] || !Cs[i])) return BDU_EINVAL;
+        if (b->hs[i]->poisoned) return BDU_EDEVICE;
+    }
+    hipStream_t st = b->stream;
+    auto fail = [&]() {
+        b->poisoned = true;
+        for (bdu_ctx *h : b->hs) h->poisoned = true;
+        return BDU_EDEVICE;
     };
-    std::vector<std::vector<Group>> passes(maxr);
-    size_t total = 0;
-    for (int p = 0; p < maxr; ++p) {
-        for (int i = 0; i < count; ++i) {
-            if (rs[i] <= p) continue;
-            bdu_ctx *h = hs[i];
-            Group *g = nullptr;
-            for (auto &x : passes[p])
-                if (x.k0 == h->plan->K0 && x.nw == h->plan->NW && x.rpl == h->rpl && x.in_lds == h->lds_gen)
-                    g = &x;
-            if (!g) {
-                passes[p].push_back(Group{h->plan->K0, h->plan->NW, h->rpl, {}, false, h->lds_gen, 0, 0, 0});
-                g = &passes[p].back();
-            }
-            g->ptrs.push_back(h->d_hd);
-            g->spike |= h->m > h->n;
-            g->lds = std::max<int64_t>(g->lds, gen_lds_bytes(h->n, h->plan->N));
-            g->tiles = std::max(g->tiles, tiles_of(h));
-            g->panels = std::max(g->panels, panels_of(h));
+    // inputs, in stream order after each handle's own work
+    for (int i = 0; i < count; ++i) {
+        bdu_ctx *h = b->hs[i];
+        if (h->stream != st) {
+            if (hipEventRecord(h->ev, h->stream) != hipSuccess || hipStreamWaitEvent(st, h->ev, 0) != hipSuccess)
+                return fail();
         }
-        for (auto &g : passes[p]) total += g.ptrs.size();
+        if (rs[i] == 0) continue;
+        if (copy_in(h->hd.bst, Bs[i], sizeof(double) * h->m * rs[i], st) != hipSuccess ||
+            copy_in(h->hd.cst, Cs[i], sizeof(double) * h->n * rs[i], st) != hipSuccess)
+            return fail();
     }
-    std::vector<HandleDev *> flat;
-    flat.reserve(total);
-    for (auto &pp : passes)
-        for (auto &g : pp) flat.insert(flat.end(), g.ptrs.begin(), g.ptrs.end());
-    HandleDev **d_arr = nullptr;
-    if (hipMalloc(&d_arr, sizeof(HandleDev *) * total) != hipSuccess) return BDU_ENOMEM;
-    hipError_t e = hipMemcpyAsync(d_arr, flat.data(), sizeof(HandleDev *) * total, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    size_t off = 0;
-    for (int p = 0; p < maxr && e == hipSuccess; ++p) {
-        for (auto &g : passes[p]) {
-            HandleDev **arr = d_arr + off;
-            int cnt = (int)g.ptrs.size();
-            e = timed(ST_PROJECT, st, [&] { return launch_project(arr, cnt, g.tiles, p, st); });
-            if (e == hipSuccess)
-                e = run_rotation_stages(arr, cnt, g.spike, g.lds, g.in_lds, g.panels, g.k0, g.nw, g.rpl, st);
-            off += cnt;
-            if (e != hipSuccess) break;
+    // this step's ranks (the pinned staging is reused once the last copy is done)
+    if (b->steps > 0 && hipEventSynchronize(b->ranks_copied) != hipSuccess) return fail();
+    for (int i = 0; i < count; ++i) b->h_ranks[b->pos[i]] = rs[i];
+    if (hipMemcpyAsync(b->d_ranks, b->h_ranks, sizeof(int32_t) * count, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipEventRecord(b->ranks_copied, st) != hipSuccess)
+        return fail();
+    hipError_t e = hipSuccess;
+    const bool graph_now = b->use_graph && !timing_on() && b->steps > 0;
+    if (graph_now && !b->exec) {
+        // capture one step's launches once; every later step replays them
+        e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t el = batch_launch(b);
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(st, &g);
+            if (el != hipSuccess) e = el;
+            if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+            if (g) (void)hipGraphDestroy(g);
         }
+        if (e != hipSuccess) return fail();
     }
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    (void)hipFree(d_arr);
-    if (e != hipSuccess) {
-        for (int i = 0; i < count; ++i) hs[i]->poisoned = true;
+    e = graph_now ? hipGraphLaunch(b->exec, st) : batch_launch(b);
+    if (e != hipSuccess || hipEventRecord(b->done, st) != hipSuccess) return fail();
+    for (bdu_ctx *h : b->hs) h->dep = b->done;
+    ++b->steps;
+    return BDU_OK;
+}
+
+int bdu_batch_sync(bdu_batch b)
+{
+    if (!b) return BDU_EINVAL;
+    if (b->poisoned) return BDU_EDEVICE;
+    if (hipStreamSynchronize(b->stream) != hipSuccess) {
+        b->poisoned = true;
         return BDU_EDEVICE;
     }
+    return BDU_OK;
+}
+
+int bdu_batch_info(bdu_batch b, int64_t *out)
+{
+    if (!b || !out) return BDU_EINVAL;
+    out[0] = (int64_t)b->hs.size();
+    out[1] = b->maxr;
+    out[2] = (int64_t)b->groups.size();
+    out[3] = b->exec != nullptr;
+    out[4] = b->steps;
+    return BDU_OK;
+}
+
+int bdu_batch_destroy(bdu_batch b)
+{
+    if (!b) return BDU_EINVAL;
+    (void)hipStreamSynchronize(b->stream);
+    for (bdu_ctx *h : b->hs)
+        if (h->dep == b->done) h->dep = nullptr;
+    batch_free(b);
     return BDU_OK;
 }
 

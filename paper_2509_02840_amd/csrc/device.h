@@ -10,7 +10,7 @@ namespace bdu {
 
 // Everything a kernel needs to update one factorization A = Q Bd P^T.
 // Q is m x m and P is n x n, column-major; their leading dimensions ldq, ldp
-// are m and n rounded up to a multiple of 64 (the padding rows are zero).
+// are m and n rounded up to a multiple of 128 (the padding rows are zero).
 struct HandleDev {
     double *Q, *P, *d, *e;
     double *u, *v;          // projections u = Q^T b (m), v = P^T c (n)
@@ -24,6 +24,14 @@ struct HandleDev {
     int32_t m, n, N, nchains, nb1, nb2;
     int32_t ldq, ldp;
     int32_t K0, NW, K, S;
+};
+
+// Per-launch gate of a batch in which streams take different ranks: the
+// handle at position i of a launch takes part in pass `pass` only if
+// pass < ranks[i] (ranks == nullptr: every handle takes part).
+struct Gate {
+    const int32_t *ranks;
+    int32_t pass;
 };
 
 constexpr int kGenThreads = 256;

@@ -101,8 +101,10 @@ __device__ __forceinline__ void rot(double c, double s, double &x, double &y)
 
 // grid (tiles, handles), 64 threads.  Tile t < ceil(m/64) projects with Q,
 // the rest with P.  Lane l of tile t owns output column 64 t + l.
-__global__ __launch_bounds__(64) void project_kernel(HandleDev *const *hs, int pass)
+__global__ __launch_bounds__(64) void project_kernel(HandleDev *const *hs, Gate gate)
 {
+    if (gate.ranks && gate.pass >= gate.ranks[blockIdx.y]) return;
+    const int pass = gate.pass;
     const CONSTANT HandleDev *h = kptr(hs[blockIdx.y]);
     const int m = h->m, n = h->n;
     const int qt = (m + 63) / 64, pt = (n + 63) / 64;
@@ -146,8 +148,9 @@ __global__ __launch_bounds__(64) void project_kernel(HandleDev *const *hs, int p
 // grid (handles), 64 threads.  For j = m..n+2 the pair (u_{j-1}, u_j) is
 // rotated onto u_{j-1} (mode 2).  Rows n+1.. of the band are zero, so only u
 // and the rotation list change.
-__global__ __launch_bounds__(64) void spike_kernel(HandleDev *const *hs)
+__global__ __launch_bounds__(64) void spike_kernel(HandleDev *const *hs, Gate gate)
 {
+    if (gate.ranks && gate.pass >= gate.ranks[blockIdx.x]) return;
     const CONSTANT HandleDev *h = kptr(hs[blockIdx.x]);
     if (h->m <= h->n) return;
     const int m = h->m, n = h->n;
@@ -220,9 +223,10 @@ __device__ __forceinline__ ChainReg load_chain(const GenChain *chains, int idx)
 // (i, i+1) rotates the band pairs in columns i-2..i+4, a right rotation on
 // columns (j, j+1) those in rows j-3..j+3, plus the matching u or v pair.
 template <bool IN_LDS>
-__global__ __launch_bounds__(kGenThreads) void gen_kernel(HandleDev *const *hs)
+__global__ __launch_bounds__(kGenThreads) void gen_kernel(HandleDev *const *hs, Gate gate)
 {
     extern __shared__ double smem[];
+    if (gate.ranks && gate.pass >= gate.ranks[blockIdx.x]) return;
     const CONSTANT HandleDev *h = kptr(hs[blockIdx.x]);
     const int n = h->n, N = h->N;
     double *S = IN_LDS ? smem : h->band;
@@ -530,7 +534,7 @@ __device__ void spike_apply(GLOBAL double *Q, int ld, int m, int n, int row, con
 // spilling; the smaller windows fit three).
 template <int K0, int NW, int R>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(K0 * R >= 24 ? 2 : 3))) void apply_kernel(
-    HandleDev *const *hs)
+    HandleDev *const *hs, Gate gate)
 {
     // Workgroups are dispatched round-robin over the 8 XCDs.  Renumber them so
     // that the panels of one handle run on the same XCD and share its L2 copy
@@ -540,6 +544,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(K0 * R 
     int item = lin;
     if (total % 8 == 0) item = (lin % 8) * (total / 8) + lin / 8;
     const int hidx = item / gridDim.x, pid = item % gridDim.x;
+    if (gate.ranks && gate.pass >= gate.ranks[hidx]) return;
     const CONSTANT HandleDev *h = kptr(hs[hidx]);
     const int m = h->m, n = h->n;
     constexpr int PH = 64 * R;
@@ -621,39 +626,46 @@ __global__ void fill_identity_kernel(double2 *p, int64_t count)
 
 // ---- launchers ---------------------------------------------------------------------
 
-hipError_t launch_project(HandleDev *const *hs, int count, int max_tiles, int pass, hipStream_t st)
+hipError_t launch_project(HandleDev *const *hs, int count, int max_tiles, Gate gate, hipStream_t st)
 {
-    hipLaunchKernelGGL(project_kernel, dim3(max_tiles, count), dim3(64), 0, st, hs, pass);
+    hipLaunchKernelGGL(project_kernel, dim3(max_tiles, count), dim3(64), 0, st, hs, gate);
     return hipGetLastError();
 }
 
-hipError_t launch_spike(HandleDev *const *hs, int count, hipStream_t st)
+hipError_t launch_spike(HandleDev *const *hs, int count, Gate gate, hipStream_t st)
 {
-    hipLaunchKernelGGL(spike_kernel, dim3(count), dim3(64), 0, st, hs);
+    hipLaunchKernelGGL(spike_kernel, dim3(count), dim3(64), 0, st, hs, gate);
     return hipGetLastError();
 }
 
-hipError_t launch_gen(HandleDev *const *hs, int count, int64_t lds_bytes, bool in_lds, hipStream_t st)
+hipError_t prepare_kernels()
+{
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)gen_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)kMaxGenLds);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_gen(HandleDev *const *hs, int count, int64_t lds_bytes, bool in_lds, Gate gate, hipStream_t st)
 {
     if (in_lds) {
-        static bool attr = false;
-        if (!attr) {
-            hipError_t e = hipFuncSetAttribute((const void *)gen_kernel<true>,
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxGenLds);
-            if (e != hipSuccess) return e;
-            attr = true;
-        }
-        hipLaunchKernelGGL(gen_kernel<true>, dim3(count), dim3(kGenThreads), (size_t)lds_bytes, st, hs);
+        hipError_t e = prepare_kernels();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(gen_kernel<true>, dim3(count), dim3(kGenThreads), (size_t)lds_bytes, st, hs, gate);
     } else {
-        hipLaunchKernelGGL(gen_kernel<false>, dim3(count), dim3(kGenThreads), 0, st, hs);
+        hipLaunchKernelGGL(gen_kernel<false>, dim3(count), dim3(kGenThreads), 0, st, hs, gate);
     }
     return hipGetLastError();
 }
 
 template <int K0, int NW, int R>
-static hipError_t launch_apply_t(HandleDev *const *hs, int count, int max_panels, hipStream_t st)
+static hipError_t launch_apply_t(HandleDev *const *hs, int count, int max_panels, Gate gate, hipStream_t st)
 {
-    hipLaunchKernelGGL((apply_kernel<K0, NW, R>), dim3(max_panels, count), dim3(64 * NW), 0, st, hs);
+    hipLaunchKernelGGL((apply_kernel<K0, NW, R>), dim3(max_panels, count), dim3(64 * NW), 0, st, hs, gate);
     return hipGetLastError();
 }
 
@@ -663,10 +675,11 @@ bool tiling_supported(int k0, int nw, int rpl)
     return (k0 == 6 || k0 == 12) && (nw == 1 || nw == 2 || nw == 4 || nw == 8) && (rpl == 1 || rpl == 2);
 }
 
-hipError_t launch_apply(HandleDev *const *hs, int count, int max_panels, int k0, int nw, int rpl, hipStream_t st)
+hipError_t launch_apply(HandleDev *const *hs, int count, int max_panels, int k0, int nw, int rpl, Gate gate,
+                        hipStream_t st)
 {
 #define BDU_APPLY_CASE(A, B, C) \
-    if (k0 == A && nw == B && rpl == C) return launch_apply_t<A, B, C>(hs, count, max_panels, st);
+    if (k0 == A && nw == B && rpl == C) return launch_apply_t<A, B, C>(hs, count, max_panels, gate, st);
     BDU_APPLY_CASE(6, 1, 1) BDU_APPLY_CASE(6, 2, 1) BDU_APPLY_CASE(6, 4, 1) BDU_APPLY_CASE(6, 8, 1)
     BDU_APPLY_CASE(12, 1, 1) BDU_APPLY_CASE(12, 2, 1) BDU_APPLY_CASE(12, 4, 1) BDU_APPLY_CASE(12, 8, 1)
     BDU_APPLY_CASE(6, 1, 2) BDU_APPLY_CASE(6, 2, 2) BDU_APPLY_CASE(6, 4, 2)
