@@ -5,8 +5,10 @@ that size): Q0, P0 are Haar orthogonal (Householder-QR factors of N(0,1)
 matrices, signed-column-permuted per stream), d ~ U(1,10), e ~ U(0,1); every
 update is b ~ N(0,1)/sqrt(m), c ~ N(0,1)/sqrt(n).
 
-- batched (the reported value): S streams; one step is one rank-1 update of
-  every stream in one bdu_update_batched call.  value = S * steps / time.
+- batched (the reported value): S streams in one batch (bdu_batch_*); one
+  step is one rank-1 update of every stream, queued with one
+  bdu_batch_update call and waited for.  value = S * steps / time.  The
+  applier tiling is autotuned on S synthetic streams beforehand (untimed).
 - plain: one stream, one bdu_update per rank-1 update, timed beside it.
 
 A step runs the whole path: projection, generation, and accumulation into Q
@@ -143,7 +145,11 @@ def main() -> int:
     ap.add_argument("--plain-steps", type=int, default=20)
     ap.add_argument("--seed", type=int, default=5000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--tiling", type=str, default=None, help="applier tiling K0,NW,RPL (default: library default)")
+    ap.add_argument("--tiling", type=str, default=None,
+                    help="applier tiling K0,NW,RPL (default: autotuned for the batched workload)")
+    ap.add_argument("--no-autotune", action="store_true", help="use the library's default tiling")
+    ap.add_argument("--graph-steps", type=int, default=3,
+                    help="extra batched steps replayed as a HIP graph after the timed region")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy three times (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -160,9 +166,16 @@ def main() -> int:
     from paper_2509_02840_amd import bdu
 
     torch.cuda.set_device(0)
+    n = args.n
+    tune = None
     if args.tiling:
         bdu.set_tiling(*[int(x) for x in args.tiling.split(",")])
-    n = args.n
+    elif not args.no_autotune:
+        # untimed: every applier tiling on S synthetic streams of this shape
+        t0 = time.perf_counter()
+        tune = bdu.autotune(n, n, args.streams)
+        tune["seconds"] = time.perf_counter() - t0
+        bdu.set_tiling_auto()
     gen = torch.Generator(device="cuda:0")
     gen.manual_seed(args.seed)
 
@@ -198,28 +211,43 @@ def main() -> int:
         Q, d, e, P = factory.make()
         hs.append(bdu.Handle(Q, d, e, P))
         del Q, P
+    tiling = hs[0].tiling()
     torch.cuda.empty_cache()
     steps = args.warmup + args.steps
     ub = [make_updates(torch, gen, n, steps) for _ in range(S)]
+    batch = bdu.Batch(hs, max_rank=1)
+    step_inputs = lambda k: ([ub[s][0][k] for s in range(S)], [ub[s][1][k] for s in range(S)])
     torch.cuda.synchronize()
     for k in range(args.warmup):
-        bdu.update_batched(hs, [ub[s][0][k] for s in range(S)], [ub[s][1][k] for s in range(S)])
-    for x in hs:
-        x.sync()
+        batch.update(*step_inputs(k))
+    batch.sync()
+    # timed region: stage events bracket every launch, so the steps run as
+    # eager launches (events cannot sit between the nodes of a replayed graph)
     bdu.timing_enable(True)
     step_lat = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.warmup, steps):
         ta = time.perf_counter()
-        bdu.update_batched(hs, [ub[s][0][k] for s in range(S)], [ub[s][1][k] for s in range(S)])
+        batch.update(*step_inputs(k))
+        batch.sync()
         step_lat.append(time.perf_counter() - ta)
-    for x in hs:
-        x.sync()
     torch.cuda.synchronize()
     batched_time = time.perf_counter() - t0
     stages = bdu.timing_read()
     bdu.timing_enable(False)
+    # after the timed region: the same steps replayed as a HIP graph
+    graph_ms = None
+    if args.graph_steps > 0:
+        batch.update(*step_inputs(args.warmup))  # captures the graph
+        batch.sync()
+        tg = time.perf_counter()
+        for j in range(args.graph_steps):
+            batch.update(*step_inputs(args.warmup + j % args.steps))
+        batch.sync()
+        graph_ms = 1e3 * (time.perf_counter() - tg) / args.graph_steps
+        assert batch.info()["graph"] == 1
+    batch.close()
     for x in hs:
         x.close()
 
@@ -228,7 +256,7 @@ def main() -> int:
     avg_apply_s = apply_ms / 1e3 / max(apply_launches, 1)
     flops_per_launch = S * applier_flops(bdu, n, n)
     achieved = flops_per_launch / avg_apply_s / 1e12
-    k0, nw, rpl = bdu.get_tiling()
+    k0, nw, rpl = tiling
 
     out = {
         "metric": METRIC,
@@ -245,7 +273,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"batched BGU rank-1 updates, {S} square streams m=n={n}, "
                                f"one update per stream per step; plain = 1 stream",
-                   "m": n, "n": n, "streams": S, "rank": 1, "tiling": [k0, nw, rpl]},
+                   "m": n, "n": n, "streams": S, "rank": 1, "tiling": [k0, nw, rpl],
+                   "autotune": tune},
         "plain_updates_per_s": plain_ups,
         "batched_over_plain": value / plain_ups,
         "p50_ms": 1e3 * float(np.percentile(step_lat, 50)),
@@ -253,6 +282,7 @@ def main() -> int:
         "plain_p50_ms": 1e3 * float(np.percentile(lat, 50)),
         "plain_p99_ms": 1e3 * float(np.percentile(lat, 99)),
         "stage_ms_per_step": {k: v[0] / args.steps for k, v in stages.items()},
+        "graph_replay_ms_per_step": graph_ms,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
                      "traffic": measured_traffic(n, S, (k0, nw, rpl)),

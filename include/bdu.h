@@ -133,6 +133,23 @@ int64_t bdu_footprint_bytes(int64_t m, int64_t n);
 int bdu_set_tiling(int k0, int nw, int rpl);
 int bdu_get_tiling(int *k0, int *nw, int *rpl);
 
+/* Autotuning of the applier tiling (its panel width 64 * rpl rows and its
+ * block depth k0 * nw chains).  bdu_set_tiling(0, 0, 0) selects "auto": a
+ * handle created afterwards takes the tiling recorded for its shape (m, n),
+ * else the default.  bdu_autotune times every supported tiling on `streams`
+ * synthetic streams of shape (m, n) (Q = I, P = I; the applier's work does
+ * not depend on the values), one batched rank-1 step after another, records
+ * the fastest for (m, n) and returns out[4] = {k0, nw, rpl, microseconds per
+ * step}.  It allocates and frees about `streams` times bdu_footprint_bytes;
+ * tilings that do not fit are skipped (BDU_ENOMEM if none fits).
+ * bdu_tune_save / bdu_tune_load write / read the recorded table as text
+ * lines "m n k0 nw rpl us"; load returns the number of entries read.
+ * bdu_handle_tiling reports the tiling a handle was created with. */
+int bdu_autotune(int64_t m, int64_t n, int streams, int64_t *out);
+int bdu_tune_save(const char *path);
+int bdu_tune_load(const char *path);
+int bdu_handle_tiling(bdu_handle h, int *k0, int *nw, int *rpl);
+
 /* Stage timing.  bdu_timing_enable(1) clears the log and brackets every
  * later kernel launch with HIP events on the stream the kernel runs on;
  * bdu_timing_enable(0) stops it.  bdu_timing_read waits for the logged events

@@ -63,6 +63,10 @@ def lib():
         L.bdu_timing_read.argtypes = [vp, vp]
         L.bdu_plan_rotations.argtypes = [i64, i64, vp, vp, vp, vp, i64]
         L.bdu_plan_rotations.restype = i64
+        L.bdu_autotune.argtypes = [i64, i64, i32, ctypes.POINTER(i64)]
+        L.bdu_tune_save.argtypes = [ctypes.c_char_p]
+        L.bdu_tune_load.argtypes = [ctypes.c_char_p]
+        L.bdu_handle_tiling.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.bdu_batch_create.argtypes = [ctypes.POINTER(vp), i32, i32, ctypes.POINTER(vp)]
         L.bdu_batch_update.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i32)]
         L.bdu_batch_sync.argtypes = [vp]
@@ -72,7 +76,8 @@ def lib():
                   "bdu_read", "bdu_set_stream", "bdu_sync", "bdu_destroy", "bdu_set_tiling",
                   "bdu_get_tiling", "bdu_plan_stats", "bdu_givens_device", "bdu_timing_enable",
                   "bdu_timing_read", "bdu_batch_create", "bdu_batch_update", "bdu_batch_sync",
-                  "bdu_batch_info", "bdu_batch_destroy"):
+                  "bdu_batch_info", "bdu_batch_destroy", "bdu_autotune", "bdu_tune_save", "bdu_tune_load",
+                  "bdu_handle_tiling"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -114,6 +119,25 @@ def _ptr(a, matrix: bool = False):
 
 def set_tiling(k0: int, nw: int, rpl: int = 1) -> None:
     _check(lib().bdu_set_tiling(k0, nw, rpl), "bdu_set_tiling")
+
+
+def set_tiling_auto() -> None:
+    """Handles created afterwards take the tiling recorded for their shape by autotune / tune_load."""
+    _check(lib().bdu_set_tiling(0, 0, 0), "bdu_set_tiling")
+
+
+def autotune(m: int, n: int, streams: int) -> dict:
+    out = (ctypes.c_int64 * 4)()
+    _check(lib().bdu_autotune(m, n, streams, out), "bdu_autotune")
+    return {"k0": out[0], "nw": out[1], "rpl": out[2], "us_per_step": out[3]}
+
+
+def tune_save(path: str) -> None:
+    _check(lib().bdu_tune_save(path.encode()), "bdu_tune_save")
+
+
+def tune_load(path: str) -> int:
+    return _check(lib().bdu_tune_load(path.encode()), "bdu_tune_load")
 
 
 def get_tiling():
@@ -224,6 +248,12 @@ class Handle:
 
     def sync(self) -> None:
         _check(lib().bdu_sync(self._h), "bdu_sync")
+
+    def tiling(self):
+        k0, nw, rpl = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().bdu_handle_tiling(self._h, ctypes.byref(k0), ctypes.byref(nw), ctypes.byref(rpl)),
+               "bdu_handle_tiling")
+        return k0.value, nw.value, rpl.value
 
     def close(self) -> None:
         if self._h:

@@ -7,6 +7,7 @@
 #include "../../include/bdu.h"
 
 #include <hip/hip_runtime.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
@@ -26,7 +27,13 @@ using namespace bdu;
 namespace {
 
 std::mutex g_mu;
-int g_k0 = 12, g_nw = 8, g_rpl = 1;
+int g_k0 = 12, g_nw = 8, g_rpl = 1;  // 0, 0, 0: per-shape tuned tiling ("auto")
+constexpr int kDefK0 = 12, kDefNW = 8, kDefRpl = 1;
+struct Tuned {
+    int k0, nw, rpl;
+    double us;  // measured microseconds per batched step
+};
+std::map<std::pair<int64_t, int64_t>, Tuned> g_tuned;
 
 struct PlanEntry {
     std::unique_ptr<Plan> plan;
@@ -295,6 +302,35 @@ int64_t slot_of(const Plan &P, const GenChain &g, const Rot &r)
 
 }  // namespace
 
+namespace {
+
+// Applier tiling for a new handle of shape (m, n).
+void tiling_for(int64_t m, int64_t n, int *k0, int *nw, int *rpl)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (g_k0 != 0) {
+        *k0 = g_k0;
+        *nw = g_nw;
+        *rpl = g_rpl;
+        return;
+    }
+    auto it = g_tuned.find({m, n});
+    if (it != g_tuned.end()) {
+        *k0 = it->second.k0;
+        *nw = it->second.nw;
+        *rpl = it->second.rpl;
+    } else {
+        *k0 = kDefK0;
+        *nw = kDefNW;
+        *rpl = kDefRpl;
+    }
+}
+
+int create_impl(int64_t m, int64_t n, const double *Q, const double *d, const double *e, const double *P, int k0,
+                int nw, int rpl, bdu_handle *out);
+
+}  // namespace
+
 // A fixed set of distinct handles updated together (see bdu_batch_create).
 struct bdu_batch_ctx {
     std::vector<bdu_ctx *> hs;  // caller's order
@@ -439,7 +475,7 @@ const char *bdu_strerror(int status)
 
 int bdu_set_tiling(int k0, int nw, int rpl)
 {
-    if (!tiling_supported(k0, nw, rpl)) return BDU_EINVAL;
+    if (!(k0 == 0 && nw == 0 && rpl == 0) && !tiling_supported(k0, nw, rpl)) return BDU_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
     g_k0 = k0;
     g_nw = nw;
@@ -459,8 +495,8 @@ int bdu_get_tiling(int *k0, int *nw, int *rpl)
 int64_t bdu_footprint_bytes(int64_t m, int64_t n)
 {
     if (m < n || n < 2) return BDU_EINVAL;
-    int k0, nw;
-    bdu_get_tiling(&k0, &nw, nullptr);
+    int k0, nw, rpl;
+    tiling_for(m, n, &k0, &nw, &rpl);
     hipError_t e;
     Plan *p = get_plan(m, n, k0, nw, false, &e);
     int64_t N = p->N;
@@ -477,7 +513,26 @@ int bdu_create(int64_t m, int64_t n, const double *Q, const double *d, const dou
     if (!out || !Q || !d || !e || !P || m < n || n < 2 || m > (int64_t)1 << 30) return BDU_EINVAL;
     *out = nullptr;
     int k0, nw, rpl;
-    bdu_get_tiling(&k0, &nw, &rpl);
+    tiling_for(m, n, &k0, &nw, &rpl);
+    return create_impl(m, n, Q, d, e, P, k0, nw, rpl, out);
+}
+
+int bdu_handle_tiling(bdu_handle h, int *k0, int *nw, int *rpl)
+{
+    if (!h) return BDU_EINVAL;
+    if (k0) *k0 = h->plan->K0;
+    if (nw) *nw = h->plan->NW;
+    if (rpl) *rpl = h->rpl;
+    return BDU_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+int create_impl(int64_t m, int64_t n, const double *Q, const double *d, const double *e, const double *P, int k0,
+                int nw, int rpl, bdu_handle *out)
+{
     hipError_t err;
     Plan *plan = get_plan(m, n, k0, nw, true, &err);
     if (!plan) return BDU_EDEVICE;
@@ -550,6 +605,10 @@ int bdu_create(int64_t m, int64_t n, const double *Q, const double *d, const dou
     *out = h.release();
     return BDU_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 int bdu_set_stream(bdu_handle h, void *stream)
 {
@@ -780,6 +839,149 @@ int bdu_batch_destroy(bdu_batch b)
     return BDU_OK;
 }
 
+int bdu_autotune(int64_t m, int64_t n, int streams, int64_t *out)
+{
+    if (m < n || n < 2 || streams < 1 || streams > 4096 || m > (int64_t)1 << 30) return BDU_EINVAL;
+    // Synthetic streams: Q = I, P = I, d = 1, e = 1/2; every stream takes the
+    // same update.  The applier's work does not depend on the values.
+    double *dQ = nullptr, *dP = nullptr, *dd = nullptr, *de = nullptr, *db = nullptr, *dc = nullptr;
+    hipStream_t st0 = nullptr;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    auto release = [&]() {
+        for (double *p : {dQ, dP, dd, de, db, dc})
+            if (p) (void)hipFree(p);
+        if (t0) (void)hipEventDestroy(t0);
+        if (t1) (void)hipEventDestroy(t1);
+    };
+    hipError_t e = hipSuccess;
+    auto A = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+    A(hipMalloc(&dQ, sizeof(double) * m * m));
+    A(hipMalloc(&dP, sizeof(double) * n * n));
+    A(hipMalloc(&dd, sizeof(double) * n));
+    A(hipMalloc(&de, sizeof(double) * n));
+    A(hipMalloc(&db, sizeof(double) * m));
+    A(hipMalloc(&dc, sizeof(double) * n));
+    A(hipEventCreate(&t0));
+    A(hipEventCreate(&t1));
+    if (e != hipSuccess) {
+        release();
+        (void)hipGetLastError();
+        return e == hipErrorOutOfMemory ? BDU_ENOMEM : BDU_EDEVICE;
+    }
+    std::vector<double> ones(m, 1.0), half(n, 0.5), bv(m), cv(n);
+    for (int64_t i = 0; i < m; ++i) bv[i] = ((i * 7919) % 1000) / 1000.0 - 0.5;
+    for (int64_t i = 0; i < n; ++i) cv[i] = ((i * 104729) % 1000) / 1000.0 - 0.5;
+    A(hipMemset(dQ, 0, sizeof(double) * m * m));
+    A(hipMemset(dP, 0, sizeof(double) * n * n));
+    A(hipMemcpy2D(dQ, sizeof(double) * (m + 1), ones.data(), sizeof(double), sizeof(double), m,
+                  hipMemcpyHostToDevice));
+    A(hipMemcpy2D(dP, sizeof(double) * (n + 1), ones.data(), sizeof(double), sizeof(double), n,
+                  hipMemcpyHostToDevice));
+    A(hipMemcpy(dd, ones.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+    A(hipMemcpy(de, half.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+    A(hipMemcpy(db, bv.data(), sizeof(double) * m, hipMemcpyHostToDevice));
+    A(hipMemcpy(dc, cv.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+    if (e != hipSuccess) {
+        release();
+        return BDU_EDEVICE;
+    }
+    std::vector<const double *> Bs(streams, db), Cs(streams, dc);
+    std::vector<int> rs(streams, 1);
+    Tuned best{0, 0, 0, 0.0};
+    const int k0s[] = {6, 12}, nws[] = {1, 2, 4, 8}, rpls[] = {1, 2};
+    int status = BDU_OK;
+    for (int k0 : k0s)
+        for (int nw : nws)
+            for (int rpl : rpls) {
+                if (!tiling_supported(k0, nw, rpl)) continue;
+                std::vector<bdu_handle> hs(streams, nullptr);
+                int s = BDU_OK;
+                for (int i = 0; i < streams && s == BDU_OK; ++i)
+                    s = create_impl(m, n, dQ, dd, de, dP, k0, nw, rpl, &hs[i]);
+                bdu_batch b = nullptr;
+                float ms = 0.0f;
+                if (s == BDU_OK) s = batch_build(hs.data(), streams, 1, true, &b);
+                if (s == BDU_OK) {
+                    // one eager step, then three graph steps (the first captures)
+                    s = bdu_batch_update(b, Bs.data(), Cs.data(), rs.data());
+                    if (s == BDU_OK) s = bdu_batch_update(b, Bs.data(), Cs.data(), rs.data());
+                    if (s == BDU_OK) s = bdu_batch_sync(b);
+                    if (s == BDU_OK && hipEventRecord(t0, b->stream) != hipSuccess) s = BDU_EDEVICE;
+                    for (int k = 0; k < 2 && s == BDU_OK; ++k) s = bdu_batch_update(b, Bs.data(), Cs.data(), rs.data());
+                    if (s == BDU_OK && hipEventRecord(t1, b->stream) != hipSuccess) s = BDU_EDEVICE;
+                    if (s == BDU_OK) s = bdu_batch_sync(b);
+                    if (s == BDU_OK && hipEventElapsedTime(&ms, t0, t1) != hipSuccess) s = BDU_EDEVICE;
+                }
+                if (b) bdu_batch_destroy(b);
+                for (bdu_handle h : hs)
+                    if (h) bdu_destroy(h);
+                if (s == BDU_ENOMEM) {  // this tiling does not fit: skip it
+                    (void)hipGetLastError();
+                    continue;
+                }
+                if (s != BDU_OK) {
+                    status = s;
+                    break;
+                }
+                const double us = 1e3 * ms / 2;
+                if (best.k0 == 0 || us < best.us) best = Tuned{k0, nw, rpl, us};
+            }
+    release();
+    if (status != BDU_OK) return status;
+    if (best.k0 == 0) return BDU_ENOMEM;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_tuned[{m, n}] = best;
+    }
+    if (out) {
+        out[0] = best.k0;
+        out[1] = best.nw;
+        out[2] = best.rpl;
+        out[3] = (int64_t)best.us;
+    }
+    return BDU_OK;
+}
+
+int bdu_tune_save(const char *path)
+{
+    if (!path) return BDU_EINVAL;
+    FILE *f = fopen(path, "w");
+    if (!f) return BDU_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    fprintf(f, "# bdu applier tiling per shape: m n k0 nw rows_per_lane us_per_step\n");
+    for (auto &kv : g_tuned)
+        fprintf(f, "%lld %lld %d %d %d %.1f\n", (long long)kv.first.first, (long long)kv.first.second, kv.second.k0,
+                kv.second.nw, kv.second.rpl, kv.second.us);
+    return fclose(f) == 0 ? BDU_OK : BDU_EINVAL;
+}
+
+int bdu_tune_load(const char *path)
+{
+    if (!path) return BDU_EINVAL;
+    FILE *f = fopen(path, "r");
+    if (!f) return BDU_EINVAL;
+    char line[256];
+    int count = 0;
+    std::map<std::pair<int64_t, int64_t>, Tuned> got;
+    while (fgets(line, sizeof line, f)) {
+        if (line[0] == '#' || line[0] == '\n') continue;
+        long long m, n;
+        int k0, nw, rpl;
+        double us;
+        if (sscanf(line, "%lld %lld %d %d %d %lf", &m, &n, &k0, &nw, &rpl, &us) != 6 || m < n || n < 2 ||
+            !tiling_supported(k0, nw, rpl)) {
+            fclose(f);
+            return BDU_EINVAL;
+        }
+        got[{m, n}] = Tuned{k0, nw, rpl, us};
+        ++count;
+    }
+    fclose(f);
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (auto &kv : got) g_tuned[kv.first] = kv.second;
+    return count;
+}
+
 int bdu_timing_enable(int on)
 {
     std::lock_guard<std::mutex> lk(g_tmu);
@@ -831,8 +1033,8 @@ int bdu_givens_device(const double *a, const double *b, int mode, double *c, dou
 int bdu_plan_stats(int64_t m, int64_t n, int64_t *out)
 {
     if (!out || m < n || n < 2) return BDU_EINVAL;
-    int k0, nw;
-    bdu_get_tiling(&k0, &nw, nullptr);
+    int k0, nw, rpl;
+    tiling_for(m, n, &k0, &nw, &rpl);
     hipError_t e;
     Plan *p = get_plan(m, n, k0, nw, false, &e);
     out[0] = p->nleft + p->nspike;
@@ -850,8 +1052,8 @@ int64_t bdu_plan_rotations(int64_t m, int64_t n, int32_t *side, int64_t *idx, in
                            int64_t cap)
 {
     if (m < n || n < 2) return BDU_EINVAL;
-    int k0, nw;
-    bdu_get_tiling(&k0, &nw, nullptr);
+    int k0, nw, rpl;
+    tiling_for(m, n, &k0, &nw, &rpl);
     hipError_t e;
     Plan *p = get_plan(m, n, k0, nw, false, &e);
     int64_t k = 0;

@@ -155,3 +155,34 @@ def test_batch_rejects_bad_arguments(bdu):
         b.close()
     finally:
         h.close()
+
+
+SUPPORTED = [(k0, nw, rpl) for k0 in (6, 12) for nw in (1, 2, 4, 8) for rpl in (1, 2)
+             if (k0, nw, rpl) != (6, 8, 2)]
+
+
+def test_autotune_records_the_tiling_auto_handles_use(bdu, oracle):
+    m, n = 150, 131
+    res = bdu.autotune(m, n, 3)
+    assert (res["k0"], res["nw"], res["rpl"]) in SUPPORTED
+    assert res["us_per_step"] > 0
+    saved = bdu.get_tiling()
+    bdu.set_tiling_auto()
+    try:
+        assert bdu.get_tiling() == (0, 0, 0)
+        f = W.factorization(m, n, 370)
+        h = bdu.Handle(f.Q, f.d, f.e, f.P)
+        assert h.tiling() == (res["k0"], res["nw"], res["rpl"])
+        (B, C), = W.gaussian_updates(m, n, 1, 371, r=2)
+        h.update(B, C)
+        ref = oracle.State(f.Q, f.d, f.e, f.P)
+        oracle.bgu_update(ref, B, C)
+        for nm, x, y in zip("QdeP", h.read(), (ref.Q, ref.d, ref.e, ref.P)):
+            _eq(f"auto-tiled {nm}", x, y)
+        h.close()
+        g = W.factorization(41, 40, 372)  # no entry for this shape: the default tiling
+        h2 = bdu.Handle(g.Q, g.d, g.e, g.P)
+        assert h2.tiling() == (12, 8, 1)
+        h2.close()
+    finally:
+        bdu.set_tiling(*saved)

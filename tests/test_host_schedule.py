@@ -110,3 +110,39 @@ def test_footprint_grows_with_size():
     a, b = bdu.footprint_bytes(512, 512), bdu.footprint_bytes(1024, 1024)
     assert 3.0 * a < b < 4.5 * a
     assert b > 16 * 1024 * 1024  # Q and P alone
+
+
+def test_tuning_table_round_trip(tmp_path):
+    """The autotuner's table is plain text; loading validates every line."""
+    good = tmp_path / "tune.txt"
+    good.write_text("# comment\n2048 2048 12 8 1 280000.0\n4000 2000 12 4 2 1500.5\n")
+    assert bdu.tune_load(str(good)) == 2
+    out = tmp_path / "saved.txt"
+    bdu.tune_save(str(out))
+    rows = [ln.split() for ln in out.read_text().splitlines() if not ln.startswith("#")]
+    assert ["2048", "2048", "12", "8", "1"] in [r[:5] for r in rows]
+    assert ["4000", "2000", "12", "4", "2"] in [r[:5] for r in rows]
+    for bad in ("2048 2048 7 8 1 1.0\n", "10 20 12 8 1 1.0\n", "2048 2048 12\n", "6 6 6 8 2 1.0\n"):
+        p = tmp_path / "bad.txt"
+        p.write_text(bad)
+        with pytest.raises(bdu.BduError):
+            bdu.tune_load(str(p))
+    with pytest.raises(bdu.BduError):
+        bdu.tune_load(str(tmp_path / "missing.txt"))
+
+
+def test_plan_queries_in_auto_tiling_mode(tmp_path):
+    """Schedule queries resolve the per-shape tiling in "auto" mode (no 0-wide blocks)."""
+    saved = bdu.get_tiling()
+    f = tmp_path / "t.txt"
+    f.write_text("64 64 6 2 1 10.0\n")
+    bdu.tune_load(str(f))
+    try:
+        bdu.set_tiling_auto()
+        a = bdu.plan_stats(64, 64)   # tuned entry
+        b = bdu.plan_stats(65, 64)   # default tiling
+        side, idx, ph, tick = bdu.plan_rotations(64, 64)
+        assert a["left"] + a["right"] + 1 == len(side)  # plus the fold
+        assert b["chains"] > 0 and bdu.footprint_bytes(64, 64) > 0
+    finally:
+        bdu.set_tiling(*saved)
