@@ -146,9 +146,61 @@ int bdu_get_tiling(int *k0, int *nw, int *rpl);
  * lines "m n k0 nw rpl us"; load returns the number of entries read.
  * bdu_handle_tiling reports the tiling a handle was created with. */
 int bdu_autotune(int64_t m, int64_t n, int streams, int64_t *out);
+
+/* Where the rotation generator keeps the working band (offsets -2..3) and
+ * u, v, about 64 bytes per row: allow = 1 (default) in LDS when they fit
+ * (n up to about 2550), else in device memory; allow = 0 always in device
+ * memory.  Applies to handles created afterwards; results do not depend on
+ * it. */
+int bdu_set_generation_in_lds(int allow);
 int bdu_tune_save(const char *path);
 int bdu_tune_load(const char *path);
 int bdu_handle_tiling(bdu_handle h, int *k0, int *nw, int *rpl);
+
+/* Serving (the served form of the update): resident streams admitted
+ * against a device-memory budget, bounded per-stream request queues, and a
+ * worker thread that batches continuously.  Each round the worker takes the
+ * oldest pending request of up to max_batch streams (oldest first) and runs
+ * them as one bdu_update_batched, so every stream's requests are applied in
+ * submission order and each result is bit-identical to the stream's own
+ * sequence of bdu_update calls.
+ *
+ * bdu_server_create: budget_bytes of device memory for resident streams
+ *   (each costs bdu_footprint_bytes(m, n)), queue_cap requests per stream.
+ * bdu_server_open: admit a stream (arguments as bdu_create); BDU_ENOMEM when
+ *   the budget would be exceeded (counted, the server is unchanged).
+ * bdu_server_submit: queue A_s <- A_s + B C^T (B m x r, C n x r, host or
+ *   device; copied before returning).  BDU_EBUSY when the stream's queue
+ *   holds queue_cap requests (counted, nothing queued).  ticket may be NULL
+ *   (nobody waits; the request is released when done); otherwise the ticket
+ *   must be waited for once, which releases it.
+ * bdu_server_wait: block until the request is done; its latency (submit to
+ *   completion) in ms.  bdu_server_poll: 1 done, 0 pending.
+ * bdu_server_drain: wait until no request is queued or running.
+ * bdu_server_pause: 1 stops the worker from starting rounds, 0 resumes.
+ * bdu_server_read / bdu_server_close: wait until the stream has no queued or
+ *   running request, then read (as bdu_read) / destroy it and return its
+ *   budget.  Both fail (BDU_EINVAL) on a paused server with queued requests.
+ * bdu_server_stats: counts[9] = {completed, rejected busy, rejected for
+ *   memory, rounds, requests run in rounds, open streams, budget bytes in
+ *   use, requests pending, failed}; latency[4] = {p50, p99, mean, max} in ms
+ *   over completed requests.
+ * bdu_server_destroy: runs what is queued (unless paused), stops the worker
+ *   and destroys every stream; no call on the server may be in progress. */
+typedef struct bdu_server_ctx *bdu_server;
+int bdu_server_create(int64_t budget_bytes, int queue_cap, int max_batch, bdu_server *out);
+int bdu_server_open(bdu_server s, int64_t m, int64_t n, const double *Q, const double *d,
+                    const double *e, const double *P, int *stream_id);
+int bdu_server_submit(bdu_server s, int stream_id, const double *B, const double *C, int r,
+                      int64_t *ticket);
+int bdu_server_wait(bdu_server s, int64_t ticket, double *latency_ms);
+int bdu_server_poll(bdu_server s, int64_t ticket);
+int bdu_server_drain(bdu_server s);
+int bdu_server_pause(bdu_server s, int paused);
+int bdu_server_read(bdu_server s, int stream_id, double *Q, double *d, double *e, double *P);
+int bdu_server_close(bdu_server s, int stream_id);
+int bdu_server_stats(bdu_server s, int64_t *counts, double *latency);
+int bdu_server_destroy(bdu_server s);
 
 /* Stage timing.  bdu_timing_enable(1) clears the log and brackets every
  * later kernel launch with HIP events on the stream the kernel runs on;

@@ -64,9 +64,21 @@ def lib():
         L.bdu_plan_rotations.argtypes = [i64, i64, vp, vp, vp, vp, i64]
         L.bdu_plan_rotations.restype = i64
         L.bdu_autotune.argtypes = [i64, i64, i32, ctypes.POINTER(i64)]
+        L.bdu_set_generation_in_lds.argtypes = [i32]
         L.bdu_tune_save.argtypes = [ctypes.c_char_p]
         L.bdu_tune_load.argtypes = [ctypes.c_char_p]
         L.bdu_handle_tiling.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.bdu_server_create.argtypes = [i64, i32, i32, ctypes.POINTER(vp)]
+        L.bdu_server_open.argtypes = [vp, i64, i64, vp, vp, vp, vp, ctypes.POINTER(i32)]
+        L.bdu_server_submit.argtypes = [vp, i32, vp, vp, i32, ctypes.POINTER(i64)]
+        L.bdu_server_wait.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_double)]
+        L.bdu_server_poll.argtypes = [vp, i64]
+        L.bdu_server_drain.argtypes = [vp]
+        L.bdu_server_pause.argtypes = [vp, i32]
+        L.bdu_server_read.argtypes = [vp, i32, vp, vp, vp, vp]
+        L.bdu_server_close.argtypes = [vp, i32]
+        L.bdu_server_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
+        L.bdu_server_destroy.argtypes = [vp]
         L.bdu_batch_create.argtypes = [ctypes.POINTER(vp), i32, i32, ctypes.POINTER(vp)]
         L.bdu_batch_update.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i32)]
         L.bdu_batch_sync.argtypes = [vp]
@@ -77,7 +89,9 @@ def lib():
                   "bdu_get_tiling", "bdu_plan_stats", "bdu_givens_device", "bdu_timing_enable",
                   "bdu_timing_read", "bdu_batch_create", "bdu_batch_update", "bdu_batch_sync",
                   "bdu_batch_info", "bdu_batch_destroy", "bdu_autotune", "bdu_tune_save", "bdu_tune_load",
-                  "bdu_handle_tiling"):
+                  "bdu_handle_tiling", "bdu_set_generation_in_lds", "bdu_server_create", "bdu_server_open", "bdu_server_submit",
+                  "bdu_server_wait", "bdu_server_poll", "bdu_server_drain", "bdu_server_pause",
+                  "bdu_server_read", "bdu_server_close", "bdu_server_stats", "bdu_server_destroy"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -119,6 +133,10 @@ def _ptr(a, matrix: bool = False):
 
 def set_tiling(k0: int, nw: int, rpl: int = 1) -> None:
     _check(lib().bdu_set_tiling(k0, nw, rpl), "bdu_set_tiling")
+
+
+def set_generation_in_lds(allow: bool) -> None:
+    _check(lib().bdu_set_generation_in_lds(1 if allow else 0), "bdu_set_generation_in_lds")
 
 
 def set_tiling_auto() -> None:
@@ -309,6 +327,83 @@ class Batch:
         if self._b:
             lib().bdu_batch_destroy(self._b)
             self._b = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """bdu_server: resident streams, budget admission, bounded queues, continuous batching."""
+
+    STAT_KEYS = ["completed", "rejected_busy", "rejected_memory", "rounds", "batched_requests",
+                 "streams", "bytes_in_use", "pending", "failed"]
+
+    def __init__(self, budget_bytes: int, queue_cap: int = 8, max_batch: int = 256):
+        s = ctypes.c_void_p()
+        _check(lib().bdu_server_create(budget_bytes, queue_cap, max_batch, ctypes.byref(s)), "bdu_server_create")
+        self._s = s
+        self.shapes = {}
+
+    def open(self, Q, d, e, P) -> int:
+        """Stream id; raises BduError (status BDU_ENOMEM) when over the budget."""
+        m, n = Q.shape[0], P.shape[0]
+        sid = ctypes.c_int()
+        _check(lib().bdu_server_open(self._s, m, n, _ptr(Q, True), _ptr(d), _ptr(e), _ptr(P, True),
+                                     ctypes.byref(sid)), "bdu_server_open")
+        self.shapes[sid.value] = (m, n)
+        return sid.value
+
+    def submit(self, sid: int, B, C, detach: bool = False):
+        """Ticket (None if detached); raises BduError (status BDU_EBUSY) when the stream's queue is full."""
+        r = 1 if B.ndim == 1 else B.shape[1]
+        t = ctypes.c_int64()
+        _check(lib().bdu_server_submit(self._s, sid, _ptr(B, True), _ptr(C, True), r,
+                                       None if detach else ctypes.byref(t)), "bdu_server_submit")
+        return None if detach else t.value
+
+    def wait(self, ticket: int) -> float:
+        ms = ctypes.c_double()
+        _check(lib().bdu_server_wait(self._s, ticket, ctypes.byref(ms)), "bdu_server_wait")
+        return ms.value
+
+    def poll(self, ticket: int) -> bool:
+        return bool(_check(lib().bdu_server_poll(self._s, ticket), "bdu_server_poll"))
+
+    def drain(self) -> None:
+        _check(lib().bdu_server_drain(self._s), "bdu_server_drain")
+
+    def pause(self, paused: bool = True) -> None:
+        _check(lib().bdu_server_pause(self._s, 1 if paused else 0), "bdu_server_pause")
+
+    def read(self, sid: int):
+        m, n = self.shapes[sid]
+        Q = np.empty((m, m), order="F")
+        P = np.empty((n, n), order="F")
+        d = np.empty(n)
+        e = np.empty(max(n - 1, 1))
+        _check(lib().bdu_server_read(self._s, sid, Q.ctypes.data, d.ctypes.data, e.ctypes.data, P.ctypes.data),
+               "bdu_server_read")
+        return Q, d, e[: n - 1], P
+
+    def close_stream(self, sid: int) -> None:
+        _check(lib().bdu_server_close(self._s, sid), "bdu_server_close")
+        self.shapes.pop(sid, None)
+
+    def stats(self) -> dict:
+        c = (ctypes.c_int64 * 9)()
+        lat = (ctypes.c_double * 4)()
+        _check(lib().bdu_server_stats(self._s, c, lat), "bdu_server_stats")
+        out = dict(zip(self.STAT_KEYS, list(c)))
+        out.update(p50_ms=lat[0], p99_ms=lat[1], mean_ms=lat[2], max_ms=lat[3])
+        return out
+
+    def close(self) -> None:
+        if self._s:
+            lib().bdu_server_destroy(self._s)
+            self._s = ctypes.c_void_p()
 
     def __del__(self):
         try:

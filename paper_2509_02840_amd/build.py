@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libbdu.so")
 
-SOURCES = ["kernels.hip", "bdu.cpp", "plan.cpp"]
+SOURCES = ["kernels.hip", "bdu.cpp", "plan.cpp", "serve.cpp"]
 
 # -ffp-contract=off: only the fma calls written in the source fuse.
 # -packed-fp32-ops off: no packed FP32 instructions are generated.
@@ -35,7 +35,7 @@ def build() -> str:
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")

@@ -34,6 +34,7 @@ struct Tuned {
     double us;  // measured microseconds per batched step
 };
 std::map<std::pair<int64_t, int64_t>, Tuned> g_tuned;
+bool g_gen_lds = true;  // generation keeps its band in LDS when it fits
 
 struct PlanEntry {
     std::unique_ptr<Plan> plan;
@@ -304,6 +305,12 @@ int64_t slot_of(const Plan &P, const GenChain &g, const Rot &r)
 
 namespace {
 
+bool gen_lds_fits(int64_t n, int64_t N)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g_gen_lds && gen_lds_bytes(n, N) <= kMaxGenLds;
+}
+
 // Applier tiling for a new handle of shape (m, n).
 void tiling_for(int64_t m, int64_t n, int *k0, int *nw, int *rpl)
 {
@@ -503,7 +510,7 @@ int64_t bdu_footprint_bytes(int64_t m, int64_t n)
     const int64_t ldq = (m + 127) / 128 * 128, ldp = (n + 127) / 128 * 128;
     int64_t bytes = 8 * (ldq * m + ldp * n + 2 * n + 2 * (m + n) + 2 * (m + n));
     bytes += 16 * (p->slots[0] + p->slots[1] + 2 * (4 * (int64_t)p->K + 64) + std::max<int64_t>(p->nspike, 1));
-    if (gen_lds_bytes(n, N) > kMaxGenLds) bytes += gen_lds_bytes(n, N);
+    if (!gen_lds_fits(n, N)) bytes += gen_lds_bytes(n, N);
     return bytes;
 }
 
@@ -515,6 +522,14 @@ int bdu_create(int64_t m, int64_t n, const double *Q, const double *d, const dou
     int k0, nw, rpl;
     tiling_for(m, n, &k0, &nw, &rpl);
     return create_impl(m, n, Q, d, e, P, k0, nw, rpl, out);
+}
+
+int bdu_set_generation_in_lds(int allow)
+{
+    if (allow != 0 && allow != 1) return BDU_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_gen_lds = allow != 0;
+    return BDU_OK;
 }
 
 int bdu_handle_tiling(bdu_handle h, int *k0, int *nw, int *rpl)
@@ -541,7 +556,7 @@ int create_impl(int64_t m, int64_t n, const double *Q, const double *d, const do
     h->n = n;
     h->plan = plan;
     h->rpl = rpl;
-    h->lds_gen = gen_lds_bytes(n, plan->N) <= kMaxGenLds;
+    h->lds_gen = gen_lds_fits(n, plan->N);
     HandleDev &hd = h->hd;
     hipError_t a = hipSuccess;
     auto A = [&](hipError_t x) { if (a == hipSuccess) a = x; };

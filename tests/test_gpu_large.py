@@ -1,0 +1,68 @@
+"""Generation with the working band in device memory (large n).
+
+The band (offsets -2..3) and u, v of the rotation generator live in LDS up
+to n of about 2550 and in device memory beyond.  The device-memory variant
+is checked bit-exactly on small shapes (forced), then on shapes that need it
+(n = 3000 and 4096) against the oracle on sampled rows of Q and P and on all
+of d and e.
+"""
+import numpy as np
+import pytest
+
+from paper_2509_02840_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bdu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2509_02840_amd import bdu as B
+    B.lib()
+    return B
+
+
+def _eq(name, x, y):
+    x, y = np.asarray(x), np.asarray(y)
+    assert x.shape == y.shape, name
+    bad = np.flatnonzero(~(x == y).ravel())
+    assert bad.size == 0, f"{name}: {bad.size} of {x.size} differ, first at {bad[0]}"
+
+
+@pytest.mark.parametrize("m,n,r", [(2, 2, 1), (5, 5, 1), (14, 12, 2), (65, 64, 1), (200, 200, 3), (257, 191, 2)])
+def test_global_band_generation_bit_exact(bdu, oracle, m, n, r):
+    f = W.factorization(m, n, 600 + m)
+    (B, C), = W.gaussian_updates(m, n, 1, 601 + n, r=r)
+    bdu.set_generation_in_lds(False)
+    try:
+        h = bdu.Handle(f.Q, f.d, f.e, f.P)
+    finally:
+        bdu.set_generation_in_lds(True)
+    h.update(B, C)
+    ref = oracle.State(f.Q, f.d, f.e, f.P)
+    oracle.bgu_update(ref, B, C)
+    for nm, x, y in zip("QdeP", h.read(), (ref.Q, ref.d, ref.e, ref.P)):
+        _eq(nm, x, y)
+    h.close()
+
+
+@pytest.mark.parametrize("m,n", [(3000, 3000), (4096, 4096), (4200, 4096)])
+def test_large_n_sampled_rows(bdu, oracle, m, n):
+    f = W.factorization(m, n, 620 + n)
+    (B, C), = W.gaussian_updates(m, n, 1, 621)
+    h = bdu.Handle(f.Q, f.d, f.e, f.P)
+    h.update(B, C)
+    Q1, d1, e1, P1 = h.read()
+    h.close()
+    u = oracle.project(f.Q, B[:, 0])
+    v = oracle.project(f.P, C[:, 0])
+    rng = np.random.default_rng(622)
+    qr = np.sort(rng.choice(m, 48, replace=False))
+    pr = np.sort(rng.choice(n, 48, replace=False))
+    Qr, d, e, Pr = oracle.bgu_pass_rows(m, n, f.Q[qr], f.d, f.e, f.P[pr], u, v)
+    _eq("d", d1, d)
+    _eq("e", e1, e)
+    _eq("Q rows", Q1[qr], Qr)
+    _eq("P rows", P1[pr], Pr)

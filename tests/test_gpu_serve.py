@@ -1,0 +1,139 @@
+"""The served form: admission, bounded queues, continuous batching.
+
+A stream's result must not depend on what else is being served: after a
+mixed, interleaved load every stream equals both the oracle's sequential
+updates and the same updates applied to a lone handle.
+"""
+import numpy as np
+import pytest
+
+from paper_2509_02840_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bdu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2509_02840_amd import bdu as B
+    B.lib()
+    return B
+
+
+def _eq(name, x, y):
+    x, y = np.asarray(x), np.asarray(y)
+    assert x.shape == y.shape, name
+    bad = np.flatnonzero(~(x == y).ravel())
+    assert bad.size == 0, f"{name}: {bad.size} of {x.size} differ, first at {bad[0]}"
+
+
+SHAPES = [(90, 90), (120, 77), (64, 64), (150, 150), (33, 20)]
+
+
+def test_mixed_load_equals_alone_and_oracle(bdu, oracle):
+    srv = bdu.Server(budget_bytes=1 << 34, queue_cap=64, max_batch=8)
+    rng = np.random.default_rng(500)
+    sids, alone, refs, plan = [], [], [], []
+    try:
+        for i, (m, n) in enumerate(SHAPES):
+            f = W.factorization(m, n, 510 + i)
+            sids.append(srv.open(f.Q, f.d, f.e, f.P))
+            alone.append(bdu.Handle(f.Q, f.d, f.e, f.P))
+            refs.append(oracle.State(f.Q, f.d, f.e, f.P))
+        # 6 requests per stream, ranks 1-3, submitted in a random interleaving
+        for i, (m, n) in enumerate(SHAPES):
+            for k in range(6):
+                (B, C), = W.gaussian_updates(m, n, 1, 5000 + 10 * i + k, r=1 + (k + i) % 3)
+                plan.append((i, k, B, C))
+        order = rng.permutation(len(plan))
+        per_stream = {i: [] for i in range(len(SHAPES))}
+        for j in order:
+            per_stream[plan[j][0]].append(plan[j])
+        # keep each stream's own order k = 0..5 (the queue is FIFO per stream)
+        for i in per_stream:
+            per_stream[i].sort(key=lambda x: x[1])
+        cursor = {i: 0 for i in per_stream}
+        tickets = []
+        for j in order:
+            i = plan[j][0]
+            _, k, B, C = per_stream[i][cursor[i]]
+            cursor[i] += 1
+            tickets.append(srv.submit(sids[i], B, C))
+            alone[i].update(B, C)
+            oracle.bgu_update(refs[i], B, C)
+        lats = [srv.wait(t) for t in tickets]
+        assert all(x >= 0 for x in lats)
+        st = srv.stats()
+        assert st["completed"] == len(plan) and st["failed"] == 0 and st["pending"] == 0
+        assert st["batched_requests"] == len(plan)
+        for i, sid in enumerate(sids):
+            got, one = srv.read(sid), alone[i].read()
+            for nm, x, y, z in zip("QdeP", got, one, (refs[i].Q, refs[i].d, refs[i].e, refs[i].P)):
+                _eq(f"stream {i} {nm} served vs alone", x, y)
+                _eq(f"stream {i} {nm} served vs oracle", x, z)
+    finally:
+        srv.close()
+        for h in alone:
+            h.close()
+
+
+def test_paused_arrivals_form_one_round(bdu, oracle):
+    """Requests for all streams queued while paused run as a single batched round."""
+    srv = bdu.Server(budget_bytes=1 << 34, queue_cap=4, max_batch=16)
+    try:
+        sids, refs = [], []
+        for i, (m, n) in enumerate(SHAPES):
+            f = W.factorization(m, n, 530 + i)
+            sids.append(srv.open(f.Q, f.d, f.e, f.P))
+            refs.append(oracle.State(f.Q, f.d, f.e, f.P))
+        srv.pause(True)
+        for i, (m, n) in enumerate(SHAPES):
+            (B, C), = W.gaussian_updates(m, n, 1, 540 + i)
+            srv.submit(sids[i], B, C, detach=True)
+            oracle.bgu_update(refs[i], B, C)
+        assert srv.stats()["pending"] == len(SHAPES)
+        srv.pause(False)
+        srv.drain()
+        st = srv.stats()
+        assert st["rounds"] == 1 and st["batched_requests"] == len(SHAPES) and st["completed"] == len(SHAPES)
+        for i, sid in enumerate(sids):
+            for nm, x, y in zip("QdeP", srv.read(sid), (refs[i].Q, refs[i].d, refs[i].e, refs[i].P)):
+                _eq(f"stream {i} {nm}", x, y)
+    finally:
+        srv.close()
+
+
+def test_queue_cap_and_budget_admission(bdu):
+    m = n = 64
+    one = bdu.footprint_bytes(m, n)
+    srv = bdu.Server(budget_bytes=2 * one + one // 2, queue_cap=2, max_batch=4)
+    try:
+        f = W.factorization(m, n, 550)
+        a = srv.open(f.Q, f.d, f.e, f.P)
+        b = srv.open(f.Q, f.d, f.e, f.P)
+        with pytest.raises(bdu.BduError) as ei:
+            srv.open(f.Q, f.d, f.e, f.P)
+        assert ei.value.status == bdu.BDU_ENOMEM
+        st = srv.stats()
+        assert st["rejected_memory"] == 1 and st["streams"] == 2 and st["bytes_in_use"] == 2 * one
+        srv.pause(True)
+        (B, C), = W.gaussian_updates(m, n, 1, 551)
+        t1 = srv.submit(a, B, C)
+        t2 = srv.submit(a, B, C)
+        with pytest.raises(bdu.BduError) as ei:
+            srv.submit(a, B, C)
+        assert ei.value.status == bdu.BDU_EBUSY
+        t3 = srv.submit(b, B, C)  # the other stream's queue is independent
+        assert not srv.poll(t1)
+        srv.pause(False)
+        for t in (t1, t2, t3):
+            srv.wait(t)
+        st = srv.stats()
+        assert st["rejected_busy"] == 1 and st["completed"] == 3
+        srv.close_stream(b)  # returns its budget: a new stream fits again
+        c = srv.open(f.Q, f.d, f.e, f.P)
+        assert srv.stats()["streams"] == 2 and c != b
+    finally:
+        srv.close()
