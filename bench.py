@@ -135,6 +135,162 @@ def copy_probe(torch) -> int:
     return 0
 
 
+def householder_pair(torch, gen, n: int):
+    """A dense orthogonal n x n matrix (I - 2 v v^T)(I - 2 w w^T), v, w random
+    unit vectors, built on the GPU.  For throughput runs over many sizes: the
+    update's work does not depend on the factors' values."""
+    dev = torch.device("cuda:0")
+    v = torch.randn(n, 1, generator=gen, dtype=torch.float64, device=dev)
+    w = torch.randn(n, 1, generator=gen, dtype=torch.float64, device=dev)
+    v /= v.norm()
+    w /= w.norm()
+    eye = torch.eye(n, dtype=torch.float64, device=dev)
+    H = (eye - 2.0 * (v @ v.T)) @ (eye - 2.0 * (w @ w.T))
+    return H.T.contiguous().T  # column-major
+
+
+def random_stream(torch, gen, n: int):
+    Q = householder_pair(torch, gen, n)
+    P = householder_pair(torch, gen, n)
+    d = 1.0 + 9.0 * torch.rand(n, generator=gen, dtype=torch.float64, device="cuda:0")
+    e = torch.rand(n - 1, generator=gen, dtype=torch.float64, device="cuda:0")
+    return Q, d, e, P
+
+
+def hetero(torch, bdu, args) -> int:
+    """Mixed sizes in one batch: S square streams, n = round(exp(U(ln 128, ln 2048))),
+    each taking 32 rank-1 and 8 rank-4 updates in a seeded random order; a
+    step updates every stream once (one batch step, max rank 4)."""
+    S = args.hetero_streams
+    rng = np.random.default_rng(args.seed)
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(args.seed)
+    sizes = [int(round(math.exp(rng.uniform(math.log(128), math.log(2048))))) for _ in range(S)]
+    orders = [rng.permutation([1] * 32 + [4] * 8) for _ in range(S)]
+    hs = []
+    for n in sizes:
+        Q, d, e, P = random_stream(torch, gen, n)
+        hs.append(bdu.Handle(Q, d, e, P))
+        del Q, P
+    torch.cuda.empty_cache()
+    nsteps = len(orders[0])
+    batch = bdu.Batch(hs, max_rank=4)
+
+    def inputs(k):
+        Bs, Cs = [], []
+        for n, o in zip(sizes, orders):
+            r = int(o[k])
+            Bs.append(torch.randn((r, n), generator=gen, dtype=torch.float64, device="cuda:0").T / math.sqrt(n))
+            Cs.append(torch.randn((r, n), generator=gen, dtype=torch.float64, device="cuda:0").T / math.sqrt(n))
+        return Bs, Cs, [int(o[k]) for o in orders]
+
+    steps_in = [inputs(k) for k in range(nsteps)]  # resident before timing
+    batch.update(*steps_in[0])  # warm-up step
+    batch.sync()
+    lat = []
+    total_r1 = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(1, nsteps):
+        Bs, Cs, rs = steps_in[k]
+        ta = time.perf_counter()
+        batch.update(Bs, Cs, rs)
+        batch.sync()
+        lat.append(time.perf_counter() - ta)
+        total_r1 += sum(rs)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    del steps_in
+    info = batch.info()
+    batch.close()
+    tilings = sorted({h.tiling() for h in hs})
+    for h in hs:
+        h.close()
+    print(json.dumps({
+        "metric": "FP64 rank-1-equivalent updates/sec, heterogeneous batch",
+        "value": total_r1 / dt, "unit": "rank-1 updates/s", "steps": nsteps - 1,
+        "ms_per_step": 1e3 * dt / (nsteps - 1), "p50_ms": 1e3 * float(np.percentile(lat, 50)),
+        "p99_ms": 1e3 * float(np.percentile(lat, 99)), "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{S} square streams, n log-uniform on [128, 2048], 32 rank-1 + 8 rank-4 "
+                               "updates per stream in random order, one batch step per update",
+                   "n_min": min(sizes), "n_max": max(sizes), "n_median": int(np.median(sizes)),
+                   "tilings": [list(t) for t in tilings], "graph": bool(info["graph"])}}))
+    return 0
+
+
+def serve(torch, bdu, args) -> int:
+    """Served load: R resident square streams, n uniform over {512, ..., 8192};
+    requests arrive as a Poisson process at the given rate, uniform over the
+    streams, rank 1/2/4/8 with probability 0.6/0.2/0.1/0.1, Gaussian b, c.
+    Reports accepted rank-1-equivalent updates/s and the latency of completed
+    requests; requests that find their stream's queue full are rejected."""
+    rng = np.random.default_rng(args.seed)
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(args.seed)
+    R = args.serve_streams
+    srv = bdu.Server(budget_bytes=int(args.serve_budget_gb * 2 ** 30), queue_cap=args.serve_queue,
+                     max_batch=R)
+    sizes = [int(x) for x in rng.choice([int(v) for v in args.serve_sizes.split(",")], R)]
+    sids = []
+    for n in sizes:
+        Q, d, e, P = random_stream(torch, gen, n)
+        try:
+            sids.append(srv.open(Q, d, e, P))
+        except bdu.BduError as err:
+            if err.status != bdu.BDU_ENOMEM:
+                raise
+            sids.append(None)
+        del Q, P
+    torch.cuda.empty_cache()
+    live = [(sid, n) for sid, n in zip(sids, sizes) if sid is not None]
+    # pre-drawn update vectors per size and rank, in host memory as a client
+    # would send them (the server copies its inputs)
+    ranks = [1, 2, 4, 8]
+    pool = {(n, r): (np.asfortranarray(rng.standard_normal((n, r)) / math.sqrt(n)),
+                     np.asfortranarray(rng.standard_normal((n, r)) / math.sqrt(n)))
+            for n in set(n for _, n in live) for r in ranks}
+    torch.cuda.synchronize()
+    submitted = busy = accepted_r1 = 0
+    t0 = time.perf_counter()
+    next_t = t0
+    while True:
+        now = time.perf_counter()
+        if now - t0 >= args.serve:
+            break
+        if now < next_t:
+            time.sleep(min(next_t - now, 0.01))
+            continue
+        next_t += rng.exponential(1.0 / args.serve_rate)
+        sid, n = live[rng.integers(len(live))]
+        r = int(rng.choice(ranks, p=[0.6, 0.2, 0.1, 0.1]))
+        B, C = pool[(n, r)]
+        try:
+            srv.submit(sid, B, C, detach=True)
+            submitted += 1
+            accepted_r1 += r
+        except bdu.BduError as err:
+            if err.status != bdu.BDU_EBUSY:
+                raise
+            busy += 1
+    t_arrivals = time.perf_counter() - t0
+    srv.drain()
+    t_all = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    print(json.dumps({
+        "metric": "FP64 served rank-1-equivalent updates/sec, p50/p99 latency of completed requests",
+        "value": accepted_r1 / t_all, "unit": "rank-1 updates/s", "dtype": "f64", "data": "synthetic",
+        "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"], "max_ms": st["max_ms"],
+        "config": {"workload": f"{R} resident square streams, n uniform over {{{args.serve_sizes}}}, Poisson arrivals "
+                               f"{args.serve_rate}/s for {args.serve} s, ranks 1/2/4/8 w.p. .6/.2/.1/.1",
+                   "streams_admitted": len(live), "streams_rejected_memory": st["rejected_memory"],
+                   "budget_gb": args.serve_budget_gb, "queue_cap": args.serve_queue},
+        "requests_accepted": submitted, "requests_rejected_busy": busy, "rounds": st["rounds"],
+        "mean_round_size": st["batched_passes"] / max(st["rounds"], 1),
+        "arrival_window_s": t_arrivals, "drain_included_s": t_all}))
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -150,6 +306,16 @@ def main() -> int:
     ap.add_argument("--no-autotune", action="store_true", help="use the library's default tiling")
     ap.add_argument("--graph-steps", type=int, default=3,
                     help="extra batched steps replayed as a HIP graph after the timed region")
+    ap.add_argument("--hetero", action="store_true",
+                    help="instead: the mixed-size batch workload (prints its own JSON line)")
+    ap.add_argument("--hetero-streams", type=int, default=256)
+    ap.add_argument("--serve", type=float, default=0.0,
+                    help="instead: serve Poisson arrivals for this many seconds (prints its own JSON line)")
+    ap.add_argument("--serve-streams", type=int, default=64)
+    ap.add_argument("--serve-sizes", type=str, default="512,1024,2048,4096,8192")
+    ap.add_argument("--serve-rate", type=float, default=20000.0)
+    ap.add_argument("--serve-queue", type=int, default=4)
+    ap.add_argument("--serve-budget-gb", type=float, default=200.0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy three times (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -166,6 +332,10 @@ def main() -> int:
     from paper_2509_02840_amd import bdu
 
     torch.cuda.set_device(0)
+    if args.hetero:
+        return hetero(torch, bdu, args)
+    if args.serve > 0:
+        return serve(torch, bdu, args)
     n = args.n
     tune = None
     if args.tiling:

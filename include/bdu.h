@@ -159,11 +159,13 @@ int bdu_handle_tiling(bdu_handle h, int *k0, int *nw, int *rpl);
 
 /* Serving (the served form of the update): resident streams admitted
  * against a device-memory budget, bounded per-stream request queues, and a
- * worker thread that batches continuously.  Each round the worker takes the
- * oldest pending request of up to max_batch streams (oldest first) and runs
- * them as one bdu_update_batched, so every stream's requests are applied in
- * submission order and each result is bit-identical to the stream's own
- * sequence of bdu_update calls.
+ * worker thread that batches continuously at the granularity of rank-1
+ * passes (a rank-r request is r passes, Section 3.1).  Each round the worker
+ * takes the next pass of the oldest pending request of up to max_batch
+ * streams (oldest first) and runs them as one batched rank-1 update, so
+ * every stream's passes are applied in submission order and each result is
+ * bit-identical to the stream's own sequence of bdu_update calls.  A round
+ * lasts one pass, so short requests are not held back by long ones.
  *
  * bdu_server_create: budget_bytes of device memory for resident streams
  *   (each costs bdu_footprint_bytes(m, n)), queue_cap requests per stream.
@@ -182,7 +184,7 @@ int bdu_handle_tiling(bdu_handle h, int *k0, int *nw, int *rpl);
  *   running request, then read (as bdu_read) / destroy it and return its
  *   budget.  Both fail (BDU_EINVAL) on a paused server with queued requests.
  * bdu_server_stats: counts[9] = {completed, rejected busy, rejected for
- *   memory, rounds, requests run in rounds, open streams, budget bytes in
+ *   memory, rounds, passes run in rounds, open streams, budget bytes in
  *   use, requests pending, failed}; latency[4] = {p50, p99, mean, max} in ms
  *   over completed requests.
  * bdu_server_destroy: runs what is queued (unless paused), stops the worker

@@ -338,7 +338,7 @@ class Batch:
 class Server:
     """bdu_server: resident streams, budget admission, bounded queues, continuous batching."""
 
-    STAT_KEYS = ["completed", "rejected_busy", "rejected_memory", "rounds", "batched_requests",
+    STAT_KEYS = ["completed", "rejected_busy", "rejected_memory", "rounds", "batched_passes",
                  "streams", "bytes_in_use", "pending", "failed"]
 
     def __init__(self, budget_bytes: int, queue_cap: int = 8, max_batch: int = 256):

@@ -1,12 +1,14 @@
 // serve.cpp -- the served form of the update: resident streams, admission by
 // a device-memory budget, bounded per-stream queues and continuous batching.
 //
-// One worker thread owns the GPU work.  Each round it takes, from every
-// stream with pending requests (up to max_batch streams, oldest request
-// first), the stream's oldest request and runs them together as one batched
-// update (bdu_update_batched), so a stream's requests are applied in
-// submission order and each result is the one its stream would get alone.
-// Requests that arrive during a round join the next one.
+// One worker thread owns the GPU work.  A rank-r request is r rank-1 passes
+// (Section 3.1), and rounds batch passes, not requests: each round takes,
+// from every stream with pending work (up to max_batch streams, oldest
+// request first), the next pass of the stream's oldest request and runs them
+// together as one batched rank-1 update (bdu_update_batched).  A stream's
+// passes thus run in submission order and each result is the one its stream
+// would get alone; a rank-1 request finishes in one round whatever the ranks
+// of the others, and requests that arrive during a round join the next.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
@@ -38,6 +40,7 @@ struct Request {
     int r;
     std::vector<double> B, C;  // host copies, m x r and n x r
     Clock::time_point submitted, finished;
+    int next = 0;  // next column (pass) to run
     bool done = false;
     bool detached = false;  // no ticket was handed out: released when done
     int status = BDU_OK;
@@ -51,10 +54,29 @@ struct Stream {
     bool held = false;       // a read or close is using the handle
 };
 
-// Copy `bytes` from a host or device pointer into host memory.
-int fetch(void *dst, const void *src, size_t bytes)
+bool on_device(const void *p)
 {
-    return hipMemcpy(dst, src, bytes, hipMemcpyDefault) == hipSuccess ? BDU_OK : BDU_EDEVICE;
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice;
+}
+
+// Copy `bytes` from a host or device pointer into host memory.  Device
+// sources go through a non-blocking stream of their own, so a submission
+// never waits for a running round.
+int fetch(void *dst, const void *src, size_t bytes, hipStream_t copy_stream)
+{
+    if (!on_device(src)) {
+        memcpy(dst, src, bytes);
+        return BDU_OK;
+    }
+    if (hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, copy_stream) != hipSuccess ||
+        hipStreamSynchronize(copy_stream) != hipSuccess)
+        return BDU_EDEVICE;
+    return BDU_OK;
 }
 
 }  // namespace
@@ -62,7 +84,9 @@ int fetch(void *dst, const void *src, size_t bytes)
 struct bdu_server_ctx {
     int64_t budget = 0, used = 0;
     int queue_cap = 1, max_batch = 1;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;       // the rounds
+    hipStream_t copy_stream = nullptr;  // submissions from device memory
+    std::mutex copy_mu;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::map<int, Stream> streams;
@@ -115,9 +139,9 @@ void bdu_server_ctx::run()
                 Request *q = s.queue.front();
                 round.push_back(q);
                 hs.push_back(s.h);
-                Bs.push_back(q->B.data());
-                Cs.push_back(q->C.data());
-                rs.push_back(q->r);
+                Bs.push_back(q->B.data() + (size_t)q->next * s.m);
+                Cs.push_back(q->C.data() + (size_t)q->next * s.n);
+                rs.push_back(1);
             }
         }
         const int st = bdu_update_batched(hs.data(), Bs.data(), Cs.data(), rs.data(), (int)round.size());
@@ -128,8 +152,9 @@ void bdu_server_ctx::run()
             batched += (int64_t)round.size();
             for (Request *q : round) {
                 Stream &s = streams[q->sid];
-                s.queue.pop_front();
                 s.in_flight = false;
+                if (st == BDU_OK && ++q->next < q->r) continue;  // more passes to run
+                s.queue.pop_front();
                 q->finished = t;
                 q->status = st;
                 q->done = true;
@@ -159,7 +184,12 @@ int bdu_server_create(int64_t budget_bytes, int queue_cap, int max_batch, bdu_se
     s->budget = budget_bytes;
     s->queue_cap = queue_cap;
     s->max_batch = max_batch;
-    if (hipStreamCreate(&s->stream) != hipSuccess) return BDU_EDEVICE;
+    // non-blocking: neither waits for work the client issues on the null stream
+    if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) return BDU_EDEVICE;
+    if (hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipStreamDestroy(s->stream);
+        return BDU_EDEVICE;
+    }
     bdu_server_ctx *p = s.get();
     s->worker = std::thread([p] { p->run(); });
     *out = s.release();
@@ -220,8 +250,12 @@ int bdu_server_submit(bdu_server s, int stream_id, const double *B, const double
     q->r = r;
     q->B.resize((size_t)(m * r));
     q->C.resize((size_t)(n * r));
-    int st = fetch(q->B.data(), B, sizeof(double) * m * r);
-    if (st == BDU_OK) st = fetch(q->C.data(), C, sizeof(double) * n * r);
+    int st;
+    {
+        std::lock_guard<std::mutex> lk(s->copy_mu);
+        st = fetch(q->B.data(), B, sizeof(double) * m * r, s->copy_stream);
+        if (st == BDU_OK) st = fetch(q->C.data(), C, sizeof(double) * n * r, s->copy_stream);
+    }
     if (st != BDU_OK) return st;
     {
         std::lock_guard<std::mutex> lk(s->mu);
@@ -388,6 +422,7 @@ int bdu_server_destroy(bdu_server s)
     }
     s->cv_done.notify_all();
     if (s->stream) (void)hipStreamDestroy(s->stream);
+    if (s->copy_stream) (void)hipStreamDestroy(s->copy_stream);
     delete s;
     return BDU_OK;
 }

@@ -67,7 +67,7 @@ def test_mixed_load_equals_alone_and_oracle(bdu, oracle):
         assert all(x >= 0 for x in lats)
         st = srv.stats()
         assert st["completed"] == len(plan) and st["failed"] == 0 and st["pending"] == 0
-        assert st["batched_requests"] == len(plan)
+        assert st["batched_passes"] == sum(B.shape[1] for _, _, B, _ in plan)
         for i, sid in enumerate(sids):
             got, one = srv.read(sid), alone[i].read()
             for nm, x, y, z in zip("QdeP", got, one, (refs[i].Q, refs[i].d, refs[i].e, refs[i].P)):
@@ -97,7 +97,7 @@ def test_paused_arrivals_form_one_round(bdu, oracle):
         srv.pause(False)
         srv.drain()
         st = srv.stats()
-        assert st["rounds"] == 1 and st["batched_requests"] == len(SHAPES) and st["completed"] == len(SHAPES)
+        assert st["rounds"] == 1 and st["batched_passes"] == len(SHAPES) and st["completed"] == len(SHAPES)
         for i, sid in enumerate(sids):
             for nm, x, y in zip("QdeP", srv.read(sid), (refs[i].Q, refs[i].d, refs[i].e, refs[i].P)):
                 _eq(f"stream {i} {nm}", x, y)
@@ -135,5 +135,33 @@ def test_queue_cap_and_budget_admission(bdu):
         srv.close_stream(b)  # returns its budget: a new stream fits again
         c = srv.open(f.Q, f.d, f.e, f.P)
         assert srv.stats()["streams"] == 2 and c != b
+    finally:
+        srv.close()
+
+
+def test_rounds_batch_passes_so_short_requests_finish_first(bdu, oracle):
+    """A rank-1 request queued beside a rank-3 one finishes after the first round."""
+    srv = bdu.Server(budget_bytes=1 << 34, queue_cap=4, max_batch=16)
+    try:
+        fa, fb = W.factorization(80, 80, 560), W.factorization(70, 60, 561)
+        a = srv.open(fa.Q, fa.d, fa.e, fa.P)
+        b = srv.open(fb.Q, fb.d, fb.e, fb.P)
+        (Ba, Ca), = W.gaussian_updates(80, 80, 1, 562, r=3)
+        (Bb, Cb), = W.gaussian_updates(70, 60, 1, 563, r=1)
+        srv.pause(True)
+        ta = srv.submit(a, Ba, Ca)
+        tb = srv.submit(b, Bb, Cb)
+        srv.pause(False)
+        lb = srv.wait(tb)
+        la = srv.wait(ta)
+        st = srv.stats()
+        assert st["rounds"] == 3 and st["batched_passes"] == 4
+        assert lb < la
+        ra, rb = oracle.State(fa.Q, fa.d, fa.e, fa.P), oracle.State(fb.Q, fb.d, fb.e, fb.P)
+        oracle.bgu_update(ra, Ba, Ca)
+        oracle.bgu_update(rb, Bb, Cb)
+        for sid, ref in ((a, ra), (b, rb)):
+            for nm, x, y in zip("QdeP", srv.read(sid), (ref.Q, ref.d, ref.e, ref.P)):
+                _eq(f"stream {sid} {nm}", x, y)
     finally:
         srv.close()
