@@ -126,10 +126,14 @@ const char *bdu_strerror(int status);
  * rotation streams), for admission control. */
 int64_t bdu_footprint_bytes(int64_t m, int64_t n);
 
-/* Applier tiling: chains per wavefront k0 in {6, 12}, wavefronts per
- * workgroup nw in {1, 2, 4, 8}, matrix rows per lane rpl in {1, 2} (except
- * k0 = 6, nw = 8, rpl = 2); default (12, 8, 1).  Applies to handles created
- * afterwards.  Results do not depend on it. */
+/* Applier tiling: chains per wavefront k0 in {6, 12}, compute wavefronts
+ * per workgroup nw, matrix rows per lane rpl in {1, 2}.  nw in {1, 2, 4, 8}
+ * (except k0 = 6, nw = 8, rpl = 2): every wavefront also loads or stores the
+ * matrix columns it needs.  nw in {3, 7, 15} with k0 = 12 (rpl = 1 only for
+ * 15): "staged", the workgroup adds one memory wavefront that streams
+ * columns and rotation coefficients through LDS for the compute wavefronts.
+ * Default (12, 8, 1).  Applies to handles created afterwards.  Results do
+ * not depend on it. */
 int bdu_set_tiling(int k0, int nw, int rpl);
 int bdu_get_tiling(int *k0, int *nw, int *rpl);
 

@@ -903,7 +903,7 @@ int bdu_autotune(int64_t m, int64_t n, int streams, int64_t *out)
     std::vector<const double *> Bs(streams, db), Cs(streams, dc);
     std::vector<int> rs(streams, 1);
     Tuned best{0, 0, 0, 0.0};
-    const int k0s[] = {6, 12}, nws[] = {1, 2, 4, 8}, rpls[] = {1, 2};
+    const int k0s[] = {6, 12}, nws[] = {1, 2, 3, 4, 7, 8, 15}, rpls[] = {1, 2};
     int status = BDU_OK;
     for (int k0 : k0s)
         for (int nw : nws)

@@ -591,6 +591,251 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(K0 * R 
     }
 }
 
+// ---- staged application ---------------------------------------------------------
+//
+// A workgroup of NW compute wavefronts and one memory wavefront (index NW).
+// The compute wavefronts run the register-window sweep above with LDS
+// traffic only: wavefront w takes its new columns from ring w and hands its
+// finished columns to ring w + 1; the coefficients of each front come from a
+// coefficient ring in LDS (one broadcast read per rotation).  The memory
+// wavefront feeds ring 0 and the coefficient ring from global memory, DL
+// fronts ahead, and writes the columns arriving in ring NW back to Q or P.
+// Compute wavefronts therefore issue no global or scalar memory operation in
+// their loop, and none of their waits depends on a global-memory latency.
+template <int K0, int NW, int R>
+struct Staged {
+    static constexpr int U = K0 + 3, WSZ = 3 * U, S = U, K = K0 * NW;
+    static constexpr int RC = ring_cols(K0);
+    static constexpr int RING = RC * 64 * R;                  // doubles per ring
+    static constexpr int COEF = (NW + 1) * RING;              // offset of the coefficient ring
+    static constexpr int LDS_DOUBLES = COEF + 3 * K * 2;      // 3 fronts of K pairs
+    static constexpr int DL = U / 3;                          // memory prefetch depth, U % DL == 0
+    static constexpr int NCI = (K + 63) / 64;                 // coefficient loads per front
+    static_assert(U % 3 == 0 && U % DL == 0 && (3 * U) % RC == 0, "static ring slots");
+};
+
+template <int K0, int NW, int R, int MODE>
+__device__ __forceinline__ void sweep_compute(const BlockDesc bd, double *lds, int w, int lane)
+{
+    using T = Staged<K0, NW, R>;
+    constexpr int U = T::U, WSZ = T::WSZ, S = T::S, K = T::K, RC = T::RC;
+    constexpr bool DESC = MODE < 2;
+    const int lmax = bd.lmax;
+    if (lmax < 0) return;
+    const int nfront = bd.nfront;
+    const int lam_hi = lmax + 1;
+    double buf[R][WSZ];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int i = 0; i < WSZ; ++i) buf[r][i] = 0.0;
+    const double *rin = lds + w * T::RING + lane;
+    double *rout = lds + (w + 1) * T::RING + lane;
+    const double2 *coef = (const double2 *)(lds + T::COEF) + w * K0;
+    constexpr FrontOrder ord = front_order(MODE, K, K0);
+    const int flush_end = lam_hi / 3 + K0 - 1;
+    const int nchunk = nfront / U;
+    int live_end = w + (flush_end + U) / U;
+    live_end = live_end < nchunk ? live_end : nchunk;
+    auto idle = [&](int chunks) {
+        for (int c = 0; c < chunks * U; ++c) __syncthreads();
+    };
+    __syncthreads();  // the memory wavefront's prologue is in LDS
+    idle(w);
+    for (int F0 = w * S; F0 < live_end * U; F0 += U) {
+#pragma unroll
+        for (int phi = 0; phi < U; ++phi) {
+            const int F = F0 + phi;
+            const int f = F - w * S;
+            if (phi == 0 && f == 0) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) buf[r][0] = rin[r * 64];
+            }
+#pragma unroll
+            for (int k = 1; k <= 3; ++k)
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    buf[r][pmod(3 * phi + k, WSZ)] = rin[(pmod(3 * phi + k, RC) * R + r) * 64];
+            // front F's coefficients sit in slot F mod 3 (F0 is a multiple of 3)
+            const double2 *cf = coef + (phi % 3) * K;
+#pragma unroll
+            for (int p = 0; p < K0; ++p) {
+                const int t = ord.t[p];
+                const int l0 = 3 * (phi - t) + rho_of(MODE, K, t);
+                const int sx = pmod(l0 + (DESC ? 1 : 0), WSZ);
+                const int sy = pmod(l0 + (DESC ? 0 : 1), WSZ);
+                const double2 cv = cf[p];
+#pragma unroll
+                for (int r = 0; r < R; ++r) rot(cv.x, cv.y, buf[r][sx], buf[r][sy]);
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    rout[(pmod(3 * (phi - K0 + 1) + k, RC) * R + r) * 64] = buf[r][pmod(3 * (phi - K0 + 1) + k, WSZ)];
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int j = -3 * (K0 - 1); j <= 3; ++j) asm volatile("" : "+v"(buf[r][pmod(3 * phi + j, WSZ)]));
+        }
+    }
+    idle(nchunk - (live_end > w ? live_end : w));
+}
+
+template <int K0, int NW, int R, int MODE>
+__device__ __forceinline__ void sweep_memory(GLOBAL double *__restrict__ X, int ld, int ncols, int row0,
+                                             const CONSTANT double *cs, const BlockDesc bd, double *lds, int lane)
+{
+    using T = Staged<K0, NW, R>;
+    constexpr int U = T::U, S = T::S, K = T::K, RC = T::RC, DL = T::DL, NCI = T::NCI;
+    constexpr bool DESC = MODE < 2;
+    constexpr int DIR = DESC ? -1 : 1;
+    const int lmax = bd.lmax;
+    if (lmax < 0) return;
+    const int nfront = bd.nfront;
+    const int base = bd.base;
+    const int lam_hi = lmax + 1;
+    const int lam_lo = DESC ? (base - ncols > 0 ? base - ncols : 0) : 0;
+    const int col0 = base - 1;
+    double *rw = lds + lane;                               // ring 0
+    const double *rr = lds + NW * T::RING + lane;          // ring NW
+    double *coef = lds + T::COEF;  // pairs (c, s)
+    const GLOBAL double *cg = (const GLOBAL double *)(uintptr_t)cs;
+    auto colptr = [&](int lam) -> const GLOBAL double * {
+        int c = col0 + DIR * lam;
+        c = c < 0 ? 0 : (c >= ncols ? ncols - 1 : c);
+        return X + (int64_t)c * ld;
+    };
+    // FIFO entry for front Fl (written to LDS during front Fl): the columns
+    // 3 Fl + 4 .. 3 Fl + 6 that wavefront 0 reads at front Fl + 1, and the
+    // coefficients of front Fl + 1.
+    double colf[DL][3][R];
+    double cof[DL][NCI][2];
+    auto load_entry = [&](int slot, int Fl) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const GLOBAL double *cp = colptr(3 * Fl + 4 + k);
+#pragma unroll
+            for (int r = 0; r < R; ++r) colf[slot][k][r] = cp[row0 + 64 * r];
+        }
+        int Fc = Fl + 1 < nfront ? Fl + 1 : nfront - 1;
+        const GLOBAL double *cp = cg + 2 * (int64_t)Fc * K;
+#pragma unroll
+        for (int i = 0; i < NCI; ++i) {
+            const int q = lane + 64 * i < K ? lane + 64 * i : K - 1;
+            cof[slot][i][0] = cp[2 * q];
+            cof[slot][i][1] = cp[2 * q + 1];
+        }
+    };
+    // prologue: columns 0..3 and front 0's coefficients, then the FIFO
+    {
+#pragma unroll
+        for (int k = 0; k <= 3; ++k) {
+            const GLOBAL double *cp = colptr(k);
+#pragma unroll
+            for (int r = 0; r < R; ++r) rw[(k * R + r) * 64] = cp[row0 + 64 * r];
+        }
+#pragma unroll
+        for (int i = 0; i < NCI; ++i)
+            if (lane + 64 * i < K) {
+                coef[2 * (lane + 64 * i)] = cg[2 * (lane + 64 * i)];
+                coef[2 * (lane + 64 * i) + 1] = cg[2 * (lane + 64 * i) + 1];
+            }
+    }
+#pragma unroll
+    for (int j = 0; j < DL; ++j) load_entry(j, j);
+    __syncthreads();
+    for (int F0 = 0; F0 < nfront; F0 += U) {
+#pragma unroll
+        for (int phi = 0; phi < U; ++phi) {
+            const int F = F0 + phi;
+            const int slot = phi % DL;
+            // columns for wavefront 0's next front, coefficients of front F + 1
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int r = 0; r < R; ++r) rw[(pmod(3 * phi + 4 + k, RC) * R + r) * 64] = colf[slot][k][r];
+#pragma unroll
+            for (int i = 0; i < NCI; ++i)
+                if (lane + 64 * i < K) {
+                    double *d = coef + 2 * (((phi + 1) % 3) * K + lane + 64 * i);
+                    d[0] = cof[slot][i][0];
+                    d[1] = cof[slot][i][1];
+                }
+            load_entry(slot, F + DL);
+            // columns the last compute wavefront finished at front F - 1
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int lam = 3 * (F - 1 - (NW - 1) * S - K0 + 1) + k;
+                if (lam >= lam_lo && lam <= lam_hi) {
+                    GLOBAL double *cp = X + (int64_t)(col0 + DIR * lam) * ld;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) cp[row0 + 64 * r] = rr[(pmod(3 * phi - 3 * K0 + k, RC) * R + r) * 64];
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <int K0, int NW, int R>
+__global__ __launch_bounds__(64 * (NW + 1)) __attribute__((amdgpu_waves_per_eu(R == 2 ? 2 : 4))) void
+apply_staged_kernel(HandleDev *const *hs, Gate gate)
+{
+    using T = Staged<K0, NW, R>;
+    const int total = gridDim.x * gridDim.y;
+    const int lin = blockIdx.y * gridDim.x + blockIdx.x;
+    int item = lin;
+    if (total % 8 == 0) item = (lin % 8) * (total / 8) + lin / 8;
+    const int hidx = item / gridDim.x, pid = item % gridDim.x;
+    if (gate.ranks && gate.pass >= gate.ranks[hidx]) return;
+    const CONSTANT HandleDev *h = kptr(hs[hidx]);
+    const int m = h->m, n = h->n;
+    constexpr int PH = 64 * R;
+    const int qp = (m + PH - 1) / PH, pp = (n + PH - 1) / PH;
+    if (pid >= qp + pp) return;
+    __shared__ double lds[T::LDS_DOUBLES];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    for (int i = threadIdx.x; i < T::LDS_DOUBLES; i += 64 * (NW + 1)) lds[i] = 0.0;
+    const int nb1 = h->nb1, nb2 = h->nb2;
+    const bool onQ = pid < qp;
+    const int row0 = (onQ ? pid : pid - qp) * PH + lane;
+    GLOBAL double *X = gptr(onQ ? h->Q : h->P);
+    const int ld = onQ ? h->ldq : h->ldp;
+    const int ncols = onQ ? m : n;
+    const BlockDesc *blk = onQ ? h->blkL : h->blkR;
+    const CONSTANT double *cs = kptr((const double *)(onQ ? h->csL : h->csR));
+    if (onQ && m > n && w == 0) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) spike_apply(X, ld, m, n, row0 + 64 * r, kptr((const double *)h->csSp));
+    }
+    __syncthreads();
+    for (int b = 0; b < nb1 + nb2; ++b) {
+        const BlockDesc bd = load_block(blk, b);
+        const CONSTANT double *cb = cs + 2 * bd.off;
+        if (w == NW) {
+            if (b < nb1) {
+                if (onQ) sweep_memory<K0, NW, R, 0>(X, ld, ncols, row0, cb, bd, lds, lane);
+                else sweep_memory<K0, NW, R, 1>(X, ld, ncols, row0, cb, bd, lds, lane);
+            } else {
+                if (onQ) sweep_memory<K0, NW, R, 2>(X, ld, ncols, row0, cb, bd, lds, lane);
+                else sweep_memory<K0, NW, R, 3>(X, ld, ncols, row0, cb, bd, lds, lane);
+            }
+        } else {
+            if (b < nb1) {
+                if (onQ) sweep_compute<K0, NW, R, 0>(bd, lds, w, lane);
+                else sweep_compute<K0, NW, R, 1>(bd, lds, w, lane);
+            } else {
+                if (onQ) sweep_compute<K0, NW, R, 2>(bd, lds, w, lane);
+                else sweep_compute<K0, NW, R, 3>(bd, lds, w, lane);
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // The rotation primitive on arrays (checks the device arithmetic against the
 // reference bit for bit).
 __global__ void givens_kernel(const double *a, const double *b, int mode, double *c, double *s, double *r,
@@ -669,8 +914,20 @@ static hipError_t launch_apply_t(HandleDev *const *hs, int count, int max_panels
     return hipGetLastError();
 }
 
+template <int K0, int NW, int R>
+static hipError_t launch_staged_t(HandleDev *const *hs, int count, int max_panels, Gate gate, hipStream_t st)
+{
+    hipLaunchKernelGGL((apply_staged_kernel<K0, NW, R>), dim3(max_panels, count), dim3(64 * (NW + 1)), 0, st, hs,
+                       gate);
+    return hipGetLastError();
+}
+
+// nw in {1, 2, 4, 8}: nw wavefronts, each loading or storing what it needs;
+// nw in {3, 7, 15} (k0 = 12): the staged kernel, nw compute wavefronts and a
+// memory wavefront.
 bool tiling_supported(int k0, int nw, int rpl)
 {
+    if (nw == 3 || nw == 7 || nw == 15) return k0 == 12 && (rpl == 1 || (rpl == 2 && nw != 15));
     if (k0 == 6 && nw == 8 && rpl == 2) return false;  // its LDS ring exceeds 160 KB
     return (k0 == 6 || k0 == 12) && (nw == 1 || nw == 2 || nw == 4 || nw == 8) && (rpl == 1 || rpl == 2);
 }
@@ -685,6 +942,11 @@ hipError_t launch_apply(HandleDev *const *hs, int count, int max_panels, int k0,
     BDU_APPLY_CASE(6, 1, 2) BDU_APPLY_CASE(6, 2, 2) BDU_APPLY_CASE(6, 4, 2)
     BDU_APPLY_CASE(12, 1, 2) BDU_APPLY_CASE(12, 2, 2) BDU_APPLY_CASE(12, 4, 2) BDU_APPLY_CASE(12, 8, 2)
 #undef BDU_APPLY_CASE
+#define BDU_STAGED_CASE(A, B, C) \
+    if (k0 == A && nw == B && rpl == C) return launch_staged_t<A, B, C>(hs, count, max_panels, gate, st);
+    BDU_STAGED_CASE(12, 3, 1) BDU_STAGED_CASE(12, 7, 1) BDU_STAGED_CASE(12, 15, 1)
+    BDU_STAGED_CASE(12, 3, 2) BDU_STAGED_CASE(12, 7, 2)
+#undef BDU_STAGED_CASE
     return hipErrorInvalidValue;
 }
 

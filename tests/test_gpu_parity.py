@@ -127,7 +127,8 @@ def test_tiling_does_not_change_results(bdu):
     outs = []
     saved = bdu.get_tiling()
     try:
-        for tk in [(6, 1, 1), (12, 1, 1), (12, 2, 2), (12, 4, 2), (6, 4, 1), (12, 8, 2), (6, 8, 1), (12, 4, 1)]:
+        for tk in [(6, 1, 1), (12, 1, 1), (12, 2, 2), (12, 4, 2), (6, 4, 1), (12, 8, 2), (6, 8, 1), (12, 4, 1),
+                   (12, 3, 1), (12, 7, 1), (12, 15, 1), (12, 3, 2), (12, 7, 2)]:
             bdu.set_tiling(*tk)
             h = bdu.Handle(f.Q, f.d, f.e, f.P)
             h.update(B, C)
@@ -138,6 +139,33 @@ def test_tiling_does_not_change_results(bdu):
     for o in outs[1:]:
         for x, y in zip(o, outs[0]):
             _eq("tiling", x, y)
+
+
+STAGED = [(12, 3, 1), (12, 7, 1), (12, 15, 1), (12, 3, 2), (12, 7, 2)]
+
+
+@pytest.mark.parametrize("tk", STAGED)
+@pytest.mark.parametrize("m,n", [(2, 2), (14, 12), (65, 64), (257, 191), (300, 300)])
+def test_staged_applier_bit_exact(bdu, oracle, tk, m, n):
+    """The staged applier (memory wavefront + compute wavefronts): one pass from
+    the oracle's projections, d, e, Q and P exactly."""
+    f = W.factorization(m, n, 80 + m)
+    rng = np.random.default_rng(81 + n)
+    u, v = rng.standard_normal(m), rng.standard_normal(n)
+    saved = bdu.get_tiling()
+    bdu.set_tiling(*tk)
+    try:
+        h = bdu.Handle(f.Q, f.d, f.e, f.P)
+    finally:
+        bdu.set_tiling(*saved)
+    assert h.tiling() == tk
+    h.update_projected(u, v)
+    got = h.read()
+    h.close()
+    st = oracle.State(f.Q, f.d, f.e, f.P)
+    oracle.bgu_pass(st, u.copy(), v.copy())
+    for nm, x, y in zip("QdeP", got, (st.Q, st.d, st.e, st.P)):
+        _eq(f"{tk} {nm}", x, y)
 
 
 def test_batched_equals_one_by_one(bdu, oracle):
