@@ -132,7 +132,7 @@ int64_t bdu_footprint_bytes(int64_t m, int64_t n);
  * matrix columns it needs.  nw in {3, 7, 15} with k0 = 12 (rpl = 1 only for
  * 15): "staged", the workgroup adds one memory wavefront that streams
  * columns and rotation coefficients through LDS for the compute wavefronts.
- * Default (12, 8, 1).  Applies to handles created afterwards.  Results do
+ * Default (12, 7, 1).  Applies to handles created afterwards.  Results do
  * not depend on it. */
 int bdu_set_tiling(int k0, int nw, int rpl);
 int bdu_get_tiling(int *k0, int *nw, int *rpl);

@@ -27,8 +27,8 @@ using namespace bdu;
 namespace {
 
 std::mutex g_mu;
-int g_k0 = 12, g_nw = 8, g_rpl = 1;  // 0, 0, 0: per-shape tuned tiling ("auto")
-constexpr int kDefK0 = 12, kDefNW = 8, kDefRpl = 1;
+int g_k0 = 12, g_nw = 7, g_rpl = 1;  // 0, 0, 0: per-shape tuned tiling ("auto")
+constexpr int kDefK0 = 12, kDefNW = 7, kDefRpl = 1;
 struct Tuned {
     int k0, nw, rpl;
     double us;  // measured microseconds per batched step

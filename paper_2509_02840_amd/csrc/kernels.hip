@@ -649,10 +649,15 @@ __device__ __forceinline__ void sweep_compute(const BlockDesc bd, double *lds, i
             const int f = F - w * S;
             if (phi == 0 && f == 0) {
 #pragma unroll
-                for (int r = 0; r < R; ++r) buf[r][0] = rin[r * 64];
-            }
+                for (int k = 0; k <= 3; ++k)
 #pragma unroll
-            for (int k = 1; k <= 3; ++k)
+                    for (int r = 0; r < R; ++r) buf[r][k] = rin[(k * R + r) * 64];
+            }
+            // the next front's new columns 3f+4 .. 3f+6, read a front early:
+            // their producer finished them two fronts ago, and their slots
+            // are not pinned, so the reads complete during this front
+#pragma unroll
+            for (int k = 4; k <= 6; ++k)
 #pragma unroll
                 for (int r = 0; r < R; ++r)
                     buf[r][pmod(3 * phi + k, WSZ)] = rin[(pmod(3 * phi + k, RC) * R + r) * 64];
@@ -708,14 +713,14 @@ __device__ __forceinline__ void sweep_memory(GLOBAL double *__restrict__ X, int 
         return X + (int64_t)c * ld;
     };
     // FIFO entry for front Fl (written to LDS during front Fl): the columns
-    // 3 Fl + 4 .. 3 Fl + 6 that wavefront 0 reads at front Fl + 1, and the
-    // coefficients of front Fl + 1.
+    // 3 Fl + 7 .. 3 Fl + 9 that wavefront 0 reads at front Fl + 1 (for its
+    // front Fl + 2), and the coefficients of front Fl + 1.
     double colf[DL][3][R];
     double cof[DL][NCI][2];
     auto load_entry = [&](int slot, int Fl) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const GLOBAL double *cp = colptr(3 * Fl + 4 + k);
+            const GLOBAL double *cp = colptr(3 * Fl + 7 + k);
 #pragma unroll
             for (int r = 0; r < R; ++r) colf[slot][k][r] = cp[row0 + 64 * r];
         }
@@ -728,10 +733,10 @@ __device__ __forceinline__ void sweep_memory(GLOBAL double *__restrict__ X, int 
             cof[slot][i][1] = cp[2 * q + 1];
         }
     };
-    // prologue: columns 0..3 and front 0's coefficients, then the FIFO
+    // prologue: columns 0..6 and front 0's coefficients, then the FIFO
     {
 #pragma unroll
-        for (int k = 0; k <= 3; ++k) {
+        for (int k = 0; k <= 6; ++k) {
             const GLOBAL double *cp = colptr(k);
 #pragma unroll
             for (int r = 0; r < R; ++r) rw[(k * R + r) * 64] = cp[row0 + 64 * r];
@@ -751,11 +756,11 @@ __device__ __forceinline__ void sweep_memory(GLOBAL double *__restrict__ X, int 
         for (int phi = 0; phi < U; ++phi) {
             const int F = F0 + phi;
             const int slot = phi % DL;
-            // columns for wavefront 0's next front, coefficients of front F + 1
+            // columns wavefront 0 reads at front F + 1, coefficients of front F + 1
 #pragma unroll
             for (int k = 0; k < 3; ++k)
 #pragma unroll
-                for (int r = 0; r < R; ++r) rw[(pmod(3 * phi + 4 + k, RC) * R + r) * 64] = colf[slot][k][r];
+                for (int r = 0; r < R; ++r) rw[(pmod(3 * phi + 7 + k, RC) * R + r) * 64] = colf[slot][k][r];
 #pragma unroll
             for (int i = 0; i < NCI; ++i)
                 if (lane + 64 * i < K) {

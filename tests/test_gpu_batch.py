@@ -33,7 +33,7 @@ def _eq(name, x, y):
 
 
 SHAPES = [(120, 120), (97, 64), (64, 64), (150, 131), (33, 20), (2, 2), (200, 200)]
-TILINGS = [(12, 8, 1), (12, 4, 2), (6, 2, 1), (12, 8, 1), (6, 4, 2), (12, 1, 1), (12, 8, 1)]
+TILINGS = [(12, 7, 1), (12, 4, 2), (6, 2, 1), (12, 8, 1), (6, 4, 2), (12, 1, 1), (12, 7, 1)]
 
 
 def _streams(bdu, oracle, seed):
@@ -82,7 +82,7 @@ def test_batch_steps_replayed_graph_match_oracle(bdu, oracle):
             _check(hs, refs, f"step {step} ranks {list(ranks)}")
             info = batch.info()
             assert info["steps"] == step + 1
-            assert info["groups"] == 5  # (12,8,1) (12,4,2) (6,2,1) (6,4,2) (12,1,1)
+            assert info["groups"] == 6  # (12,7,1) (12,4,2) (6,2,1) (12,8,1) (6,4,2) (12,1,1)
             assert info["graph"] == (1 if step >= 1 else 0)
     finally:
         batch.close()
@@ -107,7 +107,7 @@ def test_batch_with_stage_timing_runs_eagerly(bdu, oracle):
             batch.update(Bs, Cs)
             batch.sync()
         t = bdu.timing_read()
-        assert t["apply"][1] >= 2 * 5  # step 1 and 2: two passes, five tiling groups
+        assert t["apply"][1] >= 2 * 6  # steps 1 and 2: two passes, six tiling groups
         assert batch.info()["graph"] == 0  # the graph is only captured with timing off
         _check(hs, refs, "timed steps")
     finally:
@@ -182,7 +182,7 @@ def test_autotune_records_the_tiling_auto_handles_use(bdu, oracle):
         h.close()
         g = W.factorization(41, 40, 372)  # no entry for this shape: the default tiling
         h2 = bdu.Handle(g.Q, g.d, g.e, g.P)
-        assert h2.tiling() == (12, 8, 1)
+        assert h2.tiling() == (12, 7, 1)
         h2.close()
     finally:
         bdu.set_tiling(*saved)
