@@ -35,13 +35,14 @@ METRIC = "FP64 rank-1 updates/sec + p50/p99 latency, batched vs plain, n=2048"
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CUs x 128 FP64 flop/clk x 2.4 GHz
 
 # HBM bytes of one applier launch, from rocprofv3 --pmc FETCH_SIZE and
-# WRITE_SIZE runs of this script (profiles/apply_kernel_n2048_s64_traffic.md),
+# WRITE_SIZE runs of this script (profiles/apply_staged_kernel_n2048_s64_traffic.md),
 # each scaled by what the counter reads for a plain 1 GiB device copy
 # (bench.py --copy-probe).  Valid only for the sources with this digest and
 # the workload named; otherwise the traffic is reported as null.
 TRAFFIC_SOURCES = ["paper_2509_02840_amd/csrc/kernels.hip", "paper_2509_02840_amd/csrc/schedule.h",
                    "paper_2509_02840_amd/csrc/device.h", "paper_2509_02840_amd/csrc/plan.cpp"]
-MEASURED_TRAFFIC = {"sha256": None, "n": 2048, "streams": 64, "tiling": (12, 8, 1), "bytes": None}
+MEASURED_TRAFFIC = {"sha256": "808b22c05b543379ff04569bf6e06f76e07837a2b3fe6fe28ad3885b789c7b82",
+                    "n": 2048, "streams": 64, "tiling": (12, 7, 1), "bytes": 469368066980.0}
 
 
 def sources_digest() -> str:
