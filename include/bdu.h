@@ -44,7 +44,7 @@ enum {
     BDU_EINVAL = -1,     /* bad shape, NULL argument, or m < n */
     BDU_ENOMEM = -2,     /* device allocation failed or over the memory budget */
     BDU_EDEVICE = -3,    /* a HIP call failed; the handle is poisoned */
-    BDU_ENONFINITE = -4, /* reserved: non-finite input rejected */
+    BDU_ENONFINITE = -4, /* a NaN or infinite input was rejected (bdu_set_finite_check) */
     BDU_EBUSY = -5       /* serving queue full */
 };
 
@@ -126,12 +126,14 @@ const char *bdu_strerror(int status);
  * rotation streams), for admission control. */
 int64_t bdu_footprint_bytes(int64_t m, int64_t n);
 
-/* Applier tiling: chains per wavefront k0 in {6, 12}, compute wavefronts
- * per workgroup nw, matrix rows per lane rpl in {1, 2}.  nw in {1, 2, 4, 8}
- * (except k0 = 6, nw = 8, rpl = 2): every wavefront also loads or stores the
- * matrix columns it needs.  nw in {3, 7, 15} with k0 = 12 (rpl = 1 only for
- * 15): "staged", the workgroup adds one memory wavefront that streams
- * columns and rotation coefficients through LDS for the compute wavefronts.
+/* Applier tiling: chains per wavefront k0 in {6, 12, 18}, compute
+ * wavefronts per workgroup nw, matrix rows per lane rpl in {1, 2}.
+ * nw in {1, 2, 4, 8} with k0 in {6, 12} (except k0 = 6, nw = 8, rpl = 2):
+ * every wavefront also loads or stores the matrix columns it needs.
+ * "Staged": nw in {3, 7, 15} with k0 = 12 (rpl = 1 only for 15) and
+ * nw in {3, 5, 7} with k0 = 18 (rpl = 1); the workgroup adds one memory
+ * wavefront that streams columns and rotation coefficients through LDS for
+ * the compute wavefronts.
  * Default (12, 7, 1).  Applies to handles created afterwards.  Results do
  * not depend on it. */
 int bdu_set_tiling(int k0, int nw, int rpl);
@@ -157,6 +159,13 @@ int bdu_autotune(int64_t m, int64_t n, int streams, int64_t *out);
  * memory.  Applies to handles created afterwards; results do not depend on
  * it. */
 int bdu_set_generation_in_lds(int allow);
+
+/* Input check: with on = 1, bdu_create, bdu_update, bdu_update_projected,
+ * bdu_update_batched and bdu_batch_update scan their inputs (after copying
+ * them to the device) and return BDU_ENONFINITE, changing no handle, if any
+ * value is NaN or infinite.  Costs one extra pass over the inputs and a
+ * stream synchronization per call; off (0) by default. */
+int bdu_set_finite_check(int on);
 int bdu_tune_save(const char *path);
 int bdu_tune_load(const char *path);
 int bdu_handle_tiling(bdu_handle h, int *k0, int *nw, int *rpl);

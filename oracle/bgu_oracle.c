@@ -170,6 +170,10 @@ static void check_every(bgu *S)
  * u, and columns i, i+1 of Q: Q <- Q G^T keeps A = Q W P^T. */
 static void left(bgu *S, int64_t i, double c, double s)
 {
+    if ((S->flags & ORC_CHECK_WINDOW) && i + 1 <= S->N)
+        for (int64_t j = 1; j <= S->n; ++j)
+            if ((j < i - 1 || j > i + 3) && (WEL(S, i, j) != 0.0 || WEL(S, i + 1, j) != 0.0))
+                S->bad = 1;
     if (i + 1 <= S->N) {
         int64_t lo = 1, hi = S->n;
         if (!(S->flags & ORC_FULL_ROT)) {
@@ -192,6 +196,10 @@ static void left(bgu *S, int64_t i, double c, double s)
  * j, j+1 of v, and columns j, j+1 of P: P <- P G keeps A = Q W P^T. */
 static void right(bgu *S, int64_t j, double c, double s)
 {
+    if (S->flags & ORC_CHECK_WINDOW)
+        for (int64_t i = 1; i <= S->N; ++i)
+            if ((i < j - 2 || i > j + 2) && (WEL(S, i, j) != 0.0 || WEL(S, i, j + 1) != 0.0))
+                S->bad = 1;
     int64_t lo = 1, hi = S->N;
     if (!(S->flags & ORC_FULL_ROT)) {
         lo = j - 3 > 1 ? j - 3 : 1;

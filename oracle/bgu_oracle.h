@@ -35,6 +35,9 @@ extern "C" {
 #define ORC_CHECK_EVERY 2  /* assert the one-bulge invariant after every rotation (tiny n) */
 #define ORC_FULL_ROT 4     /* rotate whole rows/columns of the working matrix, not a window */
 #define ORC_NO_QP 8        /* do not accumulate into Q and P (schedule/structure studies) */
+#define ORC_CHECK_WINDOW 16 /* assert before each rotation that the rotated rows (columns) of
+                             * the working matrix are zero outside columns i-1..i+3 (rows
+                             * j-2..j+2): the pairs a rotation can change */
 
 /* One recorded rotation: side 0 = left (rows i,i+1 of the working matrix,
  * columns i,i+1 of Q), side 1 = right (columns i,i+1, columns of P).

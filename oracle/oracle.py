@@ -22,6 +22,7 @@ CHECK_PHASES = 1
 CHECK_EVERY = 2
 FULL_ROT = 4
 NO_QP = 8
+CHECK_WINDOW = 16
 
 ORC_OK = 0
 ORC_ESTRUCT = -10

@@ -19,6 +19,7 @@ BDU_OK = 0
 BDU_EINVAL = -1
 BDU_ENOMEM = -2
 BDU_EDEVICE = -3
+BDU_ENONFINITE = -4
 BDU_EBUSY = -5
 
 
@@ -65,6 +66,7 @@ def lib():
         L.bdu_plan_rotations.restype = i64
         L.bdu_autotune.argtypes = [i64, i64, i32, ctypes.POINTER(i64)]
         L.bdu_set_generation_in_lds.argtypes = [i32]
+        L.bdu_set_finite_check.argtypes = [i32]
         L.bdu_tune_save.argtypes = [ctypes.c_char_p]
         L.bdu_tune_load.argtypes = [ctypes.c_char_p]
         L.bdu_handle_tiling.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
@@ -89,7 +91,7 @@ def lib():
                   "bdu_get_tiling", "bdu_plan_stats", "bdu_givens_device", "bdu_timing_enable",
                   "bdu_timing_read", "bdu_batch_create", "bdu_batch_update", "bdu_batch_sync",
                   "bdu_batch_info", "bdu_batch_destroy", "bdu_autotune", "bdu_tune_save", "bdu_tune_load",
-                  "bdu_handle_tiling", "bdu_set_generation_in_lds", "bdu_server_create", "bdu_server_open", "bdu_server_submit",
+                  "bdu_handle_tiling", "bdu_set_generation_in_lds", "bdu_set_finite_check", "bdu_server_create", "bdu_server_open", "bdu_server_submit",
                   "bdu_server_wait", "bdu_server_poll", "bdu_server_drain", "bdu_server_pause",
                   "bdu_server_read", "bdu_server_close", "bdu_server_stats", "bdu_server_destroy"):
             getattr(L, f).restype = i32
@@ -133,6 +135,10 @@ def _ptr(a, matrix: bool = False):
 
 def set_tiling(k0: int, nw: int, rpl: int = 1) -> None:
     _check(lib().bdu_set_tiling(k0, nw, rpl), "bdu_set_tiling")
+
+
+def set_finite_check(on: bool) -> None:
+    _check(lib().bdu_set_finite_check(1 if on else 0), "bdu_set_finite_check")
 
 
 def set_generation_in_lds(allow: bool) -> None:

@@ -14,6 +14,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <initializer_list>
 #include <set>
 #include <tuple>
 #include <vector>
@@ -35,6 +36,7 @@ struct Tuned {
 };
 std::map<std::pair<int64_t, int64_t>, Tuned> g_tuned;
 bool g_gen_lds = true;  // generation keeps its band in LDS when it fits
+bool g_check_finite = false;  // reject NaN / Inf inputs (one extra pass and a sync per call)
 
 struct PlanEntry {
     std::unique_ptr<Plan> plan;
@@ -153,6 +155,7 @@ struct bdu_ctx {
     int rcap = 0;
     int rpl = 1;  // rows per lane in the applier
     bool lds_gen = true;
+    int *flag = nullptr;       // device flag of the non-finite input check
     hipEvent_t ev = nullptr;   // marks this handle's own stream work for a batch to wait on
     hipEvent_t dep = nullptr;  // completion of the last batch step this handle was in
     std::vector<void *> allocs;
@@ -168,6 +171,27 @@ namespace {
             return BDU_EDEVICE;              \
         }                                    \
     } while (0)
+
+bool check_finite_on()
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g_check_finite;
+}
+
+// With the check on: BDU_ENONFINITE if any value of the device ranges
+// (pointer, count) is NaN or infinite, else BDU_OK (waits for the stream).
+int check_finite(bdu_ctx *h, std::initializer_list<std::pair<const double *, int64_t>> ranges, hipStream_t st)
+{
+    if (!check_finite_on()) return BDU_OK;
+    if (hipMemsetAsync(h->flag, 0, sizeof(int), st) != hipSuccess) return BDU_EDEVICE;
+    for (auto &rg : ranges)
+        if (launch_nonfinite(rg.first, rg.second, h->flag, st) != hipSuccess) return BDU_EDEVICE;
+    int f = 0;
+    if (hipMemcpyAsync(&f, h->flag, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return BDU_EDEVICE;
+    return f ? BDU_ENONFINITE : BDU_OK;
+}
 
 // Order the handle's stream after the last batch step that updated it.
 hipError_t wait_dep(bdu_ctx *h)
@@ -524,6 +548,14 @@ int bdu_create(int64_t m, int64_t n, const double *Q, const double *d, const dou
     return create_impl(m, n, Q, d, e, P, k0, nw, rpl, out);
 }
 
+int bdu_set_finite_check(int on)
+{
+    if (on != 0 && on != 1) return BDU_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_check_finite = on != 0;
+    return BDU_OK;
+}
+
 int bdu_set_generation_in_lds(int allow)
 {
     if (allow != 0 && allow != 1) return BDU_EINVAL;
@@ -578,6 +610,7 @@ int create_impl(int64_t m, int64_t n, const double *Q, const double *d, const do
     if (!h->lds_gen) A(dalloc(h.get(), &hd.band, gen_lds_bytes(n, plan->N) / 8));
     A(dalloc(h.get(), &h->d_hd, 1));
     A(dalloc(h.get(), &h->d_self, 1));
+    A(dalloc(h.get(), &h->flag, 1));
     if (a != hipSuccess) {
         for (void *p : h->allocs) (void)hipFree(p);
         (void)hipGetLastError();
@@ -607,6 +640,14 @@ int create_impl(int64_t m, int64_t n, const double *Q, const double *d, const do
     HIPCHK(hp, copy_mat_in(hd.P, ldp, P, n, n, hp->stream));
     HIPCHK(hp, copy_in(hd.d, d, sizeof(double) * n, hp->stream));
     HIPCHK(hp, copy_in(hd.e, e, sizeof(double) * (n - 1), hp->stream));
+    {
+        const int fin = check_finite(hp, {{hd.Q, ldq * m}, {hd.P, ldp * n}, {hd.d, n}, {hd.e, n - 1}}, hp->stream);
+        if (fin != BDU_OK) {
+            (void)hipStreamSynchronize(hp->stream);
+            for (void *p : hp->allocs) (void)hipFree(p);
+            return fin;
+        }
+    }
     HIPCHK(hp, launch_fill_identity(hd.csL, plan->slots[0] + slack, hp->stream));
     HIPCHK(hp, launch_fill_identity(hd.csR, plan->slots[1] + slack, hp->stream));
     HIPCHK(hp, hipMemcpyAsync(h->d_hd, &hd, sizeof(HandleDev), hipMemcpyHostToDevice, hp->stream));
@@ -653,6 +694,8 @@ int bdu_update(bdu_handle h, const double *B, const double *C, int r)
     if (st != BDU_OK) return st;
     HIPCHK(h, copy_in(h->hd.bst, B, sizeof(double) * h->m * r, h->stream));
     HIPCHK(h, copy_in(h->hd.cst, C, sizeof(double) * h->n * r, h->stream));
+    st = check_finite(h, {{h->hd.bst, h->m * r}, {h->hd.cst, h->n * r}}, h->stream);
+    if (st != BDU_OK) return st;
     for (int p = 0; p < r; ++p) {
         st = pass_single(h, p, true);
         if (st != BDU_OK) return st;
@@ -667,6 +710,8 @@ int bdu_update_projected(bdu_handle h, const double *u, const double *v)
     HIPCHK(h, wait_dep(h));
     HIPCHK(h, copy_in(h->hd.u, u, sizeof(double) * h->m, h->stream));
     HIPCHK(h, copy_in(h->hd.v, v, sizeof(double) * h->n, h->stream));
+    const int st = check_finite(h, {{h->hd.u, h->m}, {h->hd.v, h->n}}, h->stream);
+    if (st != BDU_OK) return st;
     return pass_single(h, 0, false);
 }
 
@@ -794,6 +839,14 @@ int bdu_batch_update(bdu_batch b, const double *const *Bs, const double *const *
             copy_in(h->hd.cst, Cs[i], sizeof(double) * h->n * rs[i], st) != hipSuccess)
             return fail();
     }
+    // non-finite inputs reject the whole step before any handle changes
+    for (int i = 0; i < count; ++i) {
+        if (rs[i] == 0) continue;
+        bdu_ctx *h = b->hs[i];
+        const int fin = check_finite(h, {{h->hd.bst, h->m * rs[i]}, {h->hd.cst, h->n * rs[i]}}, st);
+        if (fin == BDU_ENONFINITE) return fin;
+        if (fin != BDU_OK) return fail();
+    }
     // this step's ranks (the pinned staging is reused once the last copy is done)
     if (b->steps > 0 && hipEventSynchronize(b->ranks_copied) != hipSuccess) return fail();
     for (int i = 0; i < count; ++i) b->h_ranks[b->pos[i]] = rs[i];
@@ -903,7 +956,7 @@ int bdu_autotune(int64_t m, int64_t n, int streams, int64_t *out)
     std::vector<const double *> Bs(streams, db), Cs(streams, dc);
     std::vector<int> rs(streams, 1);
     Tuned best{0, 0, 0, 0.0};
-    const int k0s[] = {6, 12}, nws[] = {1, 2, 3, 4, 7, 8, 15}, rpls[] = {1, 2};
+    const int k0s[] = {6, 12, 18}, nws[] = {1, 2, 3, 4, 5, 7, 8, 15}, rpls[] = {1, 2};
     int status = BDU_OK;
     for (int k0 : k0s)
         for (int nw : nws)

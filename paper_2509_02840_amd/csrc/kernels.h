@@ -18,6 +18,8 @@ hipError_t launch_apply(HandleDev *const *hs, int count, int max_panels, int k0,
 // One-time kernel attributes; call before capturing launches in a graph.
 hipError_t prepare_kernels();
 hipError_t launch_fill_identity(double2 *p, int64_t count, hipStream_t st);
+// flag[0] = 1 if any of p[0..count) is NaN or infinite (caller clears flag).
+hipError_t launch_nonfinite(const double *p, int64_t count, int *flag, hipStream_t st);
 bool tiling_supported(int k0, int nw, int rpl);
 hipError_t launch_givens(const double *a, const double *b, int mode, double *c, double *s, double *r,
                          int64_t count, hipStream_t st);

@@ -220,8 +220,9 @@ __device__ __forceinline__ ChainReg load_chain(const GenChain *chains, int idx)
 // are the down-right pattern R(ii+2) [(ii,ii+3) into (ii,ii+2)], L(ii+3)
 // [(ii+4,ii+2) into (ii+3,ii+2)], ii = i0 + 3*(ss>>1), whose first rotation
 // acts one column (P2A) or one row (P2B) further on.  A left rotation on rows
-// (i, i+1) rotates the band pairs in columns i-2..i+4, a right rotation on
-// columns (j, j+1) those in rows j-3..j+3, plus the matching u or v pair.
+// (i, i+1) rotates the band pairs in columns i-1..i+3, a right rotation on
+// columns (j, j+1) those in rows j-2..j+2 (the only pairs the schedule can
+// make nonzero), plus the matching u or v pair.
 template <bool IN_LDS>
 __global__ __launch_bounds__(kGenThreads) void gen_kernel(HandleDev *const *hs, Gate gate)
 {
@@ -305,28 +306,33 @@ __global__ __launch_bounds__(kGenThreads) void gen_kernel(HandleDev *const *hs, 
                 }
                 double c, sn, rr;
                 givens(S[ga], S[gb], mode, c, sn, rr);
-                double xv[7], yv[7], ux = S[vb], uy = S[vb + 1];
+                // pairs q = 1..5: columns i-1..i+3 of a left rotation, rows
+                // j-2..j+2 of a right one; the schedule keeps the other two
+                // pairs of the window zero, and rotating zeros leaves them so
+                double xv[6], yv[6], ux = S[vb], uy = S[vb + 1];
 #pragma unroll
-                for (int q = 0; q < 7; ++q) {
-                    xv[q] = q <= 5 ? S[xb + q * st] : 0.0;
-                    yv[q] = q >= 1 ? S[yb + q * st] : 0.0;
+                for (int q = 1; q <= 5; ++q) {
+                    xv[q] = S[xb + q * st];
+                    yv[q] = S[yb + q * st];
                 }
 #pragma unroll
-                for (int q = 0; q < 7; ++q) {
+                for (int q = 1; q <= 5; ++q) {
                     rot(c, sn, xv[q], yv[q]);
-                    if (q <= 5) S[xb + q * st] = xv[q];
-                    if (q >= 1) S[yb + q * st] = yv[q];
+                    S[xb + q * st] = xv[q];
+                    S[yb + q * st] = yv[q];
                 }
                 rot(c, sn, ux, uy);
                 S[vb] = ux;
                 S[vb + 1] = uy;
                 S[ga] = mode == 1 ? 0.0 : rr;
                 S[gb] = mode == 1 ? rr : 0.0;
-                // slot of this rotation in the applier layout
+                // slot of this rotation in the applier layout: one 16-byte store
                 GLOBAL double *cs = side == 0 ? csL : csR;
                 const int64_t slot = (side == 0 ? g.slot0 : g.slot1) + (int64_t)(s >> 1) * K;
-                cs[2 * slot] = c;
-                cs[2 * slot + 1] = sn;
+                HIP_vector_base<double, 2>::Native_vec_ value;
+                value[0] = c;
+                value[1] = sn;
+                *(GLOBAL HIP_vector_base<double, 2>::Native_vec_ *)(cs + 2 * slot) = value;
             }
             if (s == g.len - 1) {
                 ci += nt;
@@ -785,8 +791,8 @@ __device__ __forceinline__ void sweep_memory(GLOBAL double *__restrict__ X, int 
 }
 
 template <int K0, int NW, int R>
-__global__ __launch_bounds__(64 * (NW + 1)) __attribute__((amdgpu_waves_per_eu(R == 2 ? 2 : 4))) void
-apply_staged_kernel(HandleDev *const *hs, Gate gate)
+__global__ __launch_bounds__(64 * (NW + 1)) __attribute__((amdgpu_waves_per_eu(R == 2 ? 2 : (K0 > 12 ? 3 : 4))))
+void apply_staged_kernel(HandleDev *const *hs, Gate gate)
 {
     using T = Staged<K0, NW, R>;
     const int total = gridDim.x * gridDim.y;
@@ -928,11 +934,15 @@ static hipError_t launch_staged_t(HandleDev *const *hs, int count, int max_panel
 }
 
 // nw in {1, 2, 4, 8}: nw wavefronts, each loading or storing what it needs;
-// nw in {3, 7, 15} (k0 = 12): the staged kernel, nw compute wavefronts and a
-// memory wavefront.
+// nw in {3, 5, 7, 15}: the staged kernel, nw compute wavefronts and a memory
+// wavefront (k0 = 12: nw in {3, 7, 15}, rpl 2 only for nw <= 7; k0 = 18:
+// nw in {3, 5, 7}, rpl 1).
 bool tiling_supported(int k0, int nw, int rpl)
 {
-    if (nw == 3 || nw == 7 || nw == 15) return k0 == 12 && (rpl == 1 || (rpl == 2 && nw != 15));
+    if (nw == 3 || nw == 5 || nw == 7 || nw == 15) {
+        if (k0 == 12) return nw != 5 && (rpl == 1 || (rpl == 2 && nw != 15));
+        return k0 == 18 && nw != 15 && rpl == 1;
+    }
     if (k0 == 6 && nw == 8 && rpl == 2) return false;  // its LDS ring exceeds 160 KB
     return (k0 == 6 || k0 == 12) && (nw == 1 || nw == 2 || nw == 4 || nw == 8) && (rpl == 1 || rpl == 2);
 }
@@ -951,8 +961,29 @@ hipError_t launch_apply(HandleDev *const *hs, int count, int max_panels, int k0,
     if (k0 == A && nw == B && rpl == C) return launch_staged_t<A, B, C>(hs, count, max_panels, gate, st);
     BDU_STAGED_CASE(12, 3, 1) BDU_STAGED_CASE(12, 7, 1) BDU_STAGED_CASE(12, 15, 1)
     BDU_STAGED_CASE(12, 3, 2) BDU_STAGED_CASE(12, 7, 2)
+    BDU_STAGED_CASE(18, 3, 1) BDU_STAGED_CASE(18, 5, 1) BDU_STAGED_CASE(18, 7, 1)
 #undef BDU_STAGED_CASE
     return hipErrorInvalidValue;
+}
+
+// flag[0] = 1 if any of the count values is NaN or infinite (flag[0] is
+// cleared by the caller; every writer stores the same value).
+__global__ void nonfinite_kernel(const double *p, int64_t count, int *flag)
+{
+    bool bad = false;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        bad |= !isfinite(p[i]);
+    if (bad) flag[0] = 1;
+}
+
+hipError_t launch_nonfinite(const double *p, int64_t count, int *flag, hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(nonfinite_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p, count, flag);
+    return hipGetLastError();
 }
 
 hipError_t launch_fill_identity(double2 *p, int64_t count, hipStream_t st)

@@ -53,36 +53,58 @@ std::unique_ptr<Plan> build_plan(int64_t m, int64_t n, int K0, int NW, int gen_t
     P->nspike = (m > n) ? (m - n - 1) : 0;
 
     // ---- generation ticks -------------------------------------------------
-    const int off = 5;  // band-row line covers rows -4 .. N+5
-    std::vector<int64_t> last(N + 12, -1);
+    // A chain starts at the earliest tick at which each of its rotations runs
+    // after every earlier rotation (schedule order) that touches one of the
+    // same entries: a band cell (rows x columns within offsets -2..3), u or v.
+    // A left rotation on rows (i, i+1) touches columns i-1..i+3 of them and
+    // u_i, u_{i+1}; a right rotation on columns (j, j+1) rows j-2..j+2 and
+    // v_j, v_{j+1} (the only entries the schedule can make nonzero there).
+    const int off = 5;  // rows and columns -4 .. N+5
+    const int W = N + 12;
+    std::vector<int64_t> lastcell((size_t)W * 6, -1), lastu(W, -1), lastv(W, -1);
+    auto cells = [&](const Rot &r, auto &&fn) {
+        if (r.side == 0) {
+            for (int row = r.i; row <= r.i + 1; ++row)
+                for (int c = r.i - 1; c <= r.i + 3; ++c)
+                    if (c - row >= -2 && c - row <= 3) fn(lastcell[(size_t)(row + off) * 6 + (c - row + 2)]);
+            fn(lastu[r.i + off]);
+            fn(lastu[r.i + 1 + off]);
+        } else {
+            for (int row = r.i - 2; row <= r.i + 2; ++row)
+                for (int c = r.i; c <= r.i + 1; ++c)
+                    if (c - row >= -2 && c - row <= 3) fn(lastcell[(size_t)(row + off) * 6 + (c - row + 2)]);
+            fn(lastv[r.i + off]);
+            fn(lastv[r.i + 1 + off]);
+        }
+    };
+    auto fold_cells = [&](auto &&fn) {  // (N-1, n), (N, n), u_{N-1}, u_N, v_n
+        fn(lastcell[(size_t)(N - 1 + off) * 6 + (nn - (N - 1) + 2)]);
+        fn(lastcell[(size_t)(N + off) * 6 + (nn - N + 2)]);
+        fn(lastu[N - 1 + off]);
+        fn(lastu[N + off]);
+        fn(lastv[nn + off]);
+    };
     std::vector<int64_t> lane_free(gen_threads, 0);
     int64_t tend = 0;
     for (size_t c = 0; c < ch.size(); ++c) {
         GenChain &g = ch[c];
         int64_t tau0 = 0;
         for (int s = 0; s < g.len; ++s) {
-            int lo, hi;
-            if (g.type == CH_FOLD) {
-                lo = N - 1;
-                hi = N;
-            } else {
-                footprint(decode(g.type, g.param, s), &lo, &hi);
-            }
-            for (int x = lo; x <= hi; ++x) tau0 = std::max(tau0, last[x + off] + 1 - s);
+            auto need = [&](int64_t &t) { tau0 = std::max(tau0, t + 1 - s); };
+            if (g.type == CH_FOLD) fold_cells(need);
+            else cells(decode(g.type, g.param, s), need);
         }
         int lane = (int)(c % gen_threads);
         tau0 = std::max(tau0, lane_free[lane]);
         for (int s = 0; s < g.len; ++s) {
-            int lo, hi;
+            auto mark = [&](int64_t &t) { t = std::max(t, tau0 + s); };
             if (g.type == CH_FOLD) {
-                lo = N - 1;
-                hi = N;
+                fold_cells(mark);
             } else {
                 Rot r = decode(g.type, g.param, s);
-                footprint(r, &lo, &hi);
+                cells(r, mark);
                 if (r.side == 0) ++P->nleft; else ++P->nright;
             }
-            for (int x = lo; x <= hi; ++x) last[x + off] = std::max(last[x + off], tau0 + s);
         }
         lane_free[lane] = tau0 + g.len;
         g.tau0 = (int32_t)tau0;

@@ -29,18 +29,4 @@ struct Plan {
 // Build (no device work).  gen_threads is the number of generation threads.
 std::unique_ptr<Plan> build_plan(int64_t m, int64_t n, int K0, int NW, int gen_threads);
 
-// Footprint of a rotation on the band-row line (conservative): left rotation
-// L(i) touches rows i, i+1 (and u_i, u_{i+1}); right rotation R(j) touches
-// rows j-3..j+3 of columns j, j+1 (and v_j, v_{j+1}).
-inline void footprint(const Rot &r, int *lo, int *hi)
-{
-    if (r.side == 0) {
-        *lo = r.i;
-        *hi = r.i + 1;
-    } else {
-        *lo = r.i - 3;
-        *hi = r.i + 3;
-    }
-}
-
 }  // namespace bdu

@@ -158,7 +158,8 @@ def test_batch_rejects_bad_arguments(bdu):
 
 
 SUPPORTED = [(k0, nw, rpl) for k0 in (6, 12) for nw in (1, 2, 4, 8) for rpl in (1, 2)
-             if (k0, nw, rpl) != (6, 8, 2)] + [(12, 3, 1), (12, 7, 1), (12, 15, 1), (12, 3, 2), (12, 7, 2)]
+             if (k0, nw, rpl) != (6, 8, 2)] + [(12, 3, 1), (12, 7, 1), (12, 15, 1), (12, 3, 2), (12, 7, 2),
+                                               (18, 3, 1), (18, 5, 1), (18, 7, 1)]
 
 
 def test_autotune_records_the_tiling_auto_handles_use(bdu, oracle):

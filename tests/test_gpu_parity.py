@@ -128,7 +128,7 @@ def test_tiling_does_not_change_results(bdu):
     saved = bdu.get_tiling()
     try:
         for tk in [(6, 1, 1), (12, 1, 1), (12, 2, 2), (12, 4, 2), (6, 4, 1), (12, 8, 2), (6, 8, 1), (12, 4, 1),
-                   (12, 3, 1), (12, 7, 1), (12, 15, 1), (12, 3, 2), (12, 7, 2)]:
+                   (12, 3, 1), (12, 7, 1), (12, 15, 1), (12, 3, 2), (12, 7, 2), (18, 5, 1)]:
             bdu.set_tiling(*tk)
             h = bdu.Handle(f.Q, f.d, f.e, f.P)
             h.update(B, C)
@@ -141,7 +141,7 @@ def test_tiling_does_not_change_results(bdu):
             _eq("tiling", x, y)
 
 
-STAGED = [(12, 3, 1), (12, 7, 1), (12, 15, 1), (12, 3, 2), (12, 7, 2)]
+STAGED = [(12, 3, 1), (12, 7, 1), (12, 15, 1), (12, 3, 2), (12, 7, 2), (18, 3, 1), (18, 5, 1), (18, 7, 1)]
 
 
 @pytest.mark.parametrize("tk", STAGED)
@@ -289,3 +289,69 @@ def test_one_stream_full_size(bdu, oracle):
     assert np.linalg.norm(Q.T @ Q - np.eye(m)) <= 1e-12 * np.sqrt(m)
     assert np.linalg.norm(P.T @ P - np.eye(n)) <= 1e-12 * np.sqrt(n)
     assert abs(np.sqrt(d @ d + e @ e) - np.linalg.norm(Aplus)) <= 1e-13 * np.linalg.norm(Aplus)
+
+
+@pytest.mark.parametrize("m,n", [(700, 5), (513, 2), (260, 3), (1030, 64)])
+def test_spike_heavy_shapes(bdu, oracle, m, n):
+    """m much larger than n: the spike dominates the left rotations."""
+    f = W.factorization(m, n, 90 + n)
+    (B, C), = W.gaussian_updates(m, n, 1, 91 + n, r=2)
+    ref = oracle.State(f.Q, f.d, f.e, f.P)
+    oracle.bgu_update(ref, B, C)
+    saved = bdu.get_tiling()
+    try:
+        for tk in [(12, 7, 1), (12, 8, 1), (6, 1, 1), (12, 3, 2)]:
+            bdu.set_tiling(*tk)
+            h = bdu.Handle(f.Q, f.d, f.e, f.P)
+            h.update(B, C)
+            for nm, x, y in zip("QdeP", h.read(), (ref.Q, ref.d, ref.e, ref.P)):
+                _eq(f"{tk} {nm}", x, y)
+            h.close()
+    finally:
+        bdu.set_tiling(*saved)
+
+
+def test_nonfinite_inputs_are_rejected(bdu, oracle):
+    m, n = 60, 50
+    f = W.factorization(m, n, 95)
+    (B, C), = W.gaussian_updates(m, n, 1, 96, r=2)
+    bdu.set_finite_check(True)
+    try:
+        h = bdu.Handle(f.Q, f.d, f.e, f.P)
+        before = h.read()
+        for bad in ("B", "C"):
+            Bb, Cb = B.copy(order="F"), C.copy(order="F")
+            (Bb if bad == "B" else Cb)[3, 1] = np.nan if bad == "B" else np.inf
+            with pytest.raises(bdu.BduError) as ei:
+                h.update(Bb, Cb)
+            assert ei.value.status == bdu.BDU_ENONFINITE
+            for nm, x, y in zip("QdeP", h.read(), before):
+                _eq(f"unchanged after bad {bad}: {nm}", x, y)
+        u = np.ones(m)
+        u[7] = -np.inf
+        with pytest.raises(bdu.BduError):
+            h.update_projected(u, np.ones(n))
+        h.update(B, C)  # finite inputs still go through
+        ref = oracle.State(f.Q, f.d, f.e, f.P)
+        oracle.bgu_update(ref, B, C)
+        for nm, x, y in zip("QdeP", h.read(), (ref.Q, ref.d, ref.e, ref.P)):
+            _eq(f"after a good update: {nm}", x, y)
+        g = W.factorization(m, n, 97)
+        d_bad = g.d.copy()
+        d_bad[0] = np.nan
+        with pytest.raises(bdu.BduError) as ei:
+            bdu.Handle(g.Q, d_bad, g.e, g.P)
+        assert ei.value.status == bdu.BDU_ENONFINITE
+        h2 = bdu.Handle(g.Q, g.d, g.e, g.P)
+        b2 = h2.read()
+        Bb = B.copy(order="F")
+        Bb[0, 0] = np.nan
+        with pytest.raises(bdu.BduError) as ei:
+            bdu.update_batched([h2, h], [B, Bb], [C, C])
+        assert ei.value.status == bdu.BDU_ENONFINITE
+        for nm, x, y in zip("QdeP", h2.read(), b2):
+            _eq(f"batch member unchanged: {nm}", x, y)
+        h.close()
+        h2.close()
+    finally:
+        bdu.set_finite_check(False)

@@ -41,15 +41,18 @@ def test_decoded_schedule_is_the_oracle_sequence(oracle, m, n):
 
 
 def _cells(side, i, m, n, N):
-    """Entries a step reads and writes: ('W', r, c), ('u', i), ('v', j)."""
+    """Entries a step reads and writes: ('W', r, c), ('u', i), ('v', j).  The
+    windows are those the schedule can make nonzero (columns i-1..i+3 of a
+    left rotation, rows j-2..j+2 of a right one), which the oracle pin
+    test_rotation_windows_hold_every_nonzero checks."""
     out = []
-    if side == 0:  # left rotation on rows i, i+1; columns i-2..i+4 of the band window
-        for c in range(max(1, i - 2), min(n, i + 4) + 1):
+    if side == 0:  # left rotation on rows i, i+1
+        for c in range(max(1, i - 1), min(n, i + 3) + 1):
             if i + 1 <= N:
                 out += [("W", i, c), ("W", i + 1, c)]
         out += [("u", i), ("u", i + 1)]
-    elif side == 1:  # right rotation on columns i, i+1; rows i-3..i+3
-        for r in range(max(1, i - 3), min(N, i + 3) + 1):
+    elif side == 1:  # right rotation on columns i, i+1
+        for r in range(max(1, i - 2), min(N, i + 2) + 1):
             out += [("W", r, i), ("W", r, i + 1)]
         out += [("v", i), ("v", i + 1)]
     else:  # fold: (N-1, n), (N, n), u_{N-1}, u_N, v_n
@@ -224,10 +227,10 @@ def _staged_protocol_violations(K0, NW, lmax, RC=15, NCS=3):
     return bad
 
 
-@pytest.mark.parametrize("NW", [3, 7, 15])
+@pytest.mark.parametrize("K0,NW,RC", [(12, 3, 15), (12, 7, 15), (12, 15, 15), (18, 3, 21), (18, 5, 21), (18, 7, 21)])
 @pytest.mark.parametrize("lmax", [0, 1, 2, 5, 17, 40, 100, 257])
-def test_staged_lds_protocol_is_race_free(NW, lmax):
-    assert _staged_protocol_violations(12, NW, lmax) == []
+def test_staged_lds_protocol_is_race_free(K0, NW, RC, lmax):
+    assert _staged_protocol_violations(K0, NW, lmax, RC=RC) == []
 
 
 def test_staged_protocol_checker_sees_a_race():
@@ -235,3 +238,8 @@ def test_staged_protocol_checker_sees_a_race():
     its last read; a coefficient ring of one front likewise."""
     assert _staged_protocol_violations(12, 7, 100, RC=9) != []
     assert _staged_protocol_violations(12, 7, 100, NCS=1) != []
+
+
+def test_finite_check_switch_validates_its_argument():
+    assert bdu.lib().bdu_set_finite_check(2) == bdu.BDU_EINVAL
+    assert bdu.lib().bdu_set_finite_check(0) == bdu.BDU_OK

@@ -133,6 +133,46 @@ def test_one_bulge_at_a_time_and_bidiagonal(oracle, m, n):
     assert status == oracle.ORC_OK
 
 
+WINDOW_SHAPES = SHAPES + [(45, 40), (64, 64), (65, 64), (100, 37), (130, 97), (200, 200)]
+
+
+@pytest.mark.parametrize("m,n", WINDOW_SHAPES)
+def test_rotation_windows_hold_every_nonzero(oracle, m, n):
+    """Before each rotation the rotated rows (left, rows i and i+1) are zero
+    outside columns i-1..i+3 and the rotated columns (right, j and j+1) zero
+    outside rows j-2..j+2: a rotation changes at most these five pairs, which
+    is all the generator and its dependency model touch.  Random dense
+    projections, a zero start and a rank-3 stream."""
+    f = W.factorization(m, n, 15)
+    rng = np.random.default_rng(16)
+    flags = oracle.CHECK_WINDOW | oracle.NO_QP
+    st = oracle.State(f.Q, f.d, f.e, f.P)
+    for _ in range(3):
+        _, _, status = oracle.bgu_pass(st, rng.standard_normal(m), rng.standard_normal(n), flags=flags,
+                                       check_status=False)
+        assert status == oracle.ORC_OK
+    z = W.zero_start(m, n)
+    st = oracle.State(z.Q, z.d, z.e, z.P)
+    for _ in range(3):
+        _, _, status = oracle.bgu_pass(st, rng.standard_normal(m), rng.standard_normal(n), flags=flags,
+                                       check_status=False)
+        assert status == oracle.ORC_OK
+
+
+def test_window_check_catches_a_wrong_chase(oracle):
+    """A chase stepping by 2 instead of 3 leaves nonzeros outside the windows."""
+    f = W.factorization(30, 30, 17)
+    rng = np.random.default_rng(18)
+    st = oracle.State(f.Q, f.d, f.e, f.P)
+    oracle.set_mutation(3)
+    try:
+        _, _, status = oracle.bgu_pass(st, rng.standard_normal(30), rng.standard_normal(30),
+                                       flags=oracle.CHECK_WINDOW | oracle.NO_QP, check_status=False)
+    finally:
+        oracle.set_mutation(0)
+    assert status == oracle.ORC_ESTRUCT
+
+
 @pytest.mark.parametrize("n", [4, 5, 12, 20, 31, 60])
 def test_phase2_chase_count_is_2n_minus_3(oracle, n):
     f = W.factorization(n, n, 13)
