@@ -36,10 +36,30 @@ struct Gate {
 
 constexpr int kGenThreads = 256;
 
+// Band storage of the generation kernel: row r (1-based, -3..N+4) starts at
+// band_row(r) and holds the entries in columns r-2..r+3, column c at offset
+// c - r + 2.  The extra double every three rows spreads the rows that
+// neighbouring lanes touch in one tick (about seven rows apart) over the LDS
+// banks (with a plain stride of six they fall on a few banks), and keeps
+// band_row(r + 3) = band_row(r) + 19, so a chain's addresses move by a
+// constant from one step of its pattern to the next.
+__host__ __device__ inline int band_row(int r)
+{
+    return 6 * (r + 3) + (r + 3) / 3;
+}
+
+constexpr int kBandStep3 = 19;  // band_row(r + 3) - band_row(r)
+
+// Doubles of the band (rows -3..N+4); u (N + 8) and v (n + 8) follow.
+__host__ __device__ inline int64_t band_doubles(int64_t N)
+{
+    return 6 * (N + 8) + (N + 8) / 3 + 2;
+}
+
 // LDS bytes the generation kernel needs for n columns and N rows.
 inline int64_t gen_lds_bytes(int64_t n, int64_t N)
 {
-    return 8 * (6 * (N + 8) + (N + 8) + (n + 8) + 2);
+    return 8 * (band_doubles(N) + (N + 8) + (n + 8) + 2);
 }
 
 constexpr int64_t kMaxGenLds = 160 * 1024;
