@@ -34,7 +34,7 @@ struct Gate {
     int32_t pass;
 };
 
-constexpr int kGenThreads = 256;
+constexpr int kGenThreads = 1024;  // at n = 2048, 256 threads leave chains waiting for a free thread
 
 // Band storage of the generation kernel: row r (1-based, -3..N+4) starts at
 // band_row(r) and holds the entries in columns r-2..r+3, column c at offset
