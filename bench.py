@@ -9,7 +9,8 @@ update is b ~ N(0,1)/sqrt(m), c ~ N(0,1)/sqrt(n).
   step is one rank-1 update of every stream, queued with one
   bdu_batch_update call and waited for.  value = S * steps / time.  The
   applier tiling is autotuned on S synthetic streams beforehand (untimed).
-- plain: one stream, one bdu_update per rank-1 update, timed beside it.
+- plain: one stream, one bdu_update per rank-1 update, timed beside it, with
+  the tiling autotuned on one stream.
 
 A step runs the whole path: projection, generation, and accumulation into Q
 and P.  Inputs are resident in device memory before the timed region.  The
@@ -338,11 +339,16 @@ def main() -> int:
     if args.serve > 0:
         return serve(torch, bdu, args)
     n = args.n
-    tune = None
+    tune = plain_tune = None
     if args.tiling:
         bdu.set_tiling(*[int(x) for x in args.tiling.split(",")])
     elif not args.no_autotune:
-        # untimed: every applier tiling on S synthetic streams of this shape
+        # untimed: every applier tiling on one stream (the plain leg's
+        # workload: latency favours deeper pipelines per panel), then on S
+        # synthetic streams of this shape (the batched leg's)
+        t0 = time.perf_counter()
+        plain_tune = bdu.autotune(n, n, 1)
+        plain_tune["seconds"] = time.perf_counter() - t0
         t0 = time.perf_counter()
         tune = bdu.autotune(n, n, args.streams)
         tune["seconds"] = time.perf_counter() - t0
@@ -354,7 +360,12 @@ def main() -> int:
 
     # ---- plain: one stream, one update per call --------------------------
     Q, d, e, P = factory.make()
+    if plain_tune:
+        bdu.set_tiling(plain_tune["k0"], plain_tune["nw"], plain_tune["rpl"])
     h = bdu.Handle(Q, d, e, P)
+    plain_tiling = h.tiling()
+    if plain_tune:
+        bdu.set_tiling_auto()
     del Q, P
     pb, pc = make_updates(torch, gen, n, args.warmup + args.plain_steps)
     torch.cuda.synchronize()
@@ -445,7 +456,7 @@ def main() -> int:
         "config": {"workload": f"batched BGU rank-1 updates, {S} square streams m=n={n}, "
                                f"one update per stream per step; plain = 1 stream",
                    "m": n, "n": n, "streams": S, "rank": 1, "tiling": [k0, nw, rpl],
-                   "autotune": tune},
+                   "autotune": tune, "plain_tiling": list(plain_tiling), "plain_autotune": plain_tune},
         "plain_updates_per_s": plain_ups,
         "batched_over_plain": value / plain_ups,
         "p50_ms": 1e3 * float(np.percentile(step_lat, 50)),
