@@ -66,9 +66,10 @@ __device__ __forceinline__ BlockDesc load_block(const BlockDesc *p, int b)
 // Written with selects only: both the identity and the general result are
 // computed (the general one may be NaN when a = b = 0 and is then discarded),
 // so a wavefront runs one straight sequence whatever its lanes' data.
-__device__ __forceinline__ void givens(double a, double b, int mode, double &c, double &s, double &r)
+template <int MODE>
+__device__ __forceinline__ void givens_m(double a, double b, double &c, double &s, double &r)
 {
-    const bool m1 = mode == 1;
+    constexpr bool m1 = MODE == 1;
     const double fa = fabs(a), fb = fabs(b);
     const double big = fa > fb ? fa : fb;
     const bool hi = big > 0x1p500, lo = big < 0x1p-500;
@@ -81,6 +82,14 @@ __device__ __forceinline__ void givens(double a, double b, int mode, double &c, 
     c = ident ? 1.0 : p;
     s = ident ? 0.0 : (m1 ? q : -q);
     r = ident ? (m1 ? b : a) : rs * unsc;
+}
+
+__device__ __forceinline__ void givens(double a, double b, int mode, double &c, double &s, double &r)
+{
+    if (mode == 1)
+        givens_m<1>(a, b, c, s, r);
+    else
+        givens_m<2>(a, b, c, s, r);
 }
 
 __device__ __forceinline__ void rot(double c, double s, double &x, double &y)
@@ -373,6 +382,74 @@ __global__ __launch_bounds__(kGenThreads) void gen_kernel(HandleDev *const *hs, 
     if (ci < nch) start();
 
     double kx0 = 0.0, kx1 = 0.0, ky0 = 0.0, ky1 = 0.0;  // slots 0, 1 carried from the previous rotation
+    // One rotation with its window, for one phase (the phase is uniform
+    // across a wavefront except where phase 2 starts, so a wavefront
+    // normally runs one of the two bodies).
+    auto rotate = [&](RotAddr<BP> &a, bool first, bool last, auto phase) {
+        constexpr bool P1 = decltype(phase)::value;
+        double xv[5], yv[5];
+#pragma unroll
+        for (int q = 2; q < 5; ++q) {
+            xv[q] = *a.x[q];
+            yv[q] = *a.y[q];
+        }
+        double ux = a.vb[0], uy = a.vb[1];
+        // local copies: a select between captured variables would become a
+        // load through a selected address
+        xv[0] = kx0;
+        xv[1] = kx1;
+        yv[0] = ky0;
+        yv[1] = ky1;
+        double va = P1 ? xv[1] : xv[0], vb = P1 ? yv[1] : yv[0];
+        if (first) {
+            xv[0] = *a.x[0];
+            xv[1] = *a.x[1];
+            yv[0] = *a.y[0];
+            yv[1] = *a.y[1];
+            va = P1 ? ux : xv[1];
+            vb = P1 ? uy : yv[1];
+        }
+        double c, sn, rr;
+        givens_m<P1 ? 1 : 2>(va, vb, c, sn, rr);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) rot(c, sn, xv[q], yv[q]);
+        rot(c, sn, ux, uy);
+        // the generating pair becomes (0, r) (mode 1) or (r, 0) (mode 2)
+        if (P1) {
+            ux = first ? 0.0 : ux;
+            uy = first ? rr : uy;
+            xv[1] = first ? xv[1] : 0.0;
+            yv[1] = first ? yv[1] : rr;
+        } else {
+            xv[1] = first ? rr : xv[1];
+            yv[1] = first ? 0.0 : yv[1];
+            xv[0] = first ? xv[0] : rr;
+            yv[0] = first ? yv[0] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            *a.x[q] = xv[q];
+            *a.y[q] = yv[q];
+        }
+        a.vb[0] = ux;
+        a.vb[1] = uy;
+        if (last) {
+            *a.x[3] = xv[3];
+            *a.y[3] = yv[3];
+            *a.x[4] = xv[4];
+            *a.y[4] = yv[4];
+        }
+        kx0 = xv[3];
+        kx1 = yv[3];
+        ky0 = xv[4];
+        ky1 = yv[4];
+        // one 16-byte store of the rotation's (c, s)
+        HIP_vector_base<double, 2>::Native_vec_ value;
+        value[0] = c;
+        value[1] = sn;
+        *(GLOBAL HIP_vector_base<double, 2>::Native_vec_ *)a.cs = value;
+    };
+
     auto tick = [&](RotAddr<BP> &a, int t) {
         const bool live = ci < nch && t >= g.tau0;
         if (live) {
@@ -381,66 +458,10 @@ __global__ __launch_bounds__(kGenThreads) void gen_kernel(HandleDev *const *hs, 
                 const int fa = band_cell(N - 1, n), fb = band_cell(N, n);
                 S[fa] = fma(S[UO + N - 1 + 3], S[VO + n + 3], S[fa]);
                 S[fb] = fma(S[UO + N + 3], S[VO + n + 3], S[fb]);
+            } else if (m1) {
+                rotate(a, t == g.tau0, t == tend, std::true_type{});
             } else {
-                const bool first = t == g.tau0, last = t == tend;
-                double xv[5], yv[5];
-#pragma unroll
-                for (int q = 2; q < 5; ++q) {
-                    xv[q] = *a.x[q];
-                    yv[q] = *a.y[q];
-                }
-                double ux = a.vb[0], uy = a.vb[1];
-                // local copies: a select between captured variables would
-                // become a load through a selected address
-                xv[0] = kx0;
-                xv[1] = kx1;
-                yv[0] = ky0;
-                yv[1] = ky1;
-                double va = m1 ? xv[1] : xv[0], vb = m1 ? yv[1] : yv[0];
-                if (first) {
-                    xv[0] = *a.x[0];
-                    xv[1] = *a.x[1];
-                    yv[0] = *a.y[0];
-                    yv[1] = *a.y[1];
-                    va = m1 ? ux : xv[1];
-                    vb = m1 ? uy : yv[1];
-                }
-                double c, sn, rr;
-                givens(va, vb, m1 ? 1 : 2, c, sn, rr);
-#pragma unroll
-                for (int q = 0; q < 5; ++q) rot(c, sn, xv[q], yv[q]);
-                rot(c, sn, ux, uy);
-                // the generating pair becomes (0, r) (mode 1) or (r, 0) (mode 2)
-                const double g0 = m1 ? 0.0 : rr, g1 = m1 ? rr : 0.0;
-                const bool on_u = first && m1, on_1 = first != m1;
-                ux = on_u ? g0 : ux;
-                uy = on_u ? g1 : uy;
-                xv[1] = !on_u && on_1 ? g0 : xv[1];
-                yv[1] = !on_u && on_1 ? g1 : yv[1];
-                xv[0] = !on_u && !on_1 ? g0 : xv[0];
-                yv[0] = !on_u && !on_1 ? g1 : yv[0];
-#pragma unroll
-                for (int q = 0; q < 3; ++q) {
-                    *a.x[q] = xv[q];
-                    *a.y[q] = yv[q];
-                }
-                a.vb[0] = ux;
-                a.vb[1] = uy;
-                if (last) {
-                    *a.x[3] = xv[3];
-                    *a.y[3] = yv[3];
-                    *a.x[4] = xv[4];
-                    *a.y[4] = yv[4];
-                }
-                kx0 = xv[3];
-                kx1 = yv[3];
-                ky0 = xv[4];
-                ky1 = yv[4];
-                // one 16-byte store of the rotation's (c, s)
-                HIP_vector_base<double, 2>::Native_vec_ value;
-                value[0] = c;
-                value[1] = sn;
-                *(GLOBAL HIP_vector_base<double, 2>::Native_vec_ *)a.cs = value;
+                rotate(a, t == g.tau0, t == tend, std::false_type{});
             }
             if (t == tend) {
                 ci += nt;
