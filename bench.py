@@ -40,9 +40,10 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CUs x 128 FP64 flop/clk x 2.4 GHz
 # each scaled by what the counter reads for a plain 1 GiB device copy
 # (bench.py --copy-probe).  Valid only for the sources with this digest and
 # the workload named; otherwise the traffic is reported as null.
-TRAFFIC_SOURCES = ["paper_2509_02840_amd/csrc/kernels.hip", "paper_2509_02840_amd/csrc/schedule.h",
-                   "paper_2509_02840_amd/csrc/device.h", "paper_2509_02840_amd/csrc/plan.cpp"]
-MEASURED_TRAFFIC = {"sha256": "310a45e7cc6cc93afc80dc367ecf0f1f9da17a348055d01756f760fe6e24df78",
+TRAFFIC_SOURCES = ["paper_2509_02840_amd/csrc/kernels.hip", "paper_2509_02840_amd/csrc/primitives.h",
+                   "paper_2509_02840_amd/csrc/schedule.h", "paper_2509_02840_amd/csrc/device.h",
+                   "paper_2509_02840_amd/csrc/plan.cpp"]
+MEASURED_TRAFFIC = {"sha256": "a73bea3731a7013ca22fa618f0ebacfacf461b5f0c9663d7dcef235888891615",
                     "n": 2048, "streams": 64, "tiling": (12, 7, 1), "bytes": 469328079894.7}
 
 

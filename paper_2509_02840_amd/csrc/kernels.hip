@@ -6,9 +6,7 @@
 //                  through LDS so that global reads stay coalesced.
 //  spike_kernel    m > n: the reverse-order rotations that fold u(n+1:m)
 //                  into u(n+1); a dependent chain, one lane.
-//  gen_kernel      generation of phases 1 and 2 on the band held in LDS (or
-//                  global memory for large n): one thread per chain in
-//                  flight, one rotation per tick, ticks separated by barriers.
+//  (gen_kernel, the generation of phases 1 and 2, is in gen.hip.)
 //  apply_kernel    accumulates the rotation streams into Q and P
 //                  (eq. bidiagplus): lanes own rows, a register window of
 //                  columns slides along each block of chains, and the
@@ -19,31 +17,12 @@
 // fma only where written; sqrt and division are IEEE.
 #include <hip/hip_runtime.h>
 
-#include <type_traits>
-
 #include "device.h"
 #include "kernels.h"
+#include "primitives.h"
 #include "schedule.h"
 
 namespace bdu {
-
-#define GLOBAL __attribute__((address_space(1)))
-#define CONSTANT __attribute__((address_space(4)))
-#define LOCAL __attribute__((address_space(3)))
-
-// Pointers read from a descriptor are generic; the kernels know which memory
-// they point to.  Global pointers give global (not flat) memory instructions,
-// constant pointers with a uniform index give scalar loads.
-template <typename T>
-__device__ __forceinline__ GLOBAL T *gptr(T *p)
-{
-    return (GLOBAL T *)(uintptr_t)p;
-}
-template <typename T>
-__device__ __forceinline__ const CONSTANT T *kptr(const T *p)
-{
-    return (const CONSTANT T *)(uintptr_t)p;
-}
 
 __device__ __forceinline__ BlockDesc load_block(const BlockDesc *p, int b)
 {
@@ -55,48 +34,6 @@ __device__ __forceinline__ BlockDesc load_block(const BlockDesc *p, int b)
     d.phase = q->phase;
     d.off = q->off;
     return d;
-}
-
-// ---- primitives (eq. giv1) -------------------------------------------------
-
-// Rotation generator: mode 1 gives [c -s; s c][a;b] = [0;r], mode 2 gives
-// [r;0]; r = +sqrt(a^2 + b^2) with an exact power-of-two scaling when the
-// larger magnitude is extreme; identity when the target is already zero.
-//
-// Written with selects only: both the identity and the general result are
-// computed (the general one may be NaN when a = b = 0 and is then discarded),
-// so a wavefront runs one straight sequence whatever its lanes' data.
-template <int MODE>
-__device__ __forceinline__ void givens_m(double a, double b, double &c, double &s, double &r)
-{
-    constexpr bool m1 = MODE == 1;
-    const double fa = fabs(a), fb = fabs(b);
-    const double big = fa > fb ? fa : fb;
-    const bool hi = big > 0x1p500, lo = big < 0x1p-500;
-    const double sc = hi ? 0x1p-600 : (lo ? 0x1p600 : 1.0);
-    const double unsc = hi ? 0x1p600 : (lo ? 0x1p-600 : 1.0);
-    const double as = a * sc, bs = b * sc;
-    const double rs = sqrt(fma(as, as, bs * bs));
-    const double p = (m1 ? bs : as) / rs, q = (m1 ? as : bs) / rs;
-    const bool ident = (m1 ? a : b) == 0.0;
-    c = ident ? 1.0 : p;
-    s = ident ? 0.0 : (m1 ? q : -q);
-    r = ident ? (m1 ? b : a) : rs * unsc;
-}
-
-__device__ __forceinline__ void givens(double a, double b, int mode, double &c, double &s, double &r)
-{
-    if (mode == 1)
-        givens_m<1>(a, b, c, s, r);
-    else
-        givens_m<2>(a, b, c, s, r);
-}
-
-__device__ __forceinline__ void rot(double c, double s, double &x, double &y)
-{
-    double x0 = x, y0 = y;
-    x = fma(c, x0, -(s * y0));
-    y = fma(s, x0, c * y0);
 }
 
 // ---- projection ---------------------------------------------------------------
@@ -180,322 +117,6 @@ __global__ __launch_bounds__(64) void spike_kernel(HandleDev *const *hs, Gate ga
     if (threadIdx.x == 0) {
         u[n] = surv;  // u_{n+1}
         for (int i = n + 1; i < m; ++i) u[i] = 0.0;
-    }
-}
-
-// ---- generation -------------------------------------------------------------------
-
-// Band storage: band_row (device.h).  Entries outside the band read as zero
-// and are never written: the schedule keeps them zero.
-
-// Chain descriptor held in registers (GenChain fields).
-struct ChainReg {
-    int type, param, len, tau0;
-    int64_t slot0, slot1;
-};
-
-__device__ __forceinline__ ChainReg load_chain(const GenChain *chains, int idx)
-{
-    const GLOBAL int *p = (const GLOBAL int *)gptr(chains) + 8 * idx;
-    const GLOBAL int64_t *q = (const GLOBAL int64_t *)(p + 4);
-    ChainReg c;
-    c.type = p[0];
-    c.param = p[1];
-    c.len = p[2];
-    c.tau0 = p[3];
-    c.slot0 = q[0];
-    c.slot1 = q[1];
-    return c;
-}
-
-// A use that makes the compiler wait for a chain's loads at this point.  The
-// vector memory counter also counts the coefficient stores, so a wait for a
-// load left in flight across the tick loop would wait for the previous
-// tick's store in every tick.
-__device__ __forceinline__ void settle(const ChainReg &c)
-{
-    asm volatile("" ::"v"(c.type), "v"(c.param), "v"(c.len), "v"(c.tau0), "v"(c.slot0), "v"(c.slot1));
-}
-
-// Ticks between refills of a thread's prefetched chain descriptor.
-constexpr int kRefill = 32;
-
-__device__ __forceinline__ int band_cell(int r, int c)
-{
-    return band_row(r) + (c - r) + 2;
-}
-
-// Rotation s of chain g, decoded into band pointers.
-//
-// In phase 1 both chain types are the up-left chase pattern L(ii)
-// [(ii,ii+3) onto (ii+1,ii+3)], R(ii-1) [(ii+1,ii-1) onto (ii+1,ii)],
-// ii = i0 - 3*(ss>>1), whose first rotation eliminates an entry of v (P1A) or
-// u (P1B) instead.  In phase 2 both are the down-right pattern R(ii+2)
-// [(ii,ii+3) into (ii,ii+2)], L(ii+3) [(ii+4,ii+2) into (ii+3,ii+2)],
-// ii = i0 + 3*(ss>>1), whose first rotation acts one column (P2A) or one row
-// (P2B) further on.  A left rotation on rows (i, i+1) rotates the band pairs
-// w_j in columns i-1+j, a right rotation on columns (j', j'+1) those in rows
-// j'-2+j (j = 0..4, the only pairs the schedule can make nonzero), plus the
-// matching u or v pair.
-//
-// Consecutive rotations of a chain share two window pairs: in phase 1 pairs
-// w_0, w_1 of one rotation are w_3, w_4 of the next, in phase 2 the reverse.
-// The window is kept in the order (w_3, w_4, w_2, w_0, w_1) in phase 1 and
-// (w_0, ..., w_4) in phase 2, so slots 0 and 1 are the pairs shared with the
-// previous rotation and slots 3 and 4 those shared with the next, and the
-// next rotation's slots 0, 1 hold (x_3, y_3), (x_4, y_4) of this one's, in
-// both phases and both directions.  The pair a rotation is generated from
-// is slot 1 in phase 1 and slot 0 in phase 2, except at a chain's first
-// rotation: the u or v pair in phase 1, slot 1 in phase 2.
-//
-// Rotations s and s + 2 of a chain have the same pattern three rows and
-// columns further on: every band pointer moves by kBandStep3 doubles, the u
-// or v pointer by 3 and the coefficient slot by K.
-template <typename BP>
-struct RotAddr {
-    BP x[5], y[5];      // window pairs, in slot order
-    BP vb;              // u or v pair (vb[0], vb[1])
-    GLOBAL double *cs;  // coefficient slot (c, s)
-};
-
-template <typename BP>
-__device__ __forceinline__ RotAddr<BP> decode(BP S, const ChainReg &g, int s, int K, int UO, int VO,
-                                              GLOBAL double *csL, GLOBAL double *csR)
-{
-    const bool ph1 = g.type <= CH_P1B;
-    const bool first = ph1 ? (g.type == CH_P1A) : (g.type == CH_P2A);
-    const int ss = s + (first ? 1 : 0);
-    const int odd = ss & 1;
-    const int i0 = ph1 ? (first ? g.param + 1 : g.param) : (first ? g.param - 3 : g.param - 1);
-    const int ii = ph1 ? i0 - 3 * (ss >> 1) : i0 + 3 * (ss >> 1);
-    const int side = ph1 ? odd : 1 - odd;
-    const int i = ph1 ? (odd ? ii - 1 : ii) : (odd ? ii + 3 : ii + 2);
-    RotAddr<BP> d;
-    d.vb = S + (side == 0 ? UO : VO) + i + 3;
-    // left: rows i, i+1 at columns i-1..i+3; right: rows i-2..i+2 at
-    // columns i, i+1 (adjacent doubles)
-    const int b2 = band_row(i), b3 = band_row(i + 1);
-    const int rb[5] = {band_row(i - 2) + 4, band_row(i - 1) + 3, b2 + 2, b3 + 1, band_row(i + 2)};
-    int wx[5], wy[5];
-#pragma unroll
-    for (int j = 0; j < 5; ++j) {
-        wx[j] = side == 0 ? b2 + j + 1 : rb[j];
-        wy[j] = side == 0 ? b3 + j : rb[j] + 1;
-    }
-    constexpr int ord1[5] = {3, 4, 2, 0, 1};
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-        d.x[k] = S + (ph1 ? wx[ord1[k]] : wx[k]);
-        d.y[k] = S + (ph1 ? wy[ord1[k]] : wy[k]);
-    }
-    d.cs = (side == 0 ? csL + 2 * g.slot0 : csR + 2 * g.slot1) + (int64_t)(s >> 1) * 2 * K;
-    return d;
-}
-
-template <typename BP>
-__device__ __forceinline__ void advance(RotAddr<BP> &a, int db, int du, int64_t dcs)
-{
-#pragma unroll
-    for (int q = 0; q < 5; ++q) {
-        a.x[q] += db;
-        a.y[q] += db;
-    }
-    a.vb += du;
-    a.cs += dcs;
-}
-
-// Generation of one pass for one handle per workgroup.  Thread l runs chains
-// l, l + blockDim, ... (non-empty chains in schedule order); chain c performs
-// its rotation s at tick tau0(c) + s, and a barrier separates ticks.  The host
-// chose the start ticks so that two rotations touching a common band row, u or
-// v entry are ordered as in the sequential schedule; in particular no other
-// rotation touches a band entry between two consecutive rotations of a chain
-// that share it, so the thread keeps the two shared pairs in registers
-// (k0, k1) instead of writing and reading them back.  A tick reads three
-// window pairs and the u or v pair, generates the rotation from registers and
-// writes three pairs and the u or v pair; a chain's first tick also reads
-// slots 0 and 1, its last also writes slots 3 and 4.
-//
-// Each thread keeps the pointers of its chain's next rotation at an even tick
-// (ae) and at an odd tick (ao) and moves the set it has just used on to the
-// chain's rotation two ticks later.
-template <bool IN_LDS>
-__global__ __launch_bounds__(kGenThreads) void gen_kernel(HandleDev *const *hs, Gate gate)
-{
-    extern __shared__ double smem[];
-    if (gate.ranks && gate.pass >= gate.ranks[blockIdx.x]) return;
-    const CONSTANT HandleDev *h = kptr(hs[blockIdx.x]);
-    const int n = h->n, N = h->N;
-    double *S = IN_LDS ? smem : h->band;
-    // band pointers of the tick loop: LDS (32-bit) or global
-    using BP = typename std::conditional<IN_LDS, LOCAL double *, GLOBAL double *>::type;
-    const BP SB = (BP)S;
-    const int UO = (int)band_doubles(N);  // u_i at S[UO + i + 3]
-    const int VO = UO + (N + 8);          // v_j at S[VO + j + 3]
-    const int tid = threadIdx.x;
-    const int nt = blockDim.x;
-    const int total = VO + (n + 8);
-    for (int k = tid; k < total; k += nt) S[k] = 0.0;
-    __syncthreads();
-    for (int i = 1 + tid; i <= n; i += nt) {
-        S[band_cell(i, i)] = h->d[i - 1];
-        if (i < n) S[band_cell(i, i + 1)] = h->e[i - 1];
-        S[VO + i + 3] = h->v[i - 1];
-    }
-    for (int i = 1 + tid; i <= N; i += nt) S[UO + i + 3] = h->u[i - 1];
-    __syncthreads();
-
-    const int K = h->K;
-    const int nch = h->nchains;
-    GLOBAL double *csL = gptr((double *)h->csL), *csR = gptr((double *)h->csR);
-    const int64_t dcs = 2 * (int64_t)K;
-    // Thread tid runs chains tid, tid + nt, ...; gn holds the next one when
-    // `next` is set.  Descriptors are loaded and waited for before the loop,
-    // every kRefill ticks, or (when a chain ends before a refill) at the
-    // switch, so the tick body itself never waits on vector memory.
-    int ci = tid;
-    ChainReg g = {0, 0, 0, 0, 0, 0}, gn = {0, 0, 0, 0, 0, 0};
-    bool next = false;
-    if (ci < nch) g = load_chain(h->chains, ci);
-    if (ci + nt < nch) {
-        gn = load_chain(h->chains, ci + nt);
-        next = true;
-    }
-    settle(g);
-    settle(gn);
-
-    RotAddr<BP> ae, ao;
-    bool m1 = false, fold = false;
-    int db = 0, du = 0;
-    int tend = -1;
-    auto start = [&]() {
-        const RotAddr<BP> a0 = decode(SB, g, 0, K, UO, VO, csL, csR), a1 = decode(SB, g, 1, K, UO, VO, csL, csR);
-        const bool odd0 = g.tau0 & 1;
-        ae = odd0 ? a1 : a0;
-        ao = odd0 ? a0 : a1;
-        m1 = g.type <= CH_P1B;
-        fold = g.type == CH_FOLD;
-        db = m1 ? -kBandStep3 : kBandStep3;
-        du = m1 ? -3 : 3;
-        tend = g.tau0 + g.len - 1;
-    };
-    if (ci < nch) start();
-
-    double kx0 = 0.0, kx1 = 0.0, ky0 = 0.0, ky1 = 0.0;  // slots 0, 1 carried from the previous rotation
-    // One rotation with its window, for one phase (the phase is uniform
-    // across a wavefront except where phase 2 starts, so a wavefront
-    // normally runs one of the two bodies).
-    auto rotate = [&](RotAddr<BP> &a, bool first, bool last, auto phase) {
-        constexpr bool P1 = decltype(phase)::value;
-        double xv[5], yv[5];
-#pragma unroll
-        for (int q = 2; q < 5; ++q) {
-            xv[q] = *a.x[q];
-            yv[q] = *a.y[q];
-        }
-        double ux = a.vb[0], uy = a.vb[1];
-        // local copies: a select between captured variables would become a
-        // load through a selected address
-        xv[0] = kx0;
-        xv[1] = kx1;
-        yv[0] = ky0;
-        yv[1] = ky1;
-        double va = P1 ? xv[1] : xv[0], vb = P1 ? yv[1] : yv[0];
-        if (first) {
-            xv[0] = *a.x[0];
-            xv[1] = *a.x[1];
-            yv[0] = *a.y[0];
-            yv[1] = *a.y[1];
-            va = P1 ? ux : xv[1];
-            vb = P1 ? uy : yv[1];
-        }
-        double c, sn, rr;
-        givens_m<P1 ? 1 : 2>(va, vb, c, sn, rr);
-#pragma unroll
-        for (int q = 0; q < 5; ++q) rot(c, sn, xv[q], yv[q]);
-        rot(c, sn, ux, uy);
-        // the generating pair becomes (0, r) (mode 1) or (r, 0) (mode 2)
-        if (P1) {
-            ux = first ? 0.0 : ux;
-            uy = first ? rr : uy;
-            xv[1] = first ? xv[1] : 0.0;
-            yv[1] = first ? yv[1] : rr;
-        } else {
-            xv[1] = first ? rr : xv[1];
-            yv[1] = first ? 0.0 : yv[1];
-            xv[0] = first ? xv[0] : rr;
-            yv[0] = first ? yv[0] : 0.0;
-        }
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            *a.x[q] = xv[q];
-            *a.y[q] = yv[q];
-        }
-        a.vb[0] = ux;
-        a.vb[1] = uy;
-        if (last) {
-            *a.x[3] = xv[3];
-            *a.y[3] = yv[3];
-            *a.x[4] = xv[4];
-            *a.y[4] = yv[4];
-        }
-        kx0 = xv[3];
-        kx1 = yv[3];
-        ky0 = xv[4];
-        ky1 = yv[4];
-        // one 16-byte store of the rotation's (c, s)
-        HIP_vector_base<double, 2>::Native_vec_ value;
-        value[0] = c;
-        value[1] = sn;
-        *(GLOBAL HIP_vector_base<double, 2>::Native_vec_ *)a.cs = value;
-    };
-
-    auto tick = [&](RotAddr<BP> &a, int t) {
-        const bool live = ci < nch && t >= g.tau0;
-        if (live) {
-            if (fold) {
-                // u v^T now touches only (N-1, n) and (N, n)
-                const int fa = band_cell(N - 1, n), fb = band_cell(N, n);
-                S[fa] = fma(S[UO + N - 1 + 3], S[VO + n + 3], S[fa]);
-                S[fb] = fma(S[UO + N + 3], S[VO + n + 3], S[fb]);
-            } else if (m1) {
-                rotate(a, t == g.tau0, t == tend, std::true_type{});
-            } else {
-                rotate(a, t == g.tau0, t == tend, std::false_type{});
-            }
-            if (t == tend) {
-                ci += nt;
-                if (next) {
-                    g = gn;
-                    next = false;
-                } else if (ci < nch) {
-                    g = load_chain(h->chains, ci);
-                    settle(g);
-                }
-                if (ci < nch) start();
-            } else {
-                advance(a, db, du, dcs);
-            }
-        }
-        if (((t + 1) & (kRefill - 1)) == 0 && !next && ci + nt < nch) {
-            gn = load_chain(h->chains, ci + nt);
-            settle(gn);
-            next = true;
-        }
-        __syncthreads();
-    };
-
-    const int ticks = (int)h->ticks;
-    int t = 0;
-    for (; t + 1 < ticks; t += 2) {
-        tick(ae, t);
-        tick(ao, t + 1);
-    }
-    if (t < ticks) tick(ae, t);
-
-    for (int i = 1 + tid; i <= n; i += nt) {
-        h->d[i - 1] = S[band_cell(i, i)];
-        if (i < n) h->e[i - 1] = S[band_cell(i, i + 1)];
     }
 }
 
@@ -1042,30 +663,6 @@ hipError_t launch_project(HandleDev *const *hs, int count, int max_tiles, Gate g
 hipError_t launch_spike(HandleDev *const *hs, int count, Gate gate, hipStream_t st)
 {
     hipLaunchKernelGGL(spike_kernel, dim3(count), dim3(64), 0, st, hs, gate);
-    return hipGetLastError();
-}
-
-hipError_t prepare_kernels()
-{
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void *)gen_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)kMaxGenLds);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
-    return hipSuccess;
-}
-
-hipError_t launch_gen(HandleDev *const *hs, int count, int64_t lds_bytes, bool in_lds, Gate gate, hipStream_t st)
-{
-    if (in_lds) {
-        hipError_t e = prepare_kernels();
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(gen_kernel<true>, dim3(count), dim3(kGenThreads), (size_t)lds_bytes, st, hs, gate);
-    } else {
-        hipLaunchKernelGGL(gen_kernel<false>, dim3(count), dim3(kGenThreads), 0, st, hs, gate);
-    }
     return hipGetLastError();
 }
 
