@@ -44,7 +44,10 @@ enum {
     MUT_PROJECT_TRANS = 4,  /* project with Q instead of Q^T */
     MUT_Z2_SIGN = 5,        /* mode-2 generator returns s = +b/r */
     MUT_SKIP_Q = 6,         /* left rotations are not accumulated into Q */
-    MUT_PHASE2_SKIP_2B = 7  /* phase 2 skips the second-superdiagonal elimination */
+    MUT_PHASE2_SKIP_2B = 7, /* phase 2 skips the second-superdiagonal elimination */
+    MUT_TRACK_RESID = 8,    /* tracking: b_perp = b + Q1 b_hat */
+    MUT_TRACK_NO_DELTA = 9, /* tracking: the middle update vector ends in 0, not delta */
+    MUT_TRACK_KEEP = 10     /* tracking: drops the column of largest norm */
 };
 static int g_mut = MUT_NONE;
 void orc_set_mutation(int which) { g_mut = which; }
@@ -438,6 +441,141 @@ int orc_bgu_update(int64_t m, int64_t n, double *Q, int64_t ldq, double *d,
     }
     free(u);
     free(v);
+    return st;
+}
+
+/* ---- subspace tracking: Section 4, eqs. (lrup)-(bdlrup) ----------------- */
+
+/* b_perp = b - Q1 (Q1^T b) with (Q1 b_hat)_i = sum_j Q1(i,j) b_hat_j
+ * accumulated as fma, j ascending from 0; delta^2 = sum_i b_perp_i^2 the
+ * same way, i ascending. */
+static void track_complement(int64_t rows, int64_t r, const double *A, int64_t lda,
+                             const double *x, double *xhat, double *xperp, double *norm)
+{
+    orc_project(rows, r, A, lda, x, xhat);
+    for (int64_t i = 0; i < rows; ++i) {
+        double s = 0.0;
+        for (int64_t j = 0; j < r; ++j)
+            s = fma(A[i + j * lda], xhat[j], s);
+        xperp[i] = (g_mut == MUT_TRACK_RESID) ? x[i] + s : x[i] - s;
+    }
+    double acc = 0.0;
+    for (int64_t i = 0; i < rows; ++i)
+        acc = fma(xperp[i], xperp[i], acc);
+    *norm = sqrt(acc);
+}
+
+/* out(:, j) = [A, w] M(:, keep_j): sequential fma over the r + 1 terms,
+ * the appended column w last. */
+static void track_product(int64_t rows, int64_t r, const double *A, int64_t lda,
+                          const double *w, const double *M, int64_t ldm,
+                          const int64_t *keep, int64_t ncols, double *out, int64_t ldo)
+{
+    for (int64_t j = 0; j < ncols; ++j) {
+        const double *mc = M + keep[j] * ldm;
+        for (int64_t i = 0; i < rows; ++i) {
+            double acc = 0.0;
+            for (int64_t l = 0; l < r; ++l)
+                acc = fma(A[i + l * lda], mc[l], acc);
+            out[i + j * ldo] = fma(w[i], mc[r], acc);
+        }
+    }
+}
+
+int orc_track_update(int64_t m, int64_t n, int64_t r, const double *U, int64_t ldu,
+                     const double *d, const double *e, const double *V, int64_t ldv,
+                     const double *b, const double *c, int flags, double *U2,
+                     int64_t ldu2, double *d2, double *e2, double *V2, int64_t ldv2,
+                     double *info)
+{
+    const int keep_all = (flags & ORC_TRACK_KEEP_ALL) != 0;
+    if (r < 1 || m < r + 1 || n < r + 1 || ldu < m || ldv < n || ldu2 < m || ldv2 < n ||
+        !U || !d || !V || !b || !c || !U2 || !d2 || !V2 || (r > 1 && !e) || (!keep_all && r > 1 && !e2) ||
+        (keep_all && !e2))
+        return ORC_EINVAL;
+    const int64_t R = r + 1;
+    double *bh = (double *)calloc((size_t)R, sizeof(double));
+    double *ch = (double *)calloc((size_t)R, sizeof(double));
+    double *bp = (double *)malloc(sizeof(double) * (size_t)m);
+    double *cp = (double *)malloc(sizeof(double) * (size_t)n);
+    double *Qm = (double *)calloc((size_t)(R * R), sizeof(double));
+    double *Pm = (double *)calloc((size_t)(R * R), sizeof(double));
+    double *dm = (double *)calloc((size_t)R, sizeof(double));
+    double *em = (double *)calloc((size_t)R, sizeof(double));
+    int64_t *keep = (int64_t *)malloc(sizeof(int64_t) * (size_t)R);
+    int st = ORC_OK;
+    if (!bh || !ch || !bp || !cp || !Qm || !Pm || !dm || !em || !keep) {
+        st = ORC_ENOMEM;
+        goto out;
+    }
+    /* eq. (defup): projections onto the tracked bases and their complements */
+    double delta, gamma;
+    track_complement(m, r, U, ldu, b, bh, bp, &delta);
+    track_complement(n, r, V, ldv, c, ch, cp, &gamma);
+    if (info) {
+        info[0] = delta;
+        info[1] = gamma;
+    }
+    if (!(delta > 0.0) || !(gamma > 0.0)) { /* not augmented: outside this mode */
+        st = ORC_ESPAN;
+        goto out;
+    }
+    /* eq. (qrlr): the appended columns b_perp / delta and c_perp / gamma */
+    for (int64_t i = 0; i < m; ++i)
+        bp[i] = bp[i] / delta;
+    for (int64_t i = 0; i < n; ++i)
+        cp[i] = cp[i] / gamma;
+    /* eq. (equivlrup): BGU on [B 0; 0 0] + [b_hat; delta][c_hat; gamma]^T */
+    for (int64_t i = 0; i < R; ++i)
+        Qm[i + i * R] = Pm[i + i * R] = 1.0;
+    for (int64_t i = 0; i < r; ++i)
+        dm[i] = d[i];
+    for (int64_t i = 0; i + 1 < r; ++i)
+        em[i] = e[i];
+    bh[r] = (g_mut == MUT_TRACK_NO_DELTA) ? 0.0 : delta;
+    ch[r] = gamma;
+    st = orc_bgu_update(R, R, Qm, R, dm, em, Pm, R, bh, R, ch, R, 1, 0);
+    if (st != ORC_OK)
+        goto out;
+    /* truncation: drop the row and column of smallest column norm
+     * (squared norm d_k^2 + e_{k-1}^2 as fma(d_k, d_k, e_{k-1} * e_{k-1}));
+     * ties drop the highest index */
+    int64_t kdrop = R;
+    if (!keep_all) {
+        kdrop = R - 1;
+        double best = fma(dm[R - 1], dm[R - 1], em[R - 2] * em[R - 2]);
+        for (int64_t k = R - 2; k >= 0; --k) {
+            double nk = (k == 0) ? dm[0] * dm[0] : fma(dm[k], dm[k], em[k - 1] * em[k - 1]);
+            if (g_mut == MUT_TRACK_KEEP ? nk > best : nk < best) {
+                best = nk;
+                kdrop = k;
+            }
+        }
+    }
+    if (info)
+        info[2] = (double)kdrop;
+    int64_t nk = 0;
+    for (int64_t k = 0; k < R; ++k)
+        if (k != kdrop)
+            keep[nk++] = k;
+    for (int64_t j = 0; j < nk; ++j)
+        d2[j] = dm[keep[j]];
+    for (int64_t j = 0; j + 1 < nk; ++j)
+        e2[j] = (keep[j + 1] == keep[j] + 1) ? em[keep[j]] : 0.0;
+    /* eq. (bdlrup): the thin factors [Q1, b_perp/delta] Q2(:, keep) and
+     * [P1, c_perp/gamma] P2(:, keep) */
+    track_product(m, r, U, ldu, bp, Qm, R, keep, nk, U2, ldu2);
+    track_product(n, r, V, ldv, cp, Pm, R, keep, nk, V2, ldv2);
+out:
+    free(bh);
+    free(ch);
+    free(bp);
+    free(cp);
+    free(Qm);
+    free(Pm);
+    free(dm);
+    free(em);
+    free(keep);
     return st;
 }
 

@@ -29,6 +29,7 @@ extern "C" {
 #define ORC_EINVAL (-1)
 #define ORC_ENOMEM (-2)
 #define ORC_ESTRUCT (-10) /* a band/zero-pattern assertion failed */
+#define ORC_ESPAN (-11)   /* tracking: b or c lies in the span of the tracked basis */
 
 /* flags for orc_bgu_pass / orc_bgu_update */
 #define ORC_CHECK_PHASES 1 /* assert the zero pattern after each phase */
@@ -91,6 +92,33 @@ int orc_bgu_pass_rows(int64_t m, int64_t n, double *Q, int64_t qrows,
 int orc_bgu_update(int64_t m, int64_t n, double *Q, int64_t ldq, double *d,
                    double *e, double *P, int64_t ldp, const double *B,
                    int64_t ldb, const double *C, int64_t ldc, int r, int flags);
+
+/* flags for orc_track_update */
+#define ORC_TRACK_KEEP_ALL 1 /* return the rank r+1 factorization (no truncation) */
+
+/* Subspace tracking (Section 4, eqs. (lrup)-(bdlrup)): the thin rank-r
+ * factorization A = U B V^T (U m x r, V n x r orthonormal columns, B upper
+ * bidiagonal with d (r), e (r-1)) updated with b c^T.
+ *   b_hat = U^T b (orc_project order), b_perp_i = b_i - sum_j U(i,j) b_hat_j
+ *   (fma, j ascending), delta = sqrt(sum_i b_perp_i^2) (fma, i ascending);
+ *   the same for c, V, gamma.
+ *   One BGU pass (orc_bgu_update with Q = P = I) on the (r+1) x (r+1) matrix
+ *   [B 0; 0 0] + [b_hat; delta][c_hat; gamma]^T gives Q2 Bbar P2^T.
+ *   Unless ORC_TRACK_KEEP_ALL: the row and column k of Bbar with the smallest
+ *   column norm (d_k^2 + e_{k-1}^2 as fma(d_k, d_k, e_{k-1}*e_{k-1}); ties:
+ *   the highest k) are removed; the superdiagonal entry joining k-1 and k+1
+ *   is 0.
+ *   U2(:, j) = [U, b_perp/delta] Q2(:, keep_j), each entry a sequential fma
+ *   over the r+1 terms in column order; V2 the same with P2.
+ * U2 is m x (r or r+1), V2 n x (r or r+1), d2 r or r+1 entries, e2 one fewer.
+ * info (optional, 3 entries): delta, gamma, the removed index (r+1 if none).
+ * Requires m, n >= r + 1.  Returns ORC_ESPAN, changing no output, when delta
+ * or gamma is 0 (the paper then does not augment that side). */
+int orc_track_update(int64_t m, int64_t n, int64_t r, const double *U, int64_t ldu,
+                     const double *d, const double *e, const double *V, int64_t ldv,
+                     const double *b, const double *c, int flags, double *U2,
+                     int64_t ldu2, double *d2, double *e2, double *V2, int64_t ldv2,
+                     double *info);
 
 /* Householder bidiagonalization A = Q B P^T (Section 2, eq. (house)),
  * m >= n >= 1.  Q is m x m, P is n x n (P e1 = e1), d n entries, e n-1. */

@@ -79,6 +79,8 @@ def lib():
         L.orc_jacobi_sv.argtypes = [i64, i64, dp, i64, dp]
         L.orc_jacobi_sv.restype = ctypes.c_int
         L.orc_set_mutation.argtypes = [ctypes.c_int]
+        L.orc_track_update.argtypes = [i64, i64, i64, dp, i64, dp, dp, dp, i64, dp, dp, ctypes.c_int,
+                                       dp, i64, dp, dp, dp, i64, dp]
         L.orc_set_mutation.restype = None
         _lib = L
     return _lib
@@ -234,6 +236,35 @@ def bidiag_sv(d, e):
     Bd[np.arange(n), np.arange(n)] = d
     Bd[np.arange(n - 1), np.arange(1, n)] = e
     return jacobi_sv(Bd)
+
+
+ORC_ESPAN = -11
+TRACK_KEEP_ALL = 1
+
+
+def track_update(U, d, e, V, b, c, keep_all: bool = False):
+    """Subspace-tracking update (Section 4): returns (U2, d2, e2, V2, info)
+    with info = (delta, gamma, removed index).  Raises ValueError with the
+    status when b or c lies in the span of U or V (status ORC_ESPAN)."""
+    U, V = _f64(U), _f64(V)
+    m, r = U.shape
+    n = V.shape[0]
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    e = np.ascontiguousarray(e, dtype=np.float64) if r > 1 else np.zeros(1)
+    b = np.ascontiguousarray(b, dtype=np.float64).ravel()
+    c = np.ascontiguousarray(c, dtype=np.float64).ravel()
+    k = r + 1 if keep_all else r
+    U2 = np.zeros((m, k), order="F")
+    V2 = np.zeros((n, k), order="F")
+    d2 = np.zeros(k)
+    e2 = np.zeros(max(k - 1, 1))
+    info = np.zeros(3)
+    st = lib().orc_track_update(m, n, r, _p(U), m, _p(d), _p(e), _p(V), n, _p(b), _p(c),
+                                TRACK_KEEP_ALL if keep_all else 0, _p(U2), m, _p(d2), _p(e2),
+                                _p(V2), n, _p(info))
+    if st != ORC_OK:
+        raise ValueError(f"orc_track_update failed with status {st}")
+    return U2, d2, e2[:k - 1], V2, (info[0], info[1], int(info[2]))
 
 
 def set_mutation(k: int) -> None:

@@ -155,3 +155,25 @@ def rating_row(rng: np.random.Generator, items: int, nnz: int, zipf_s: float = 1
     its = rng.choice(items, size=min(nnz, items), replace=False, p=pz)
     row[its] = rng.integers(1, 6, len(its)).astype(np.float64)
     return row
+
+
+def tracking_state(m: int, n: int, r: int, seed: int):
+    """Thin tracked factors for subspace tracking (Section 4): U (m x r) and
+    V (n x r) with orthonormal columns (Q factors of the Householder QR of
+    N(0,1) matrices), d ~ U(1, 10) sorted descending (a dominant subspace),
+    e ~ U(0, 1).  Returns (U, d, e, V), column-major."""
+    if r < 1 or m < r + 1 or n < r + 1:
+        raise ValueError("need m, n >= r + 1 >= 2")
+    rng = np.random.default_rng(seed)
+    U, _ = np.linalg.qr(rng.standard_normal((m, r)))
+    V, _ = np.linalg.qr(rng.standard_normal((n, r)))
+    d = np.sort(rng.uniform(1.0, 10.0, r))[::-1].copy()
+    e = rng.uniform(0.0, 1.0, max(r - 1, 0))
+    return np.asfortranarray(U), d, e, np.asfortranarray(V)
+
+
+def tracking_update(m: int, n: int, seed: int, scale: float = 1.0):
+    """One streaming rank-1 update b c^T: b ~ N(0,1) scale / sqrt(m),
+    c ~ N(0,1) / sqrt(n)."""
+    rng = np.random.default_rng(seed)
+    return (rng.standard_normal(m) * scale / math.sqrt(m), rng.standard_normal(n) / math.sqrt(n))
