@@ -45,7 +45,8 @@ enum {
     BDU_ENOMEM = -2,     /* device allocation failed or over the memory budget */
     BDU_EDEVICE = -3,    /* a HIP call failed; the handle is poisoned */
     BDU_ENONFINITE = -4, /* a NaN or infinite input was rejected (bdu_set_finite_check) */
-    BDU_EBUSY = -5       /* serving queue full */
+    BDU_EBUSY = -5,      /* serving queue full */
+    BDU_ESPAN = -6       /* tracking: b or c lies in the span of the tracked basis */
 };
 
 /* Create a handle from A = Q Bd P^T (eq. bidiag).  Requires m >= n >= 2.
@@ -231,6 +232,53 @@ int bdu_timing_read(double *ms, int64_t *launches);
  * (IEEE sqrt and division) against a reference. */
 int bdu_givens_device(const double *a, const double *b, int mode, double *c,
                       double *s, double *r, int64_t count);
+
+/* ---- subspace tracking (Section 4, eqs. (lrup)-(bdlrup)) ------------ */
+
+/* A thin rank-r factorization A = U B V^T (U m x r and V n x r with
+ * orthonormal columns, B upper bidiagonal r x r) tracked under rank-1
+ * updates A + b c^T, each followed by truncation back to rank r. */
+typedef struct bdu_track_ctx *bdu_track;
+
+/* U (m x r), V (n x r): column-major, leading dimension m (n); d r entries,
+ * e r-1 (may be NULL when r = 1).  Host or device pointers; the library
+ * keeps device copies.  Requires 1 <= r, r + 1 <= m, r + 1 <= n.
+ * BDU_EINVAL for bad sizes or NULL inputs, BDU_ENOMEM, BDU_EDEVICE;
+ * BDU_ENONFINITE with the input check on. */
+int bdu_track_create(int64_t m, int64_t n, int64_t r, const double *U, const double *d,
+                     const double *e, const double *V, bdu_track *out);
+
+/* One tracking update with b (m) and c (n), host or device:
+ *   b_hat = U^T b (each entry a sequential fma over the rows, ascending),
+ *   b_perp_i = b_i - sum_j U(i,j) b_hat_j (fma, j ascending),
+ *   delta = sqrt(sum_i b_perp_i^2) (fma, i ascending); the same for c, V
+ *   and gamma (eq. (defup));
+ *   one BGU pass (bdu_update_projected) on the (r+1) x (r+1) middle matrix
+ *   [B 0; 0 0] + [b_hat; delta][c_hat; gamma]^T from identity factors
+ *   (eq. (equivlrup)), giving Q2 Bbar P2^T;
+ *   removal of the row and column k of Bbar with the smallest column norm
+ *   (d_k^2 + e_{k-1}^2 as fma(d_k, d_k, e_{k-1} e_{k-1}); ties: the highest
+ *   k; the superdiagonal entry joining k-1 and k+1 becomes 0);
+ *   U <- [U, b_perp/delta] Q2(:, kept), V <- [V, c_perp/gamma] P2(:, kept),
+ *   each entry a sequential fma over the r+1 terms in column order
+ *   (eq. (bdlrup)).
+ * BDU_ESPAN, changing nothing, when delta or gamma is 0 (b or c lies in the
+ * span of U or V; the paper then does not augment that side, which this
+ * mode does not implement).  Inputs are consumed before returning; the work
+ * is queued on the tracker's stream. */
+int bdu_track_update(bdu_track t, const double *b, const double *c);
+
+/* Wait for the tracker's queued work. */
+int bdu_track_sync(bdu_track t);
+
+/* Copy the tracked factors out (any pointer may be NULL; host or device). */
+int bdu_track_read(bdu_track t, double *U, double *d, double *e, double *V);
+
+/* delta, gamma and the removed index (0-based, of the r+1 columns) of the
+ * last successful update; BDU_EINVAL before the first one. */
+int bdu_track_last(bdu_track t, double *delta, double *gamma, int64_t *dropped);
+
+int bdu_track_destroy(bdu_track t);
 
 /* ---- schedule inspection (host only, no device needed) ---------------- */
 

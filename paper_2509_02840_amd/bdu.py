@@ -21,6 +21,7 @@ BDU_ENOMEM = -2
 BDU_EDEVICE = -3
 BDU_ENONFINITE = -4
 BDU_EBUSY = -5
+BDU_ESPAN = -6
 
 
 class BduError(RuntimeError):
@@ -67,6 +68,13 @@ def lib():
         L.bdu_autotune.argtypes = [i64, i64, i32, ctypes.POINTER(i64)]
         L.bdu_set_generation_in_lds.argtypes = [i32]
         L.bdu_set_finite_check.argtypes = [i32]
+        L.bdu_track_create.argtypes = [i64, i64, i64, vp, vp, vp, vp, ctypes.POINTER(vp)]
+        L.bdu_track_update.argtypes = [vp, vp, vp]
+        L.bdu_track_sync.argtypes = [vp]
+        L.bdu_track_read.argtypes = [vp, vp, vp, vp, vp]
+        L.bdu_track_last.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(i64)]
+        L.bdu_track_destroy.argtypes = [vp]
         L.bdu_tune_save.argtypes = [ctypes.c_char_p]
         L.bdu_tune_load.argtypes = [ctypes.c_char_p]
         L.bdu_handle_tiling.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
@@ -410,6 +418,54 @@ class Server:
         if self._s:
             lib().bdu_server_destroy(self._s)
             self._s = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Tracker:
+    """Subspace tracking (Section 4): a thin rank-r factorization
+    A = U B V^T on the GPU, updated with rank-1 b c^T and truncated back to
+    rank r (bdu_track_*)."""
+
+    def __init__(self, U, d, e, V):
+        self.m, self.r = int(U.shape[0]), int(U.shape[1])
+        self.n = int(V.shape[0])
+        h = ctypes.c_void_p()
+        _check(lib().bdu_track_create(self.m, self.n, self.r, _ptr(U, True), _ptr(d),
+                                      _ptr(e) if self.r > 1 else None, _ptr(V, True), ctypes.byref(h)),
+               "bdu_track_create")
+        self._h = h
+
+    def update(self, b, c) -> None:
+        _check(lib().bdu_track_update(self._h, _ptr(b), _ptr(c)), "bdu_track_update")
+
+    def sync(self) -> None:
+        _check(lib().bdu_track_sync(self._h), "bdu_track_sync")
+
+    def read(self):
+        U = np.empty((self.m, self.r), order="F")
+        V = np.empty((self.n, self.r), order="F")
+        d = np.empty(self.r)
+        e = np.empty(max(self.r - 1, 1))
+        _check(lib().bdu_track_read(self._h, U.ctypes.data, d.ctypes.data, e.ctypes.data, V.ctypes.data),
+               "bdu_track_read")
+        return U, d, e[: self.r - 1], V
+
+    def last(self):
+        """(delta, gamma, removed index) of the last update."""
+        dl, gm, k = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+        _check(lib().bdu_track_last(self._h, ctypes.byref(dl), ctypes.byref(gm), ctypes.byref(k)),
+               "bdu_track_last")
+        return dl.value, gm.value, k.value
+
+    def close(self) -> None:
+        if self._h:
+            lib().bdu_track_destroy(self._h)
+            self._h = ctypes.c_void_p()
 
     def __del__(self):
         try:

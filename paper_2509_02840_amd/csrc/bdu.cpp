@@ -22,6 +22,7 @@
 #include "device.h"
 #include "kernels.h"
 #include "plan.h"
+#include "track.h"
 
 using namespace bdu;
 
@@ -500,6 +501,7 @@ const char *bdu_strerror(int status)
     case BDU_EDEVICE: return "device error (handle poisoned)";
     case BDU_ENONFINITE: return "non-finite input";
     case BDU_EBUSY: return "queue full";
+    case BDU_ESPAN: return "update vector in the span of the tracked basis";
     default: return "unknown status";
     }
 }
@@ -1146,6 +1148,223 @@ int64_t bdu_plan_rotations(int64_t m, int64_t n, int32_t *side, int64_t *idx, in
         }
     }
     return k;
+}
+
+}  // extern "C"
+
+// ---- subspace tracking (Section 4) ---------------------------------------------
+
+struct bdu_track_ctx {
+    int64_t m = 0, n = 0, r = 0;
+    bdu_handle mid = nullptr;      // the (r+1) x (r+1) middle factorization
+    double *U[2] = {nullptr, nullptr}, *V[2] = {nullptr, nullptr};
+    int cur = 0;                   // U[cur], V[cur] hold the tracked factors
+    double *d = nullptr, *e = nullptr;
+    double *b = nullptr, *c = nullptr;    // staged update vectors
+    double *bh = nullptr, *ch = nullptr;  // projections (r + 1: the last is delta / gamma)
+    double *bp = nullptr, *cp = nullptr;  // complements, then unit vectors
+    double *norms = nullptr;              // delta, gamma (device)
+    int *kdrop = nullptr;                 // removed index (device)
+    double *h_info = nullptr;             // pinned: delta, gamma
+    int *h_k = nullptr;                   // pinned: removed index
+    bool have_last = false;
+    bool poisoned = false;
+    std::vector<void *> allocs;
+    std::vector<void *> pinned;
+};
+
+namespace {
+
+template <typename T>
+hipError_t talloc(bdu_track_ctx *t, T **p, int64_t count)
+{
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, (size_t)std::max<int64_t>(count, 1) * sizeof(T));
+    if (e == hipSuccess) {
+        t->allocs.push_back(q);
+        *p = (T *)q;
+    }
+    return e;
+}
+
+void track_free(bdu_track_ctx *t)
+{
+    if (t->mid) (void)hipStreamSynchronize(t->mid->stream);
+    for (void *p : t->allocs) (void)hipFree(p);
+    for (void *p : t->pinned) (void)hipHostFree(p);
+    if (t->mid) bdu_destroy(t->mid);
+    delete t;
+}
+
+TrackSides track_sides(bdu_track_ctx *t)
+{
+    TrackSides s;
+    s.side[0] = TrackSide{t->U[t->cur], t->m, t->r, t->m, t->b, t->bh, t->bp};
+    s.side[1] = TrackSide{t->V[t->cur], t->n, t->r, t->n, t->c, t->ch, t->cp};
+    return s;
+}
+
+TrackMiddle track_middle(bdu_track_ctx *t)
+{
+    const HandleDev &hd = t->mid->hd;
+    return TrackMiddle{hd.Q, hd.P, hd.d, hd.e, hd.ldq, hd.ldp, (int)(t->r + 1)};
+}
+
+}  // namespace
+
+extern "C" {
+
+int bdu_track_create(int64_t m, int64_t n, int64_t r, const double *U, const double *d, const double *e,
+                     const double *V, bdu_track *out)
+{
+    if (!out || !U || !d || !V || (r > 1 && !e) || r < 1 || m < r + 1 || n < r + 1 || r + 1 > 65535 ||
+        m > (int64_t)1 << 30 || n > (int64_t)1 << 30)
+        return BDU_EINVAL;
+    *out = nullptr;
+    const int64_t R = r + 1;
+    // the middle factorization starts as I [B 0; 0 0] I^T; its values are
+    // reset before every update
+    std::vector<double> I((size_t)(R * R), 0.0), dz((size_t)R, 0.0), ez((size_t)R, 0.0);
+    for (int64_t i = 0; i < R; ++i) I[(size_t)(i + i * R)] = 1.0;
+    bdu_track_ctx *t = new bdu_track_ctx;
+    t->m = m;
+    t->n = n;
+    t->r = r;
+    int st = bdu_create(R, R, I.data(), dz.data(), ez.data(), I.data(), &t->mid);
+    if (st != BDU_OK) {
+        t->mid = nullptr;
+        track_free(t);
+        return st;
+    }
+    hipError_t e2 = hipSuccess;
+    auto A = [&](hipError_t x) {
+        if (e2 == hipSuccess) e2 = x;
+    };
+    for (int k = 0; k < 2; ++k) {
+        A(talloc(t, &t->U[k], m * r));
+        A(talloc(t, &t->V[k], n * r));
+    }
+    A(talloc(t, &t->d, r));
+    A(talloc(t, &t->e, r));
+    A(talloc(t, &t->b, m));
+    A(talloc(t, &t->c, n));
+    A(talloc(t, &t->bh, R));
+    A(talloc(t, &t->ch, R));
+    A(talloc(t, &t->bp, m));
+    A(talloc(t, &t->cp, n));
+    A(talloc(t, &t->norms, 2));
+    A(talloc(t, &t->kdrop, 1));
+    if (e2 == hipSuccess) {
+        A(hipHostMalloc((void **)&t->h_info, 2 * sizeof(double), hipHostMallocDefault));
+        if (e2 == hipSuccess) t->pinned.push_back(t->h_info);
+        A(hipHostMalloc((void **)&t->h_k, sizeof(int), hipHostMallocDefault));
+        if (e2 == hipSuccess) t->pinned.push_back(t->h_k);
+    }
+    if (e2 != hipSuccess) {
+        track_free(t);
+        (void)hipGetLastError();
+        return e2 == hipErrorOutOfMemory ? BDU_ENOMEM : BDU_EDEVICE;
+    }
+    hipStream_t s = t->mid->stream;
+    A(copy_in(t->U[0], U, sizeof(double) * m * r, s));
+    A(copy_in(t->V[0], V, sizeof(double) * n * r, s));
+    A(copy_in(t->d, d, sizeof(double) * r, s));
+    if (r > 1) A(copy_in(t->e, e, sizeof(double) * (r - 1), s));
+    A(hipStreamSynchronize(s));
+    if (e2 != hipSuccess) {
+        track_free(t);
+        return BDU_EDEVICE;
+    }
+    st = check_finite(t->mid, {{t->U[0], m * r}, {t->V[0], n * r}, {t->d, r}, {t->e, r - 1}}, s);
+    if (st != BDU_OK) {
+        track_free(t);
+        return st;
+    }
+    *out = t;
+    return BDU_OK;
+}
+
+int bdu_track_update(bdu_track t, const double *b, const double *c)
+{
+    if (!t || !b || !c) return BDU_EINVAL;
+    if (t->poisoned || t->mid->poisoned) return BDU_EDEVICE;
+    hipStream_t s = t->mid->stream;
+#define TCHK(expr)                        \
+    do {                                  \
+        if ((expr) != hipSuccess) {       \
+            t->poisoned = true;           \
+            return BDU_EDEVICE;           \
+        }                                 \
+    } while (0)
+    TCHK(wait_dep(t->mid));
+    TCHK(copy_in(t->b, b, sizeof(double) * t->m, s));
+    TCHK(copy_in(t->c, c, sizeof(double) * t->n, s));
+    int st = check_finite(t->mid, {{t->b, t->m}, {t->c, t->n}}, s);
+    if (st != BDU_OK) return st;
+    const TrackSides sides = track_sides(t);
+    const int64_t rows = std::max(t->m, t->n);
+    // eq. (defup): projections, complements and their norms
+    TCHK(launch_track_project(sides, rows, t->r, s));
+    TCHK(launch_track_complement(sides, rows, t->norms, s));
+    TCHK(hipMemcpyAsync(t->h_info, t->norms, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    TCHK(hipStreamSynchronize(s));
+    if (!(t->h_info[0] > 0.0) || !(t->h_info[1] > 0.0)) return BDU_ESPAN;
+    // eq. (qrlr) and (equivlrup): one BGU pass on the middle matrix
+    TCHK(launch_track_scale(sides, rows, s));
+    const TrackMiddle mid = track_middle(t);
+    TCHK(launch_track_reset(mid, t->d, t->e, s));
+    st = bdu_update_projected(t->mid, t->bh, t->ch);
+    if (st != BDU_OK) {
+        t->poisoned = true;
+        return st;
+    }
+    // truncation and eq. (bdlrup)
+    const int nxt = 1 - t->cur;
+    TCHK(launch_track_finish(sides, mid, t->d, t->e, t->kdrop, rows, t->r, t->U[nxt], t->V[nxt], s));
+    TCHK(hipMemcpyAsync(t->h_k, t->kdrop, sizeof(int), hipMemcpyDeviceToHost, s));
+    t->cur = nxt;
+    t->have_last = true;
+#undef TCHK
+    return BDU_OK;
+}
+
+int bdu_track_sync(bdu_track t)
+{
+    if (!t) return BDU_EINVAL;
+    if (t->poisoned) return BDU_EDEVICE;
+    return hipStreamSynchronize(t->mid->stream) == hipSuccess ? BDU_OK : BDU_EDEVICE;
+}
+
+int bdu_track_read(bdu_track t, double *U, double *d, double *e, double *V)
+{
+    if (!t) return BDU_EINVAL;
+    if (t->poisoned) return BDU_EDEVICE;
+    hipStream_t s = t->mid->stream;
+    if (hipStreamSynchronize(s) != hipSuccess) return BDU_EDEVICE;
+    if (U && copy_out(U, t->U[t->cur], sizeof(double) * t->m * t->r, s) != hipSuccess) return BDU_EDEVICE;
+    if (V && copy_out(V, t->V[t->cur], sizeof(double) * t->n * t->r, s) != hipSuccess) return BDU_EDEVICE;
+    if (d && copy_out(d, t->d, sizeof(double) * t->r, s) != hipSuccess) return BDU_EDEVICE;
+    if (e && t->r > 1 && copy_out(e, t->e, sizeof(double) * (t->r - 1), s) != hipSuccess) return BDU_EDEVICE;
+    return hipStreamSynchronize(s) == hipSuccess ? BDU_OK : BDU_EDEVICE;
+}
+
+int bdu_track_last(bdu_track t, double *delta, double *gamma, int64_t *dropped)
+{
+    if (!t) return BDU_EINVAL;
+    if (t->poisoned) return BDU_EDEVICE;
+    if (!t->have_last) return BDU_EINVAL;
+    if (hipStreamSynchronize(t->mid->stream) != hipSuccess) return BDU_EDEVICE;
+    if (delta) *delta = t->h_info[0];
+    if (gamma) *gamma = t->h_info[1];
+    if (dropped) *dropped = *t->h_k;
+    return BDU_OK;
+}
+
+int bdu_track_destroy(bdu_track t)
+{
+    if (!t) return BDU_EINVAL;
+    track_free(t);
+    return BDU_OK;
 }
 
 }  // extern "C"

@@ -243,3 +243,25 @@ def test_staged_protocol_checker_sees_a_race():
 def test_finite_check_switch_validates_its_argument():
     assert bdu.lib().bdu_set_finite_check(2) == bdu.BDU_EINVAL
     assert bdu.lib().bdu_set_finite_check(0) == bdu.BDU_OK
+
+
+def test_tracking_rejects_bad_sizes_without_a_device():
+    import ctypes
+    L = bdu.lib()
+    h = ctypes.c_void_p()
+    U = np.zeros((4, 3), order="F")
+    d = np.ones(3)
+    e = np.ones(2)
+    V = np.zeros((5, 3), order="F")
+    # r + 1 > m
+    assert L.bdu_track_create(3, 5, 3, U.ctypes.data, d.ctypes.data, e.ctypes.data, V.ctypes.data,
+                              ctypes.byref(h)) == bdu.BDU_EINVAL
+    # r = 0
+    assert L.bdu_track_create(4, 5, 0, U.ctypes.data, d.ctypes.data, e.ctypes.data, V.ctypes.data,
+                              ctypes.byref(h)) == bdu.BDU_EINVAL
+    # e missing with r > 1
+    assert L.bdu_track_create(4, 5, 3, U.ctypes.data, d.ctypes.data, None, V.ctypes.data,
+                              ctypes.byref(h)) == bdu.BDU_EINVAL
+    assert L.bdu_track_update(None, None, None) == bdu.BDU_EINVAL
+    assert L.bdu_track_last(None, None, None, None) == bdu.BDU_EINVAL
+    assert L.bdu_strerror(bdu.BDU_ESPAN) == b"update vector in the span of the tracked basis"
