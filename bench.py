@@ -294,6 +294,62 @@ def serve(torch, bdu, args) -> int:
     return 0
 
 
+def track(torch, bdu, args) -> int:
+    """Subspace tracking (Section 4) on the recommendation shape: a thin
+    rank-r factorization of a users x items matrix (U, V Haar-like thin
+    orthonormal factors, d ~ U(1,10) descending, e ~ U(0,1)), updated with
+    b ~ N(0,1)/sqrt(m), c ~ N(0,1)/sqrt(n) and truncated back to rank r after
+    each update.  One update per call, each waited for (latency); inputs
+    resident on the device before the timed region."""
+    from paper_2509_02840_amd import workloads as W
+
+    m, n, r = args.track_m, args.track_n, args.track_r
+    U, d, e, V = W.tracking_state(m, n, r, args.seed)
+    t = bdu.Tracker(U, d, e, V)
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(args.seed)
+    total = args.warmup + args.track_steps
+    bs = torch.randn((total, m), generator=gen, dtype=torch.float64, device="cuda:0") / math.sqrt(m)
+    cs = torch.randn((total, n), generator=gen, dtype=torch.float64, device="cuda:0") / math.sqrt(n)
+    for k in range(args.warmup):
+        t.update(bs[k], cs[k])
+    t.sync()
+    bdu.timing_enable(True)
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.warmup, total):
+        ta = time.perf_counter()
+        t.update(bs[k], cs[k])
+        t.sync()
+        lat.append(time.perf_counter() - ta)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stages = bdu.timing_read()
+    bdu.timing_enable(False)
+    t.close()
+    line = {
+        "metric": "FP64 subspace-tracking rank-1 updates/sec + p50/p99 latency",
+        "value": args.track_steps / dt, "unit": "rank-1 updates/s", "steps": args.track_steps,
+        "ms_per_step": 1e3 * dt / args.track_steps, "p50_ms": 1e3 * float(np.percentile(lat, 50)),
+        "p99_ms": 1e3 * float(np.percentile(lat, 99)), "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"rank-{r} subspace tracking of a {m} x {n} users x items matrix, one rank-1 "
+                               "update per call, truncated back to rank r",
+                   "m": m, "n": n, "r": r},
+        "middle_stage_ms_per_step": {k: v[0] / args.track_steps for k, v in stages.items()},
+    }
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        bh, ch = W.tracking_update(m, n, args.seed + 1)
+        c0 = time.perf_counter()
+        O.track_update(U, d, e, V, bh, ch)
+        cdt = time.perf_counter() - c0
+        line["cpu_baseline"] = {"value": 1.0 / cdt, "unit": "rank-1 updates/s", "cores": 1, "kind": "oracle",
+                                "sample": f"one tracking update at this shape, single thread ({1e3 * cdt:.0f} ms)"}
+    print(json.dumps(line))
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -319,6 +375,12 @@ def main() -> int:
     ap.add_argument("--serve-rate", type=float, default=20000.0)
     ap.add_argument("--serve-queue", type=int, default=4)
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
+    ap.add_argument("--track", action="store_true",
+                    help="subspace tracking (Section 4) instead of the full-factorization benchmark")
+    ap.add_argument("--track-m", type=int, default=10000)
+    ap.add_argument("--track-n", type=int, default=2000)
+    ap.add_argument("--track-r", type=int, default=64)
+    ap.add_argument("--track-steps", type=int, default=200)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy three times (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -335,6 +397,8 @@ def main() -> int:
     from paper_2509_02840_amd import bdu
 
     torch.cuda.set_device(0)
+    if args.track:
+        return track(torch, bdu, args)
     if args.hetero:
         return hetero(torch, bdu, args)
     if args.serve > 0:

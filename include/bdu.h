@@ -249,10 +249,11 @@ int bdu_track_create(int64_t m, int64_t n, int64_t r, const double *U, const dou
                      const double *e, const double *V, bdu_track *out);
 
 /* One tracking update with b (m) and c (n), host or device:
- *   b_hat = U^T b (each entry a sequential fma over the rows, ascending),
- *   b_perp_i = b_i - sum_j U(i,j) b_hat_j (fma, j ascending),
- *   delta = sqrt(sum_i b_perp_i^2) (fma, i ascending); the same for c, V
- *   and gamma (eq. (defup));
+ *   b_hat = U^T b and delta^2 = sum_i b_perp_i^2 are chunked row sums
+ *   (chunks of 256 rows: a sequential fma from 0 inside a chunk, rows
+ *   ascending; the chunk partials added in ascending order from 0),
+ *   b_perp_i = b_i - sum_j U(i,j) b_hat_j (fma, j ascending); the same for
+ *   c, V and gamma (eq. (defup));
  *   one BGU pass (bdu_update_projected) on the (r+1) x (r+1) middle matrix
  *   [B 0; 0 0] + [b_hat; delta][c_hat; gamma]^T from identity factors
  *   (eq. (equivlrup)), giving Q2 Bbar P2^T;

@@ -446,23 +446,37 @@ int orc_bgu_update(int64_t m, int64_t n, double *Q, int64_t ldq, double *d,
 
 /* ---- subspace tracking: Section 4, eqs. (lrup)-(bdlrup) ----------------- */
 
-/* b_perp = b - Q1 (Q1^T b) with (Q1 b_hat)_i = sum_j Q1(i,j) b_hat_j
- * accumulated as fma, j ascending from 0; delta^2 = sum_i b_perp_i^2 the
- * same way, i ascending. */
+/* Sums over the rows of a tracked basis run in chunks of ORC_TRACK_CHUNK
+ * rows: inside a chunk a sequential fma from 0, rows ascending; the chunk
+ * partials then added in ascending order from 0. */
+static double chunk_dot(int64_t rows, const double *a, const double *b)
+{
+    double total = 0.0;
+    for (int64_t i0 = 0; i0 < rows; i0 += ORC_TRACK_CHUNK) {
+        const int64_t i1 = i0 + ORC_TRACK_CHUNK < rows ? i0 + ORC_TRACK_CHUNK : rows;
+        double p = 0.0;
+        for (int64_t i = i0; i < i1; ++i)
+            p = fma(a[i], b[i], p);
+        total = total + p;
+    }
+    return total;
+}
+
+/* x_hat = A^T x (chunked sums), x_perp = x - A x_hat with
+ * (A x_hat)_i = sum_j A(i,j) x_hat_j as fma, j ascending from 0, and
+ * norm = sqrt(x_perp^T x_perp) (chunked sum). */
 static void track_complement(int64_t rows, int64_t r, const double *A, int64_t lda,
                              const double *x, double *xhat, double *xperp, double *norm)
 {
-    orc_project(rows, r, A, lda, x, xhat);
+    for (int64_t j = 0; j < r; ++j)
+        xhat[j] = chunk_dot(rows, A + j * lda, x);
     for (int64_t i = 0; i < rows; ++i) {
         double s = 0.0;
         for (int64_t j = 0; j < r; ++j)
             s = fma(A[i + j * lda], xhat[j], s);
         xperp[i] = (g_mut == MUT_TRACK_RESID) ? x[i] + s : x[i] - s;
     }
-    double acc = 0.0;
-    for (int64_t i = 0; i < rows; ++i)
-        acc = fma(xperp[i], xperp[i], acc);
-    *norm = sqrt(acc);
+    *norm = sqrt(chunk_dot(rows, xperp, xperp));
 }
 
 /* out(:, j) = [A, w] M(:, keep_j): sequential fma over the r + 1 terms,

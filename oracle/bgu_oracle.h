@@ -95,12 +95,15 @@ int orc_bgu_update(int64_t m, int64_t n, double *Q, int64_t ldq, double *d,
 
 /* flags for orc_track_update */
 #define ORC_TRACK_KEEP_ALL 1 /* return the rank r+1 factorization (no truncation) */
+#define ORC_TRACK_CHUNK 256  /* rows per chunk of the tracking update's row sums */
 
 /* Subspace tracking (Section 4, eqs. (lrup)-(bdlrup)): the thin rank-r
  * factorization A = U B V^T (U m x r, V n x r orthonormal columns, B upper
  * bidiagonal with d (r), e (r-1)) updated with b c^T.
- *   b_hat = U^T b (orc_project order), b_perp_i = b_i - sum_j U(i,j) b_hat_j
- *   (fma, j ascending), delta = sqrt(sum_i b_perp_i^2) (fma, i ascending);
+ *   b_hat_j = sum_i U(i,j) b_i and delta^2 = sum_i b_perp_i^2 are chunked
+ *   sums: rows in chunks of ORC_TRACK_CHUNK, a sequential fma from 0 inside
+ *   a chunk, the partials added in ascending order from 0;
+ *   b_perp_i = b_i - sum_j U(i,j) b_hat_j (fma, j ascending);
  *   the same for c, V, gamma.
  *   One BGU pass (orc_bgu_update with Q = P = I) on the (r+1) x (r+1) matrix
  *   [B 0; 0 0] + [b_hat; delta][c_hat; gamma]^T gives Q2 Bbar P2^T.

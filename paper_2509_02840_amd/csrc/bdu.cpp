@@ -282,11 +282,13 @@ int ensure_rcap(bdu_ctx *h, int r)
 // Rotation stages of one pass (spike, generation, application) for `count`
 // handles listed in the device array hs (all with the same tiling).
 hipError_t run_rotation_stages(HandleDev *const *hs, int count, bool any_spike, int64_t lds_bytes,
-                               bool in_lds, int max_panels, int k0, int nw, int rpl, Gate gate, hipStream_t st)
+                               bool in_lds, int gen_threads, int max_panels, int k0, int nw, int rpl, Gate gate,
+                               hipStream_t st)
 {
     hipError_t e = hipSuccess;
     if (any_spike) e = timed(ST_SPIKE, st, [&] { return launch_spike(hs, count, gate, st); });
-    if (e == hipSuccess) e = timed(ST_GEN, st, [&] { return launch_gen(hs, count, lds_bytes, in_lds, gate, st); });
+    if (e == hipSuccess)
+        e = timed(ST_GEN, st, [&] { return launch_gen(hs, count, lds_bytes, in_lds, gen_threads, gate, st); });
     if (e == hipSuccess)
         e = timed(ST_APPLY, st, [&] { return launch_apply(hs, count, max_panels, k0, nw, rpl, gate, st); });
     return e;
@@ -307,7 +309,8 @@ int pass_single(bdu_ctx *h, int pass, bool project)
                   [&] { return launch_project(h->d_self, 1, tiles_of(h), Gate{nullptr, pass}, h->stream); });
     if (e == hipSuccess)
         e = run_rotation_stages(h->d_self, 1, h->m > h->n, gen_lds_bytes(h->n, h->plan->N), h->lds_gen,
-                                panels_of(h), h->plan->K0, h->plan->NW, h->rpl, Gate{nullptr, pass}, h->stream);
+                                h->plan->L, panels_of(h), h->plan->K0, h->plan->NW, h->rpl, Gate{nullptr, pass},
+                                h->stream);
     if (e != hipSuccess) {
         h->poisoned = true;
         return BDU_EDEVICE;
@@ -375,6 +378,7 @@ struct bdu_batch_ctx {
         bool spike, in_lds;
         int64_t lds;
         int tiles, panels, off, cnt;
+        int gen_threads;  // largest plan thread count of the group
     };
     std::vector<Group> groups;  // handles of one applier tiling, contiguous in the arrays
     HandleDev **d_ptrs = nullptr;
@@ -434,13 +438,14 @@ int batch_build(const bdu_handle *hs, int count, int maxr, bool graph, bdu_batch
             if (x.k0 == h->plan->K0 && x.nw == h->plan->NW && x.rpl == h->rpl && x.in_lds == h->lds_gen) break;
         }
         if (g == b->groups.size()) {
-            b->groups.push_back({h->plan->K0, h->plan->NW, h->rpl, false, h->lds_gen, 0, 0, 0, 0, 0});
+            b->groups.push_back({h->plan->K0, h->plan->NW, h->rpl, false, h->lds_gen, 0, 0, 0, 0, 0, 64});
             members.emplace_back();
         }
         auto &x = b->groups[g];
         members[g].push_back(i);
         x.spike |= h->m > h->n;
         x.lds = std::max<int64_t>(x.lds, gen_lds_bytes(h->n, h->plan->N));
+        x.gen_threads = std::max(x.gen_threads, h->plan->L);
         x.tiles = std::max(x.tiles, tiles_of(h));
         x.panels = std::max(x.panels, panels_of(h));
     }
@@ -481,7 +486,8 @@ hipError_t batch_launch(bdu_batch b)
             const Gate gate{b->d_ranks + g.off, p};
             hipError_t e = timed(ST_PROJECT, st, [&] { return launch_project(arr, g.cnt, g.tiles, gate, st); });
             if (e == hipSuccess)
-                e = run_rotation_stages(arr, g.cnt, g.spike, g.lds, g.in_lds, g.panels, g.k0, g.nw, g.rpl, gate, st);
+                e = run_rotation_stages(arr, g.cnt, g.spike, g.lds, g.in_lds, g.gen_threads, g.panels, g.k0, g.nw,
+                                        g.rpl, gate, st);
             if (e != hipSuccess) return e;
         }
     }
@@ -1163,6 +1169,8 @@ struct bdu_track_ctx {
     double *b = nullptr, *c = nullptr;    // staged update vectors
     double *bh = nullptr, *ch = nullptr;  // projections (r + 1: the last is delta / gamma)
     double *bp = nullptr, *cp = nullptr;  // complements, then unit vectors
+    double *part = nullptr;               // chunk partials of the projections
+    double *npart = nullptr;              // chunk partials of the squared norms
     double *norms = nullptr;              // delta, gamma (device)
     int *kdrop = nullptr;                 // removed index (device)
     double *h_info = nullptr;             // pinned: delta, gamma
@@ -1252,6 +1260,9 @@ int bdu_track_create(int64_t m, int64_t n, int64_t r, const double *U, const dou
     A(talloc(t, &t->ch, R));
     A(talloc(t, &t->bp, m));
     A(talloc(t, &t->cp, n));
+    const int64_t nchunk = (std::max(m, n) + kTrackChunk - 1) / kTrackChunk;
+    A(talloc(t, &t->part, 2 * nchunk * r));
+    A(talloc(t, &t->npart, 2 * nchunk));
     A(talloc(t, &t->norms, 2));
     A(talloc(t, &t->kdrop, 1));
     if (e2 == hipSuccess) {
@@ -1304,8 +1315,8 @@ int bdu_track_update(bdu_track t, const double *b, const double *c)
     const TrackSides sides = track_sides(t);
     const int64_t rows = std::max(t->m, t->n);
     // eq. (defup): projections, complements and their norms
-    TCHK(launch_track_project(sides, rows, t->r, s));
-    TCHK(launch_track_complement(sides, rows, t->norms, s));
+    TCHK(launch_track_project(sides, rows, t->r, t->part, s));
+    TCHK(launch_track_complement(sides, rows, t->npart, t->norms, s));
     TCHK(hipMemcpyAsync(t->h_info, t->norms, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     TCHK(hipStreamSynchronize(s));
     if (!(t->h_info[0] > 0.0) || !(t->h_info[1] > 0.0)) return BDU_ESPAN;

@@ -342,14 +342,16 @@ hipError_t prepare_kernels()
     return hipSuccess;
 }
 
-hipError_t launch_gen(HandleDev *const *hs, int count, int64_t lds_bytes, bool in_lds, Gate gate, hipStream_t st)
+hipError_t launch_gen(HandleDev *const *hs, int count, int64_t lds_bytes, bool in_lds, int threads, Gate gate,
+                      hipStream_t st)
 {
+    if (threads < 64 || threads > kGenThreads || threads % 64) return hipErrorInvalidValue;
     if (in_lds) {
         hipError_t e = prepare_kernels();
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(gen_kernel<true>, dim3(count), dim3(kGenThreads), (size_t)lds_bytes, st, hs, gate);
+        hipLaunchKernelGGL(gen_kernel<true>, dim3(count), dim3(threads), (size_t)lds_bytes, st, hs, gate);
     } else {
-        hipLaunchKernelGGL(gen_kernel<false>, dim3(count), dim3(kGenThreads), 0, st, hs, gate);
+        hipLaunchKernelGGL(gen_kernel<false>, dim3(count), dim3(threads), 0, st, hs, gate);
     }
     return hipGetLastError();
 }

@@ -12,7 +12,10 @@ namespace bdu {
 // projection reads column gate.pass of the staged B and C.
 hipError_t launch_project(HandleDev *const *hs, int count, int max_tiles, Gate gate, hipStream_t st);
 hipError_t launch_spike(HandleDev *const *hs, int count, Gate gate, hipStream_t st);
-hipError_t launch_gen(HandleDev *const *hs, int count, int64_t lds_bytes, bool in_lds, Gate gate, hipStream_t st);
+// threads: the largest plan thread count (Plan::L) of the launch's handles;
+// a handle with fewer chains than threads runs one chain per thread.
+hipError_t launch_gen(HandleDev *const *hs, int count, int64_t lds_bytes, bool in_lds, int threads, Gate gate,
+                      hipStream_t st);
 hipError_t launch_apply(HandleDev *const *hs, int count, int max_panels, int k0, int nw, int rpl, Gate gate,
                         hipStream_t st);
 // One-time kernel attributes; call before capturing launches in a graph.

@@ -84,7 +84,12 @@ std::unique_ptr<Plan> build_plan(int64_t m, int64_t n, int K0, int NW, int gen_t
         fn(lastu[N + off]);
         fn(lastv[nn + off]);
     };
-    std::vector<int64_t> lane_free(gen_threads, 0);
+    // With fewer chains than threads every chain gets its own thread, so
+    // the workgroup only needs that many (rounded to whole wavefronts):
+    // fewer wavefronts meet at every tick's barrier.
+    const int L = (int)std::min<int64_t>(gen_threads, std::max<int64_t>(64, ((int64_t)ch.size() + 63) / 64 * 64));
+    P->L = L;
+    std::vector<int64_t> lane_free(L, 0);
     int64_t tend = 0;
     for (size_t c = 0; c < ch.size(); ++c) {
         GenChain &g = ch[c];
@@ -94,7 +99,7 @@ std::unique_ptr<Plan> build_plan(int64_t m, int64_t n, int K0, int NW, int gen_t
             if (g.type == CH_FOLD) fold_cells(need);
             else cells(decode(g.type, g.param, s), need);
         }
-        int lane = (int)(c % gen_threads);
+        int lane = (int)(c % L);
         tau0 = std::max(tau0, lane_free[lane]);
         for (int s = 0; s < g.len; ++s) {
             auto mark = [&](int64_t &t) { t = std::max(t, tau0 + s); };

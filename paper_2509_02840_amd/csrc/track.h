@@ -6,6 +6,10 @@
 
 namespace bdu {
 
+// Rows per chunk of the row sums (a sequential fma inside a chunk, chunk
+// partials added in ascending order).
+constexpr int kTrackChunk = 256;
+
 // One side of the tracking update: the tracked basis A (rows x cols,
 // column-major, leading dimension lda = rows), the new vector x (rows),
 // its projection xhat (cols + 1: the last entry receives the complement's
@@ -27,8 +31,10 @@ struct TrackMiddle {
     int R;
 };
 
-hipError_t launch_track_project(const TrackSides &s, int64_t max_rows, int64_t r, hipStream_t st);
-hipError_t launch_track_complement(const TrackSides &s, int64_t max_rows, double *norms, hipStream_t st);
+// part: 2 * ceil(max_rows / kTrackChunk) * r doubles; npart: 2 * ceil(max_rows / kTrackChunk).
+hipError_t launch_track_project(const TrackSides &s, int64_t max_rows, int64_t r, double *part, hipStream_t st);
+hipError_t launch_track_complement(const TrackSides &s, int64_t max_rows, double *npart, double *norms,
+                                   hipStream_t st);
 hipError_t launch_track_scale(const TrackSides &s, int64_t max_rows, hipStream_t st);
 hipError_t launch_track_reset(const TrackMiddle &mid, const double *d, const double *e, hipStream_t st);
 hipError_t launch_track_finish(const TrackSides &s, const TrackMiddle &mid, double *d, double *e, int *kdrop,

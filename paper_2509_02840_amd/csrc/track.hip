@@ -11,55 +11,91 @@
 
 namespace bdu {
 
-// y_j = sum_i A(i, j) x_i, acc = fma(A(i, j), x_i, acc), i ascending from 0.
-// One lane per output column; 64 x 64 tiles of A pass through LDS so that
-// the global reads run down the columns.  grid (ceil(cols / 64), 2 sides).
-__global__ __launch_bounds__(64) void track_project_kernel(TrackSides s)
+// Row sums over a tracked basis run in chunks of kTrackChunk rows: a
+// sequential fma from 0 inside a chunk (rows ascending), then the chunk
+// partials added in ascending order from 0.
+
+// part[side][k][j] = sum over the rows i of chunk k of A(i, j) x_i.  grid
+// (chunks, ceil(cols / 64), 2 sides), one lane per column j; each lane runs
+// down its own column, 32 loads ahead.
+__global__ __launch_bounds__(64) void track_partial_kernel(TrackSides s, double *part, int64_t nchunk)
 {
-    __shared__ double tile[64][65];
-    __shared__ double xs[64];
-    const TrackSide &t = s.side[blockIdx.y];
-    const int lane = threadIdx.x;
-    const int64_t j0 = (int64_t)blockIdx.x * 64;
-    if (j0 >= t.cols) return;
-    const int64_t j = j0 + lane;
-    double acc = 0.0;
-    for (int64_t i0 = 0; i0 < t.rows; i0 += 64) {
-        const int64_t i = i0 + lane;
-        for (int c = 0; c < 64; ++c)
-            tile[c][lane] = (i < t.rows && j0 + c < t.cols) ? t.A[i + (j0 + c) * t.lda] : 0.0;
-        xs[lane] = i < t.rows ? t.x[i] : 0.0;
-        __syncthreads();
-        const int nr = t.rows - i0 < 64 ? (int)(t.rows - i0) : 64;
-        for (int k = 0; k < nr; ++k) acc = fma(tile[lane][k], xs[k], acc);
-        __syncthreads();
+    const TrackSide &t = s.side[blockIdx.z];
+    const int64_t i0 = (int64_t)blockIdx.x * kTrackChunk;
+    const int64_t j = (int64_t)blockIdx.y * 64 + threadIdx.x;
+    if (i0 >= t.rows || j >= t.cols) return;
+    const int64_t i1 = i0 + kTrackChunk < t.rows ? i0 + kTrackChunk : t.rows;
+    const double *a = t.A + j * t.lda;
+    double p = 0.0;
+    int64_t i = i0;
+    for (; i + 32 <= i1; i += 32) {
+        double av[32], xv[32];
+#pragma unroll
+        for (int q = 0; q < 32; ++q) {
+            av[q] = a[i + q];
+            xv[q] = t.x[i + q];
+        }
+#pragma unroll
+        for (int q = 0; q < 32; ++q) p = fma(av[q], xv[q], p);
     }
-    if (j < t.cols) t.xhat[j] = acc;
+    for (; i < i1; ++i) p = fma(a[i], t.x[i], p);
+    part[((int64_t)blockIdx.z * nchunk + blockIdx.x) * t.cols + j] = p;
 }
 
-// xperp_i = x_i - s_i, s_i = sum_j A(i, j) xhat_j (fma, j ascending).
-// grid (ceil(rows / 256), 2 sides), 256 lanes, one per row.
-__global__ __launch_bounds__(256) void track_residual_kernel(TrackSides s)
+// xhat_j = sum over chunks k (ascending) of part[side][k][j], from 0.
+// grid (ceil(cols / 64), 2 sides).
+__global__ __launch_bounds__(64) void track_combine_kernel(TrackSides s, const double *part, int64_t nchunk)
 {
     const TrackSide &t = s.side[blockIdx.y];
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= t.rows) return;
-    double acc = 0.0;
-    for (int64_t j = 0; j < t.cols; ++j) acc = fma(t.A[i + j * t.lda], t.xhat[j], acc);
-    t.xperp[i] = t.x[i] - acc;
+    const int64_t j = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    if (j >= t.cols) return;
+    const int64_t nk = (t.rows + kTrackChunk - 1) / kTrackChunk;
+    double total = 0.0;
+    for (int64_t k = 0; k < nk; ++k) total = total + part[((int64_t)blockIdx.y * nchunk + k) * t.cols + j];
+    t.xhat[j] = total;
 }
 
-// norm = sqrt(sum_i xperp_i^2), acc = fma(xperp_i, xperp_i, acc), i
-// ascending: lane 0 for side 0, lane 1 for side 1.  The norm becomes the
-// last entry of the middle update vector and is copied to norms[side].
-__global__ __launch_bounds__(64) void track_norm_kernel(TrackSides s, double *norms)
+// xperp_i = x_i - s_i, s_i = sum_j A(i, j) xhat_j (fma, j ascending); one
+// block per chunk of rows, one lane per row; lane 0 then sums the chunk's
+// xperp_i^2 in row order (fma from 0) into npart[side][chunk].
+// grid (chunks, 2 sides), kTrackChunk lanes.
+__global__ __launch_bounds__(kTrackChunk) void track_residual_kernel(TrackSides s, double *npart, int64_t nchunk)
+{
+    __shared__ double sq[kTrackChunk];
+    const TrackSide &t = s.side[blockIdx.y];
+    const int64_t i0 = (int64_t)blockIdx.x * kTrackChunk;
+    if (i0 >= t.rows) return;
+    const int64_t i = i0 + threadIdx.x;
+    double xp = 0.0;
+    if (i < t.rows) {
+        double acc = 0.0;
+        for (int64_t j = 0; j < t.cols; ++j) acc = fma(t.A[i + j * t.lda], t.xhat[j], acc);
+        xp = t.x[i] - acc;
+        t.xperp[i] = xp;
+    }
+    sq[threadIdx.x] = xp;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int cnt = t.rows - i0 < kTrackChunk ? (int)(t.rows - i0) : kTrackChunk;
+        double p = 0.0;
+        for (int q = 0; q < cnt; ++q) p = fma(sq[q], sq[q], p);
+        npart[(int64_t)blockIdx.y * nchunk + blockIdx.x] = p;
+    }
+}
+
+// norm = sqrt(sum over chunks (ascending, from 0) of npart): lane 0 for
+// side 0, lane 1 for side 1.  The norm becomes the last entry of the middle
+// update vector and is copied to norms[side].
+__global__ __launch_bounds__(64) void track_norm_kernel(TrackSides s, const double *npart, int64_t nchunk,
+                                                        double *norms)
 {
     const int side = threadIdx.x;
     if (side > 1) return;
     const TrackSide &t = s.side[side];
-    double acc = 0.0;
-    for (int64_t i = 0; i < t.rows; ++i) acc = fma(t.xperp[i], t.xperp[i], acc);
-    const double nrm = sqrt(acc);
+    const int64_t nk = (t.rows + kTrackChunk - 1) / kTrackChunk;
+    double total = 0.0;
+    for (int64_t k = 0; k < nk; ++k) total = total + npart[(int64_t)side * nchunk + k];
+    const double nrm = sqrt(total);
     t.xhat[t.cols] = nrm;
     norms[side] = nrm;
 }
@@ -133,18 +169,22 @@ __global__ __launch_bounds__(256) void track_product_kernel(TrackSides s, TrackM
     (blockIdx.z == 0 ? out0 : out1)[i + (int64_t)j * t.lda] = acc;
 }
 
-hipError_t launch_track_project(const TrackSides &s, int64_t max_rows, int64_t r, hipStream_t st)
+hipError_t launch_track_project(const TrackSides &s, int64_t max_rows, int64_t r, double *part, hipStream_t st)
 {
-    (void)max_rows;
-    hipLaunchKernelGGL(track_project_kernel, dim3((unsigned)((r + 63) / 64), 2), dim3(64), 0, st, s);
+    const int64_t nchunk = (max_rows + kTrackChunk - 1) / kTrackChunk;
+    hipLaunchKernelGGL(track_partial_kernel, dim3((unsigned)nchunk, (unsigned)((r + 63) / 64), 2), dim3(64), 0, st, s,
+                       part, nchunk);
+    hipLaunchKernelGGL(track_combine_kernel, dim3((unsigned)((r + 63) / 64), 2), dim3(64), 0, st, s,
+                       (const double *)part, nchunk);
     return hipGetLastError();
 }
 
-hipError_t launch_track_complement(const TrackSides &s, int64_t max_rows, double *norms, hipStream_t st)
+hipError_t launch_track_complement(const TrackSides &s, int64_t max_rows, double *npart, double *norms,
+                                   hipStream_t st)
 {
-    const dim3 g((unsigned)((max_rows + 255) / 256), 2);
-    hipLaunchKernelGGL(track_residual_kernel, g, dim3(256), 0, st, s);
-    hipLaunchKernelGGL(track_norm_kernel, dim3(1), dim3(64), 0, st, s, norms);
+    const int64_t nchunk = (max_rows + kTrackChunk - 1) / kTrackChunk;
+    hipLaunchKernelGGL(track_residual_kernel, dim3((unsigned)nchunk, 2), dim3(kTrackChunk), 0, st, s, npart, nchunk);
+    hipLaunchKernelGGL(track_norm_kernel, dim3(1), dim3(64), 0, st, s, (const double *)npart, nchunk, norms);
     return hipGetLastError();
 }
 
