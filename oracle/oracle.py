@@ -269,3 +269,25 @@ def track_update(U, d, e, V, b, c, keep_all: bool = False):
 
 def set_mutation(k: int) -> None:
     lib().orc_set_mutation(k)
+
+
+# ---- orthogonality monitor and correction (test infrastructure) -----------
+# The paper reorthogonalizes its factors "only a few times" without saying
+# how.  The reading used here: the drift of a factor X is the Frobenius norm
+# of E = X^T X - I, and the correction is one Newton-Schulz step towards the
+# orthogonal polar factor of X, X <- X - X E / 2 (the nearest orthogonal
+# matrix; from a drift e the step leaves a drift of order e^2).  Plain
+# numpy products, fp64.
+
+def orth_gram(X):
+    X = np.asarray(X, dtype=np.float64)
+    return X.T @ X - np.eye(X.shape[1])
+
+
+def orth_error(X) -> float:
+    return float(np.sqrt(np.sum(orth_gram(X) ** 2)))
+
+
+def reorth_step(X):
+    X = np.asarray(X, dtype=np.float64)
+    return X - (X @ orth_gram(X)) / 2.0
