@@ -233,6 +233,27 @@ int bdu_timing_read(double *ms, int64_t *launches);
 int bdu_givens_device(const double *a, const double *b, int mode, double *c,
                       double *s, double *r, int64_t count);
 
+/* ---- orthogonality monitor and correction ----------------------------- */
+
+/* Over a long stream of updates the accumulated rotations leave Q and P
+ * orthogonal only up to rounding; the paper reorthogonalizes its factors a
+ * few times without saying how.  Drift of a factor X: ||X^T X - I||_F,
+ * computed on the FP64 matrix cores (the sums' order is not fixed: results
+ * agree with a plain fp64 product to within the rounding of a length-m dot
+ * product).  eq / ep (either may be NULL) receive the drift of Q and P.
+ * Synchronizes the handle's stream.  BDU_ENOMEM if the scratch (about
+ * 8 max(m,n)^2 + 8 ld m bytes, allocated on first use and kept) does not
+ * fit. */
+int bdu_orth_error(bdu_handle h, double *eq, double *ep);
+
+/* Measure the drift as above and, for each factor whose drift exceeds tol
+ * (every factor if tol <= 0), take one Newton-Schulz step
+ * X <- X - X (X^T X - I) / 2 towards its orthogonal polar factor (the
+ * nearest orthogonal matrix): from drift e it leaves a drift of order e^2,
+ * and the represented matrix Q Bd P^T moves by O(e) ||A||.  eq / ep receive
+ * the drift measured before the step. */
+int bdu_reorthogonalize(bdu_handle h, double tol, double *eq, double *ep);
+
 /* ---- subspace tracking (Section 4, eqs. (lrup)-(bdlrup)) ------------ */
 
 /* A thin rank-r factorization A = U B V^T (U m x r and V n x r with

@@ -68,6 +68,9 @@ def lib():
         L.bdu_autotune.argtypes = [i64, i64, i32, ctypes.POINTER(i64)]
         L.bdu_set_generation_in_lds.argtypes = [i32]
         L.bdu_set_finite_check.argtypes = [i32]
+        L.bdu_orth_error.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+        L.bdu_reorthogonalize.argtypes = [vp, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_double)]
         L.bdu_track_create.argtypes = [i64, i64, i64, vp, vp, vp, vp, ctypes.POINTER(vp)]
         L.bdu_track_update.argtypes = [vp, vp, vp]
         L.bdu_track_sync.argtypes = [vp]
@@ -280,6 +283,19 @@ class Handle:
 
     def sync(self) -> None:
         _check(lib().bdu_sync(self._h), "bdu_sync")
+
+    def orth_error(self):
+        """(||Q^T Q - I||_F, ||P^T P - I||_F) measured on the device."""
+        eq, ep = ctypes.c_double(), ctypes.c_double()
+        _check(lib().bdu_orth_error(self._h, ctypes.byref(eq), ctypes.byref(ep)), "bdu_orth_error")
+        return eq.value, ep.value
+
+    def reorthogonalize(self, tol: float = 0.0):
+        """One Newton-Schulz step on each factor whose drift exceeds tol
+        (every factor if tol <= 0); returns the drifts measured before."""
+        eq, ep = ctypes.c_double(), ctypes.c_double()
+        _check(lib().bdu_reorthogonalize(self._h, tol, ctypes.byref(eq), ctypes.byref(ep)), "bdu_reorthogonalize")
+        return eq.value, ep.value
 
     def tiling(self):
         k0, nw, rpl = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()

@@ -22,6 +22,7 @@
 #include "device.h"
 #include "kernels.h"
 #include "plan.h"
+#include "orth.h"
 #include "track.h"
 
 using namespace bdu;
@@ -159,6 +160,8 @@ struct bdu_ctx {
     int *flag = nullptr;       // device flag of the non-finite input check
     hipEvent_t ev = nullptr;   // marks this handle's own stream work for a batch to wait on
     hipEvent_t dep = nullptr;  // completion of the last batch step this handle was in
+    // orthogonality monitor scratch (allocated on first use)
+    double *orthE = nullptr, *orthY = nullptr, *orthPart = nullptr, *orthOut = nullptr;
     std::vector<void *> allocs;
 };
 
@@ -1154,6 +1157,76 @@ int64_t bdu_plan_rotations(int64_t m, int64_t n, int32_t *side, int64_t *idx, in
         }
     }
     return k;
+}
+
+}  // extern "C"
+
+// ---- orthogonality monitor and correction ----------------------------------------
+
+namespace {
+
+int orth_scratch(bdu_ctx *h)
+{
+    if (h->orthE) return BDU_OK;
+    const int64_t lde = (std::max(h->m, h->n) + 63) / 64 * 64;
+    const int64_t ymax = std::max<int64_t>((int64_t)h->hd.ldq * h->m, (int64_t)h->hd.ldp * h->n);
+    double *E = nullptr, *Y = nullptr, *part = nullptr, *out = nullptr;
+    if (dalloc(h, &E, lde * lde) != hipSuccess || dalloc(h, &Y, ymax) != hipSuccess ||
+        dalloc(h, &part, lde) != hipSuccess || dalloc(h, &out, 2) != hipSuccess) {
+        (void)hipGetLastError();
+        return BDU_ENOMEM;
+    }
+    h->orthE = E;
+    h->orthY = Y;
+    h->orthPart = part;
+    h->orthOut = out;
+    return BDU_OK;
+}
+
+// Drift ||X^T X - I||_F of one factor (X: ld x k on the device); with fix,
+// one Newton-Schulz step X <- X - X E / 2 when the drift exceeds tol (or
+// tol <= 0).
+int orth_side(bdu_ctx *h, double *X, int64_t ld, int64_t k, bool fix, double tol, double *err)
+{
+    const int64_t lde = (k + 63) / 64 * 64;
+    hipStream_t st = h->stream;
+    double e = 0.0;
+    HIPCHK(h, launch_orth_gram(X, ld, k, h->orthE, lde, st));
+    HIPCHK(h, launch_orth_norm(h->orthE, k, lde, h->orthPart, h->orthOut, st));
+    HIPCHK(h, hipMemcpyAsync(&e, h->orthOut, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(h, hipStreamSynchronize(st));
+    if (err) *err = e;
+    if (fix && (tol <= 0.0 || e > tol)) {
+        HIPCHK(h, launch_orth_update(X, ld, k, h->orthE, lde, h->orthY, st));
+        HIPCHK(h, hipMemcpyAsync(X, h->orthY, sizeof(double) * ld * k, hipMemcpyDeviceToDevice, st));
+    }
+    return BDU_OK;
+}
+
+int orth_both(bdu_handle h, bool fix, double tol, double *eq, double *ep)
+{
+    if (!h) return BDU_EINVAL;
+    if (h->poisoned) return BDU_EDEVICE;
+    HIPCHK(h, wait_dep(h));
+    int st = orth_scratch(h);
+    if (st != BDU_OK) return st;
+    st = orth_side(h, h->hd.Q, h->hd.ldq, h->m, fix, tol, eq);
+    if (st == BDU_OK) st = orth_side(h, h->hd.P, h->hd.ldp, h->n, fix, tol, ep);
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bdu_orth_error(bdu_handle h, double *eq, double *ep)
+{
+    return orth_both(h, false, 0.0, eq, ep);
+}
+
+int bdu_reorthogonalize(bdu_handle h, double tol, double *eq, double *ep)
+{
+    return orth_both(h, true, tol, eq, ep);
 }
 
 }  // extern "C"

@@ -265,3 +265,9 @@ def test_tracking_rejects_bad_sizes_without_a_device():
     assert L.bdu_track_update(None, None, None) == bdu.BDU_EINVAL
     assert L.bdu_track_last(None, None, None, None) == bdu.BDU_EINVAL
     assert L.bdu_strerror(bdu.BDU_ESPAN) == b"update vector in the span of the tracked basis"
+
+
+def test_orthogonality_calls_reject_a_null_handle():
+    L = bdu.lib()
+    assert L.bdu_orth_error(None, None, None) == bdu.BDU_EINVAL
+    assert L.bdu_reorthogonalize(None, 0.0, None, None) == bdu.BDU_EINVAL
