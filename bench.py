@@ -350,6 +350,45 @@ def track(torch, bdu, args) -> int:
     return 0
 
 
+def orth(torch, bdu, args) -> int:
+    """Orthogonality monitor and correction at m = n = args.n: drift
+    measurement (X^T X - I on the FP64 matrix cores) and one Newton-Schulz
+    step on both factors of one stream, each call waited for.  Flops per
+    factor of size k (ld rows): gram 2 ld k^2 on the blocks computed (the
+    upper half and the diagonal blocks, mirrored), update 2 ld k^2."""
+    n = args.n
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(args.seed)
+    Q, d, e, P = random_stream(torch, gen, n)
+    h = bdu.Handle(Q, d, e, P)
+    del Q, P
+    h.orth_error()  # scratch allocation and warm-up
+    h.reorthogonalize(0.0)
+    k = args.orth_steps
+    t0 = time.perf_counter()
+    for _ in range(k):
+        eq, ep = h.orth_error()
+    t_mon = (time.perf_counter() - t0) / k
+    t0 = time.perf_counter()
+    for _ in range(k):
+        h.reorthogonalize(0.0)
+    h.sync()
+    t_fix = (time.perf_counter() - t0) / k
+    h.close()
+    ld = (n + 127) // 128 * 128
+    nb = (n + 63) // 64
+    gram_flops = 2.0 * ld * (64 * 64) * (nb * (nb + 1) // 2)  # upper blocks incl. the diagonal
+    upd_flops = 2.0 * ld * n * n
+    print(json.dumps({
+        "metric": "orthogonality monitor / Newton-Schulz correction, one stream, both factors",
+        "n": n, "monitor_ms": 1e3 * t_mon, "correction_ms": 1e3 * t_fix, "drift_q": eq, "drift_p": ep,
+        "monitor_tflops_wall": 2 * gram_flops / t_mon / 1e12,
+        "correction_tflops_wall": 2 * (gram_flops + upd_flops) / t_fix / 1e12,
+        "flops": {"gram_per_factor": gram_flops, "update_per_factor": upd_flops},
+        "dtype": "f64", "data": "synthetic"}))
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -375,6 +414,9 @@ def main() -> int:
     ap.add_argument("--serve-rate", type=float, default=20000.0)
     ap.add_argument("--serve-queue", type=int, default=4)
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
+    ap.add_argument("--orth", action="store_true",
+                    help="time the orthogonality monitor and correction at m = n = --n")
+    ap.add_argument("--orth-steps", type=int, default=10)
     ap.add_argument("--track", action="store_true",
                     help="subspace tracking (Section 4) instead of the full-factorization benchmark")
     ap.add_argument("--track-m", type=int, default=10000)
@@ -399,6 +441,8 @@ def main() -> int:
     torch.cuda.set_device(0)
     if args.track:
         return track(torch, bdu, args)
+    if args.orth:
+        return orth(torch, bdu, args)
     if args.hetero:
         return hetero(torch, bdu, args)
     if args.serve > 0:
