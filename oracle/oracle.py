@@ -291,3 +291,35 @@ def orth_error(X) -> float:
 def reorth_step(X):
     X = np.asarray(X, dtype=np.float64)
     return X - (X @ orth_gram(X)) / 2.0
+
+
+# ---- truncated bidiagonal approximation (Section 2, eqs. (trBD), (errtrBD)) --
+
+def truncated_bd(Q, d, e, P, r: int):
+    """Best rank-r truncated bidiagonal approximation of A = Q Bd P^T: keep
+    the r columns i of Bd with the largest t_i = d_i^2 + e_{i-1}^2 (each
+    product and the sum rounded on their own; e_0 = 0; ties keep the lower
+    index), so that A_r = Qr Pr^T with Qr(:, j) = d_i q_i + e_{i-1} q_{i-1}
+    and Pr(:, j) = p_i, i = idx[j] in the selection order; the squared
+    Frobenius error is the sum of the dropped t_i (ascending i).
+    Returns (idx, err2, Qr, Pr)."""
+    Q = np.asarray(Q, dtype=np.float64)
+    P = np.asarray(P, dtype=np.float64)
+    d = np.asarray(d, dtype=np.float64)
+    e = np.asarray(e, dtype=np.float64)
+    n = d.shape[0]
+    t = d * d
+    t[1:] = t[1:] + e * e
+    idx = np.argsort(-t, kind="stable")[:r]
+    keep = np.zeros(n, dtype=bool)
+    keep[idx] = True
+    err2 = 0.0
+    for i in range(n):
+        if not keep[i]:
+            err2 = err2 + float(t[i])
+    Qr = np.empty((Q.shape[0], r), order="F")
+    Pr = np.empty((P.shape[0], r), order="F")
+    for j, i in enumerate(idx):
+        Qr[:, j] = d[i] * Q[:, i] if i == 0 else d[i] * Q[:, i] + e[i - 1] * Q[:, i - 1]
+        Pr[:, j] = P[:, i]
+    return idx.astype(np.int64), err2, Qr, Pr
