@@ -254,6 +254,19 @@ int bdu_orth_error(bdu_handle h, double *eq, double *ep);
  * the drift measured before the step. */
 int bdu_reorthogonalize(bdu_handle h, double tol, double *eq, double *ep);
 
+/* ---- truncated bidiagonal approximation (Section 2) ------------------- */
+
+/* The best rank-r truncated bidiagonal approximation of the handle's
+ * A = Q Bd P^T (eqs. (trBD), (errtrBD)): keep the r columns i of Bd (0-based)
+ * with the largest t_i = d_i^2 + e_{i-1}^2 (e_{-1} = 0; each product and
+ * the sum rounded on their own; ties keep the lower index), in order of
+ * decreasing t.  idx (r, int64) receives those columns, err2 the exact
+ * squared Frobenius error (the dropped t_i summed in increasing i from 0),
+ * Qr (m x r) the columns d_i q_i + e_{i-1} q_{i-1} and Pr (n x r) the columns
+ * p_i, so that A_r = Qr Pr^T.  Any output may be NULL; host or device
+ * pointers.  1 <= r <= n.  Synchronizes the handle's stream. */
+int bdu_truncated_bd(bdu_handle h, int64_t r, int64_t *idx, double *err2, double *Qr, double *Pr);
+
 /* ---- subspace tracking (Section 4, eqs. (lrup)-(bdlrup)) ------------ */
 
 /* A thin rank-r factorization A = U B V^T (U m x r and V n x r with

@@ -71,6 +71,7 @@ def lib():
         L.bdu_orth_error.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.bdu_reorthogonalize.argtypes = [vp, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_double)]
+        L.bdu_truncated_bd.argtypes = [vp, i64, vp, ctypes.POINTER(ctypes.c_double), vp, vp]
         L.bdu_track_create.argtypes = [i64, i64, i64, vp, vp, vp, vp, ctypes.POINTER(vp)]
         L.bdu_track_update.argtypes = [vp, vp, vp]
         L.bdu_track_sync.argtypes = [vp]
@@ -283,6 +284,17 @@ class Handle:
 
     def sync(self) -> None:
         _check(lib().bdu_sync(self._h), "bdu_sync")
+
+    def truncated_bd(self, r: int):
+        """Best rank-r truncated bidiagonal approximation: (idx, err2, Qr, Pr)
+        with A_r = Qr Pr^T (eqs. (trBD), (errtrBD))."""
+        idx = np.empty(r, np.int64)
+        Qr = np.empty((self.m, r), order="F")
+        Pr = np.empty((self.n, r), order="F")
+        err2 = ctypes.c_double()
+        _check(lib().bdu_truncated_bd(self._h, r, idx.ctypes.data, ctypes.byref(err2), Qr.ctypes.data, Pr.ctypes.data),
+               "bdu_truncated_bd")
+        return idx, err2.value, Qr, Pr
 
     def orth_error(self):
         """(||Q^T Q - I||_F, ||P^T P - I||_F) measured on the device."""

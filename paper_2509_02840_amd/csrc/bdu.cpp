@@ -23,6 +23,7 @@
 #include "kernels.h"
 #include "plan.h"
 #include "orth.h"
+#include "trbd.h"
 #include "track.h"
 
 using namespace bdu;
@@ -1230,6 +1231,50 @@ int bdu_reorthogonalize(bdu_handle h, double tol, double *eq, double *ep)
 }
 
 }  // extern "C"
+
+// ---- truncated bidiagonal approximation (Section 2) -----------------------------
+
+extern "C" int bdu_truncated_bd(bdu_handle h, int64_t r, int64_t *idx, double *err2, double *Qr, double *Pr)
+{
+    if (!h || r < 1 || r > h->n || r > 65535) return BDU_EINVAL;
+    if (h->poisoned) return BDU_EDEVICE;
+    HIPCHK(h, wait_dep(h));
+    const int64_t m = h->m, n = h->n;
+    // per-call scratch, freed before returning
+    double *t = nullptr, *er = nullptr, *qr = nullptr, *pr = nullptr;
+    int64_t *rank = nullptr, *ix = nullptr;
+    hipError_t e = hipMalloc(&t, sizeof(double) * n);
+    if (e == hipSuccess) e = hipMalloc(&rank, sizeof(int64_t) * n);
+    if (e == hipSuccess) e = hipMalloc(&ix, sizeof(int64_t) * r);
+    if (e == hipSuccess) e = hipMalloc(&er, sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&qr, sizeof(double) * m * r);
+    if (e == hipSuccess) e = hipMalloc(&pr, sizeof(double) * n * r);
+    int st = BDU_OK;
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        st = e == hipErrorOutOfMemory ? BDU_ENOMEM : BDU_EDEVICE;
+    } else {
+        hipStream_t s = h->stream;
+        e = launch_trbd(h->hd.Q, h->hd.ldq, m, h->hd.P, h->hd.ldp, n, h->hd.d, h->hd.e, r, t, rank, ix, er, qr, pr,
+                        s);
+        if (e == hipSuccess && idx) e = copy_out(idx, ix, sizeof(int64_t) * r, s);
+        if (e == hipSuccess && err2) e = copy_out(err2, er, sizeof(double), s);
+        if (e == hipSuccess && Qr) e = copy_out(Qr, qr, sizeof(double) * m * r, s);
+        if (e == hipSuccess && Pr) e = copy_out(Pr, pr, sizeof(double) * n * r, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            h->poisoned = true;
+            st = BDU_EDEVICE;
+        }
+    }
+    (void)hipFree(t);
+    (void)hipFree(rank);
+    (void)hipFree(ix);
+    (void)hipFree(er);
+    (void)hipFree(qr);
+    (void)hipFree(pr);
+    return st;
+}
 
 // ---- subspace tracking (Section 4) ---------------------------------------------
 

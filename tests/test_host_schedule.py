@@ -271,3 +271,8 @@ def test_orthogonality_calls_reject_a_null_handle():
     L = bdu.lib()
     assert L.bdu_orth_error(None, None, None) == bdu.BDU_EINVAL
     assert L.bdu_reorthogonalize(None, 0.0, None, None) == bdu.BDU_EINVAL
+
+
+def test_truncated_bd_rejects_bad_ranks_without_a_device():
+    L = bdu.lib()
+    assert L.bdu_truncated_bd(None, 1, None, None, None, None) == bdu.BDU_EINVAL
