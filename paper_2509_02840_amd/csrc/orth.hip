@@ -17,9 +17,17 @@ typedef double mfma_acc __attribute__((ext_vector_type(4)));
 // E = X^T X - I on the blocks at or above the diagonal, each entry also
 // written to its mirror, so E is exactly symmetric.  grid (nb, nb), nb =
 // lde / 64; the contraction runs over the ld rows (padding rows are zero).
+// The MFMA operands run across columns of X, so 16-row x 64-column tiles of
+// X are loaded down the columns (16 consecutive doubles per 16 lanes) into
+// LDS, the next tile's loads in flight while the current one is multiplied.
+// A tile column is 34 doubles apart: a 32-lane half of an operand read
+// (columns c = 0..15, rows r and r+1) then meets 32 distinct bank pairs.
+constexpr int kGramRows = 16, kGramPad = 34;
+
 __global__ __launch_bounds__(64) void orth_gram_kernel(const double *X, int64_t ld, int64_t k, double *E,
                                                        int64_t lde)
 {
+    __shared__ double ta[64 * kGramPad], tb[64 * kGramPad];
     const int bi = blockIdx.x, bj = blockIdx.y;
     if (bj < bi) return;
     const int l = threadIdx.x, rr = l / 16, cc = l % 16;
@@ -29,19 +37,40 @@ __global__ __launch_bounds__(64) void orth_gram_kernel(const double *X, int64_t 
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = mfma_acc{0.0, 0.0, 0.0, 0.0};
-    for (int64_t r0 = 0; r0 < ld; r0 += 4) {
-        const int64_t r = r0 + rr;
-        double av[4], bv[4];
+    // load q of a tile: row cc, column 4 q + rr of the 64-column block
+    double pa[16], pb[16];
+    auto load = [&](int64_t r0) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int64_t ci = I0 + 16 * t + cc, cj = J0 + 16 * t + cc;
-            av[t] = ci < k ? X[r + ci * ld] : 0.0;
-            bv[t] = cj < k ? X[r + cj * ld] : 0.0;
+        for (int q = 0; q < 16; ++q) {
+            const int64_t ci = I0 + 4 * q + rr, cj = J0 + 4 * q + rr;
+            pa[q] = ci < k ? X[(r0 + cc) + ci * ld] : 0.0;
+            pb[q] = cj < k ? X[(r0 + cc) + cj * ld] : 0.0;
         }
+    };
+    load(0);
+    for (int64_t r0 = 0; r0 < ld; r0 += kGramRows) {
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int q = 0; q < 16; ++q) {
+            ta[(4 * q + rr) * kGramPad + cc] = pa[q];
+            tb[(4 * q + rr) * kGramPad + cc] = pb[q];
+        }
+        if (r0 + kGramRows < ld) load(r0 + kGramRows);
+        __syncthreads();
 #pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+        for (int s4 = 0; s4 < kGramRows / 4; ++s4) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                av[t] = ta[(16 * t + cc) * kGramPad + 4 * s4 + rr];
+                bv[t] = tb[(16 * t + cc) * kGramPad + 4 * s4 + rr];
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+        }
+        __syncthreads();
     }
 #pragma unroll
     for (int a = 0; a < 4; ++a)
@@ -128,7 +157,7 @@ __global__ __launch_bounds__(64) void orth_update_kernel(const double *X, int64_
 
 hipError_t launch_orth_gram(const double *X, int64_t ld, int64_t k, double *E, int64_t lde, hipStream_t st)
 {
-    if (ld % 128 || lde % 64 || lde < k || k < 1) return hipErrorInvalidValue;
+    if (ld % 128 || lde % 64 || lde < k || k < 1) return hipErrorInvalidValue;  // ld: whole 16-row tiles
     const unsigned nb = (unsigned)(lde / 64);
     hipLaunchKernelGGL(orth_gram_kernel, dim3(nb, nb), dim3(64), 0, st, X, ld, k, E, lde);
     return hipGetLastError();
