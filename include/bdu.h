@@ -161,6 +161,16 @@ int bdu_autotune(int64_t m, int64_t n, int streams, int64_t *out);
  * it. */
 int bdu_set_generation_in_lds(int allow);
 
+/* Split passes: with on = 1 (default), a handle whose schedule ends phase 1
+ * (Section 3.4: the upper-left chase, with the fold of the remaining rank-1
+ * term) at a tick where no rotation chain is in flight generates each pass
+ * in two launches and applies the phase-1 rotations to Q and P on a stream
+ * of its own while the phase-2 rotations are generated; the handle's stream
+ * waits for both.  Same rotations in the same order, so results do not
+ * depend on it.  Applies to handles created afterwards; batches never
+ * split. */
+int bdu_set_split_pass(int on);
+
 /* Input check: with on = 1, bdu_create, bdu_update, bdu_update_projected,
  * bdu_update_batched and bdu_batch_update scan their inputs (after copying
  * them to the device) and return BDU_ENONFINITE, changing no handle, if any
@@ -320,7 +330,9 @@ int bdu_track_destroy(bdu_track t);
 /* Statistics of the rotation schedule for (m, n) under the current tiling:
  * out[0] left rotations, out[1] right rotations, out[2] spike rotations,
  * out[3] generation chains, out[4] generation ticks, out[5] left stream
- * slots, out[6] right stream slots, out[7] generation threads. */
+ * slots, out[6] right stream slots, out[7] generation threads, out[8] the
+ * tick where a split pass ends its first part (0: passes do not split).
+ * out holds 9 values. */
 int bdu_plan_stats(int64_t m, int64_t n, int64_t *out);
 
 /* The schedule in order as the device decodes it: side, first index (1-based),

@@ -68,6 +68,7 @@ def lib():
         L.bdu_autotune.argtypes = [i64, i64, i32, ctypes.POINTER(i64)]
         L.bdu_set_generation_in_lds.argtypes = [i32]
         L.bdu_set_finite_check.argtypes = [i32]
+        L.bdu_set_split_pass.argtypes = [i32]
         L.bdu_orth_error.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.bdu_reorthogonalize.argtypes = [vp, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_double)]
@@ -103,7 +104,7 @@ def lib():
                   "bdu_get_tiling", "bdu_plan_stats", "bdu_givens_device", "bdu_timing_enable",
                   "bdu_timing_read", "bdu_batch_create", "bdu_batch_update", "bdu_batch_sync",
                   "bdu_batch_info", "bdu_batch_destroy", "bdu_autotune", "bdu_tune_save", "bdu_tune_load",
-                  "bdu_handle_tiling", "bdu_set_generation_in_lds", "bdu_set_finite_check", "bdu_server_create", "bdu_server_open", "bdu_server_submit",
+                  "bdu_handle_tiling", "bdu_set_generation_in_lds", "bdu_set_finite_check", "bdu_set_split_pass", "bdu_server_create", "bdu_server_open", "bdu_server_submit",
                   "bdu_server_wait", "bdu_server_poll", "bdu_server_drain", "bdu_server_pause",
                   "bdu_server_read", "bdu_server_close", "bdu_server_stats", "bdu_server_destroy"):
             getattr(L, f).restype = i32
@@ -155,6 +156,11 @@ def set_finite_check(on: bool) -> None:
 
 def set_generation_in_lds(allow: bool) -> None:
     _check(lib().bdu_set_generation_in_lds(1 if allow else 0), "bdu_set_generation_in_lds")
+
+
+def set_split_pass(on: bool) -> None:
+    """Apply phase 1 on a side stream while phase 2 is generated (handles created afterwards)."""
+    _check(lib().bdu_set_split_pass(1 if on else 0), "bdu_set_split_pass")
 
 
 def set_tiling_auto() -> None:
@@ -211,9 +217,9 @@ def timing_read() -> dict:
 
 
 def plan_stats(m: int, n: int) -> dict:
-    out = (ctypes.c_int64 * 8)()
+    out = (ctypes.c_int64 * 9)()
     _check(lib().bdu_plan_stats(m, n, out), "bdu_plan_stats")
-    keys = ["left", "right", "spike", "chains", "ticks", "left_slots", "right_slots", "gen_threads"]
+    keys = ["left", "right", "spike", "chains", "ticks", "left_slots", "right_slots", "gen_threads", "split"]
     return dict(zip(keys, list(out)))
 
 

@@ -40,6 +40,7 @@ struct Tuned {
 std::map<std::pair<int64_t, int64_t>, Tuned> g_tuned;
 bool g_gen_lds = true;  // generation keeps its band in LDS when it fits
 bool g_check_finite = false;  // reject NaN / Inf inputs (one extra pass and a sync per call)
+bool g_split = true;          // single-handle passes apply phase 1 while phase 2 is generated
 
 struct PlanEntry {
     std::unique_ptr<Plan> plan;
@@ -161,6 +162,11 @@ struct bdu_ctx {
     int *flag = nullptr;       // device flag of the non-finite input check
     hipEvent_t ev = nullptr;   // marks this handle's own stream work for a batch to wait on
     hipEvent_t dep = nullptr;  // completion of the last batch step this handle was in
+    // split pass: phase 1 is applied on `side` while phase 2 is generated on
+    // `stream`; sp1/sp2 mark the ends of the two generation parts, sp3 the
+    // end of the application
+    hipStream_t side = nullptr;
+    hipEvent_t sp1 = nullptr, sp2 = nullptr, sp3 = nullptr;
     // orthogonality monitor scratch (allocated on first use)
     double *orthE = nullptr, *orthY = nullptr, *orthPart = nullptr, *orthOut = nullptr;
     std::vector<void *> allocs;
@@ -308,13 +314,37 @@ int panels_of(const bdu_ctx *h)
 int pass_single(bdu_ctx *h, int pass, bool project)
 {
     hipError_t e = hipSuccess;
+    hipStream_t st = h->stream;
     if (project)
-        e = timed(ST_PROJECT, h->stream,
-                  [&] { return launch_project(h->d_self, 1, tiles_of(h), Gate{nullptr, pass}, h->stream); });
-    if (e == hipSuccess)
-        e = run_rotation_stages(h->d_self, 1, h->m > h->n, gen_lds_bytes(h->n, h->plan->N), h->lds_gen,
-                                h->plan->L, panels_of(h), h->plan->K0, h->plan->NW, h->rpl, Gate{nullptr, pass},
-                                h->stream);
+        e = timed(ST_PROJECT, st, [&] { return launch_project(h->d_self, 1, tiles_of(h), Gate{nullptr, pass}, st); });
+    const int64_t lds = gen_lds_bytes(h->n, h->plan->N);
+    const int L = h->plan->L, np = panels_of(h), k0 = h->plan->K0, nw = h->plan->NW;
+    if (e == hipSuccess && h->side) {
+        // Phase 1 ends with no chain in flight: generate it, then apply it on
+        // the side stream while phase 2 is generated.
+        //   stream: [spike] gen 1 -> sp1 -> gen 2 -> sp2 -> wait sp3
+        //   side:   wait sp1 -> apply 1 -> wait sp2 -> apply 2 -> sp3
+        const Gate g1{nullptr, pass, 1}, g2{nullptr, pass, 2};
+        hipStream_t sd = h->side;
+        if (h->m > h->n) e = timed(ST_SPIKE, st, [&] { return launch_spike(h->d_self, 1, g1, st); });
+        if (e == hipSuccess)
+            e = timed(ST_GEN, st, [&] { return launch_gen(h->d_self, 1, lds, h->lds_gen, L, g1, st); });
+        if (e == hipSuccess) e = hipEventRecord(h->sp1, st);
+        if (e == hipSuccess)
+            e = timed(ST_GEN, st, [&] { return launch_gen(h->d_self, 1, lds, h->lds_gen, L, g2, st); });
+        if (e == hipSuccess) e = hipEventRecord(h->sp2, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(sd, h->sp1, 0);
+        if (e == hipSuccess)
+            e = timed(ST_APPLY, sd, [&] { return launch_apply(h->d_self, 1, np, k0, nw, h->rpl, g1, sd); });
+        if (e == hipSuccess) e = hipStreamWaitEvent(sd, h->sp2, 0);
+        if (e == hipSuccess)
+            e = timed(ST_APPLY, sd, [&] { return launch_apply(h->d_self, 1, np, k0, nw, h->rpl, g2, sd); });
+        if (e == hipSuccess) e = hipEventRecord(h->sp3, sd);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, h->sp3, 0);
+    } else if (e == hipSuccess) {
+        e = run_rotation_stages(h->d_self, 1, h->m > h->n, lds, h->lds_gen, L, np, k0, nw, h->rpl,
+                                Gate{nullptr, pass}, st);
+    }
     if (e != hipSuccess) {
         h->poisoned = true;
         return BDU_EDEVICE;
@@ -336,6 +366,23 @@ int64_t slot_of(const Plan &P, const GenChain &g, const Rot &r)
 }  // namespace
 
 namespace {
+
+bool split_on()
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g_split;
+}
+
+void release_streams(bdu_ctx *h)
+{
+    if (h->ev) (void)hipEventDestroy(h->ev);
+    if (h->sp1) (void)hipEventDestroy(h->sp1);
+    if (h->sp2) (void)hipEventDestroy(h->sp2);
+    if (h->sp3) (void)hipEventDestroy(h->sp3);
+    if (h->side) (void)hipStreamDestroy(h->side);
+    h->ev = h->sp1 = h->sp2 = h->sp3 = nullptr;
+    h->side = nullptr;
+}
 
 bool gen_lds_fits(int64_t n, int64_t N)
 {
@@ -546,7 +593,7 @@ int64_t bdu_footprint_bytes(int64_t m, int64_t n)
     const int64_t ldq = (m + 127) / 128 * 128, ldp = (n + 127) / 128 * 128;
     int64_t bytes = 8 * (ldq * m + ldp * n + 2 * n + 2 * (m + n) + 2 * (m + n));
     bytes += 16 * (p->slots[0] + p->slots[1] + 2 * (4 * (int64_t)p->K + 64) + std::max<int64_t>(p->nspike, 1));
-    if (!gen_lds_fits(n, N)) bytes += gen_lds_bytes(n, N);
+    bytes += gen_lds_bytes(n, N);  // band (device memory or the image between split parts)
     return bytes;
 }
 
@@ -573,6 +620,14 @@ int bdu_set_generation_in_lds(int allow)
     if (allow != 0 && allow != 1) return BDU_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
     g_gen_lds = allow != 0;
+    return BDU_OK;
+}
+
+int bdu_set_split_pass(int on)
+{
+    if (on != 0 && on != 1) return BDU_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_split = on != 0;
     return BDU_OK;
 }
 
@@ -619,7 +674,9 @@ int create_impl(int64_t m, int64_t n, const double *Q, const double *d, const do
     A(dalloc(h.get(), &hd.csL, plan->slots[0] + slack));
     A(dalloc(h.get(), &hd.csR, plan->slots[1] + slack));
     A(dalloc(h.get(), &hd.csSp, plan->nspike));
-    if (!h->lds_gen) A(dalloc(h.get(), &hd.band, gen_lds_bytes(n, plan->N) / 8));
+    // the band in device memory (large n), or the image of the LDS band
+    // kept between the two parts of a split generation
+    A(dalloc(h.get(), &hd.band, gen_lds_bytes(n, plan->N) / 8));
     A(dalloc(h.get(), &h->d_hd, 1));
     A(dalloc(h.get(), &h->d_self, 1));
     A(dalloc(h.get(), &h->flag, 1));
@@ -633,6 +690,7 @@ int create_impl(int64_t m, int64_t n, const double *Q, const double *d, const do
     hd.blkL = plan->d_blocks[0];
     hd.blkR = plan->d_blocks[1];
     hd.ticks = plan->ticks;
+    hd.split = plan->split;
     hd.m = (int32_t)m;
     hd.n = (int32_t)n;
     hd.ldq = (int32_t)ldq;
@@ -666,7 +724,15 @@ int create_impl(int64_t m, int64_t n, const double *Q, const double *d, const do
     HandleDev *self = h->d_hd;
     HIPCHK(hp, hipMemcpyAsync(h->d_self, &self, sizeof(self), hipMemcpyHostToDevice, hp->stream));
     HIPCHK(hp, hipStreamSynchronize(hp->stream));
-    if (hipEventCreateWithFlags(&hp->ev, hipEventDisableTiming) != hipSuccess) {
+    bool ok = hipEventCreateWithFlags(&hp->ev, hipEventDisableTiming) == hipSuccess;
+    if (ok && plan->split > 0 && split_on()) {
+        ok = hipStreamCreateWithFlags(&hp->side, hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&hp->sp1, hipEventDisableTiming) == hipSuccess &&
+             hipEventCreateWithFlags(&hp->sp2, hipEventDisableTiming) == hipSuccess &&
+             hipEventCreateWithFlags(&hp->sp3, hipEventDisableTiming) == hipSuccess;
+    }
+    if (!ok) {
+        release_streams(hp);
         for (void *p : h->allocs) (void)hipFree(p);
         return BDU_EDEVICE;
     }
@@ -792,8 +858,9 @@ int bdu_destroy(bdu_handle h)
     if (!h) return BDU_EINVAL;
     (void)wait_dep(h);
     (void)hipStreamSynchronize(h->stream);
+    if (h->side) (void)hipStreamSynchronize(h->side);
     for (void *p : h->allocs) (void)hipFree(p);
-    if (h->ev) (void)hipEventDestroy(h->ev);
+    release_streams(h);
     delete h;
     return BDU_OK;
 }
@@ -1125,6 +1192,7 @@ int bdu_plan_stats(int64_t m, int64_t n, int64_t *out)
     out[5] = p->slots[0];
     out[6] = p->slots[1];
     out[7] = p->L;
+    out[8] = p->split;
     return BDU_OK;
 }
 

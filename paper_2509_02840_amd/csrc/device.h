@@ -24,14 +24,18 @@ struct HandleDev {
     int32_t m, n, N, nchains, nb1, nb2;
     int32_t ldq, ldp;
     int32_t K0, NW, K, S;
+    int64_t split;          // generation split tick (Plan::split)
 };
 
 // Per-launch gate of a batch in which streams take different ranks: the
 // handle at position i of a launch takes part in pass `pass` only if
 // pass < ranks[i] (ranks == nullptr: every handle takes part).
+// part: 0 the whole pass; 1 generation up to the end of phase 1 (with the
+// fold) and application of the spike and the phase-1 blocks; 2 the rest.
 struct Gate {
     const int32_t *ranks;
     int32_t pass;
+    int32_t part;
 };
 
 constexpr int kGenThreads = 1024;  // at n = 2048, 256 threads leave chains waiting for a free thread

@@ -166,15 +166,27 @@ __global__ __launch_bounds__(kGenThreads) void gen_kernel(HandleDev *const *hs, 
     const int tid = threadIdx.x;
     const int nt = blockDim.x;
     const int total = VO + (n + 8);
-    for (int k = tid; k < total; k += nt) S[k] = 0.0;
-    __syncthreads();
-    for (int i = 1 + tid; i <= n; i += nt) {
-        S[band_cell(i, i)] = h->d[i - 1];
-        if (i < n) S[band_cell(i, i + 1)] = h->e[i - 1];
-        S[VO + i + 3] = h->v[i - 1];
+    // part 2 continues from the band part 1 left (in device memory, or the
+    // image of the LDS band part 1 saved there); otherwise start from d, e,
+    // u and v
+    const int part = gate.part;
+    const int t_begin = part == 2 ? (int)h->split : 0;
+    const int t_end = part == 1 ? (int)h->split : (int)h->ticks;
+    if (part == 2) {
+        if (IN_LDS)
+            for (int k = tid; k < total; k += nt) S[k] = h->band[k];
+        __syncthreads();
+    } else {
+        for (int k = tid; k < total; k += nt) S[k] = 0.0;
+        __syncthreads();
+        for (int i = 1 + tid; i <= n; i += nt) {
+            S[band_cell(i, i)] = h->d[i - 1];
+            if (i < n) S[band_cell(i, i + 1)] = h->e[i - 1];
+            S[VO + i + 3] = h->v[i - 1];
+        }
+        for (int i = 1 + tid; i <= N; i += nt) S[UO + i + 3] = h->u[i - 1];
+        __syncthreads();
     }
-    for (int i = 1 + tid; i <= N; i += nt) S[UO + i + 3] = h->u[i - 1];
-    __syncthreads();
 
     const int K = h->K;
     const int nch = h->nchains;
@@ -188,11 +200,20 @@ __global__ __launch_bounds__(kGenThreads) void gen_kernel(HandleDev *const *hs, 
     ChainReg g = {0, 0, 0, 0, 0, 0}, gn = {0, 0, 0, 0, 0, 0};
     bool next = false;
     if (ci < nch) g = load_chain(h->chains, ci);
+    settle(g);
+    // part 2: skip the chains that finished before it (none is in flight at
+    // the split)
+    while (ci < nch && g.tau0 + g.len <= t_begin) {
+        ci += nt;
+        if (ci < nch) {
+            g = load_chain(h->chains, ci);
+            settle(g);
+        }
+    }
     if (ci + nt < nch) {
         gn = load_chain(h->chains, ci + nt);
         next = true;
     }
-    settle(g);
     settle(gn);
 
     RotAddr<BP> ae, ao;
@@ -316,14 +337,22 @@ __global__ __launch_bounds__(kGenThreads) void gen_kernel(HandleDev *const *hs, 
         __syncthreads();
     };
 
-    const int ticks = (int)h->ticks;
-    int t = 0;
-    for (; t + 1 < ticks; t += 2) {
+    int t = t_begin;
+    if (t < t_end && (t & 1)) {
+        tick(ao, t);
+        ++t;
+    }
+    for (; t + 1 < t_end; t += 2) {
         tick(ae, t);
         tick(ao, t + 1);
     }
-    if (t < ticks) tick(ae, t);
+    if (t < t_end) tick(ae, t);
 
+    if (part == 1) {
+        if (IN_LDS)
+            for (int k = tid; k < total; k += nt) h->band[k] = S[k];
+        return;
+    }
     for (int i = 1 + tid; i <= n; i += nt) {
         h->d[i - 1] = S[band_cell(i, i)];
         if (i < n) h->e[i - 1] = S[band_cell(i, i + 1)];

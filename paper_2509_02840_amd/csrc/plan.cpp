@@ -116,6 +116,20 @@ std::unique_ptr<Plan> build_plan(int64_t m, int64_t n, int K0, int NW, int gen_t
         tend = std::max(tend, tau0 + g.len);
     }
     P->ticks = tend;
+    // Phase 1 (with the fold) ends at the tick its last chain finishes; the
+    // pass can be generated in two parts split there when no chain is in
+    // flight at that tick and no phase-2 chain starts before it (then the
+    // second part needs only the band, and phase 1 can be applied while
+    // phase 2 is generated).
+    int64_t p1end = 0;
+    for (const GenChain &g : ch)
+        if (g.type <= CH_P1B || g.type == CH_FOLD) p1end = std::max<int64_t>(p1end, g.tau0 + g.len);
+    bool clean = p1end > 0 && p1end < tend;
+    for (const GenChain &g : ch) {
+        if (g.tau0 < p1end && g.tau0 + g.len > p1end) clean = false;
+        if (g.type >= CH_P2A && g.tau0 < p1end) clean = false;
+    }
+    P->split = clean ? p1end : 0;
 
     // ---- applier blocks -------------------------------------------------
     const int K = P->K, S = P->S;

@@ -15,6 +15,7 @@ struct Plan {
     int L = 0;                      // generation threads
     std::vector<GenChain> chains;   // non-empty chains in schedule order (with the fold)
     int64_t ticks = 0;              // generation ticks
+    int64_t split = 0;              // tick where phase 1 ends with nothing in flight (0: no split)
     int64_t nleft = 0, nright = 0;  // rotations of phases 1 and 2 per side
     int64_t nspike = 0;             // spike rotations (m > n)
     std::vector<BlockDesc> blocks[2];  // per side: phase-1 blocks, then phase-2 blocks

@@ -66,3 +66,25 @@ def test_large_n_sampled_rows(bdu, oracle, m, n):
     _eq("e", e1, e)
     _eq("Q rows", Q1[qr], Qr)
     _eq("P rows", P1[pr], Pr)
+
+
+@pytest.mark.parametrize("in_lds", [True, False])
+@pytest.mark.parametrize("m,n,r", [(2, 2, 1), (14, 12, 2), (65, 64, 1), (257, 191, 2)])
+def test_unsplit_pass_bit_exact(bdu, oracle, m, n, r, in_lds):
+    """Passes generated in one launch and applied after it (split passes
+    off) give the oracle's result too; the other tests run split passes."""
+    f = W.factorization(m, n, 610 + m)
+    (B, C), = W.gaussian_updates(m, n, 1, 611 + n, r=r)
+    bdu.set_split_pass(False)
+    bdu.set_generation_in_lds(in_lds)
+    try:
+        h = bdu.Handle(f.Q, f.d, f.e, f.P)
+    finally:
+        bdu.set_split_pass(True)
+        bdu.set_generation_in_lds(True)
+    h.update(B, C)
+    ref = oracle.State(f.Q, f.d, f.e, f.P)
+    oracle.bgu_update(ref, B, C)
+    for nm, x, y in zip("QdeP", h.read(), (ref.Q, ref.d, ref.e, ref.P)):
+        _eq(nm, x, y)
+    h.close()

@@ -276,3 +276,23 @@ def test_orthogonality_calls_reject_a_null_handle():
 def test_truncated_bd_rejects_bad_ranks_without_a_device():
     L = bdu.lib()
     assert L.bdu_truncated_bd(None, 1, None, None, None, None) == bdu.BDU_EINVAL
+
+
+@pytest.mark.parametrize("m,n", [(2, 2), (3, 2), (8, 6), (17, 13), (65, 65), (300, 257), (2048, 2048), (4096, 2048)])
+def test_split_tick_separates_the_phases(m, n):
+    """A split pass generates ticks [0, split) and then [split, ticks): every
+    rotation of phase 1 and the fold (Section 3.4) must lie in the first part
+    and every phase-2 rotation in the second, so that the first part's
+    rotations can be applied while the second part is generated."""
+    side, idx, ph, tick = bdu.plan_rotations(m, n)
+    split = bdu.plan_stats(m, n)["split"]
+    assert 0 < split < bdu.plan_stats(m, n)["ticks"]
+    first = (ph == 1) | (ph == 3)
+    assert np.all(tick[first] < split)
+    assert np.all(tick[ph == 2] >= split)
+    assert tick[first].max() == split - 1
+
+
+def test_split_switch_validates_its_argument():
+    assert bdu.lib().bdu_set_split_pass(2) == bdu.BDU_EINVAL
+    assert bdu.lib().bdu_set_split_pass(1) == bdu.BDU_OK
