@@ -2,7 +2,9 @@
 
 The oracle (``bgu_oracle.c``) is a plain, slow reference of the Givens
 bidiagonal update of Brust & Saunders (Section 3.4, Algorithm 2) plus the
-dense factorizations that check it (Section 2).  Only the test suite, the
+dense factorizations that check it (Section 2); the Householder bidiagonal
+update (Section 3.3, Algorithm 1) and the other read-side utilities are
+plain numpy in this module.  Only the test suite, the
 smoke check and the benchmark's CPU-baseline leg may import this module.
 It shares no code with the GPU library.
 """
@@ -323,3 +325,144 @@ def truncated_bd(Q, d, e, P, r: int):
         Qr[:, j] = d[i] * Q[:, i] if i == 0 else d[i] * Q[:, i] + e[i - 1] * Q[:, i - 1]
         Pr[:, j] = P[:, i]
     return idx.astype(np.int64), err2, Qr, Pr
+
+
+# ---- Householder bidiagonal update, BHU (Section 3.3, Theorem 1, Algorithm 1) --
+#
+# Readings taken here (the paper leaves them open):
+# - house(x) for a column x(k:m) or a row x(k+1:n): when the entries to be
+#   annihilated are already all zero the reflector is the identity (its
+#   essential vector is zero and the leading entry is kept); otherwise
+#   alpha = -sign(x_1) ||x|| (sign(0) = +1) and y = (x - alpha e_1) / ||x - alpha e_1||,
+#   so H = I - 2 y y^T with ||y|| = 1 as the compact forms (eq. QP) assume.
+# - Left reflectors k = 1..n-1 when m = n and k = 1..n when m > n (column n
+#   has entries below the diagonal only when m > n); right reflectors
+#   w_{k+1} for k = 1..n-2, each zeroing row k right of entry k+1.
+# - The row reflector of step k is computed from row k of A_{k,k-1} (the
+#   printed e_{k+1} index is read as the row that holds the entries
+#   w_{k+1} annihilates).
+# - The last bidiagonal entries not produced as a reflector's leading value
+#   (e_{n-1}, and d_n when m = n) are read from column n of the final
+#   representation.
+
+def _bd_mul(d, e, x, m):
+    """B x for the m x n upper bidiagonal B (diagonal d, superdiagonal e)."""
+    n = len(d)
+    y = np.zeros(m)
+    y[:n] = d * x
+    y[: n - 1] += e * x[1:]
+    return y
+
+
+def _bd_tmul(d, e, y):
+    """B^T y (y of length m)."""
+    n = len(d)
+    x = d * y[:n]
+    x[1:] += e * y[: n - 1]
+    return x
+
+
+def _house(x):
+    """(alpha, y) for x: y unit with (I - 2 y y^T) x = alpha e_1, or y = 0 and
+    alpha = x_1 when x(2:) is already zero."""
+    x = np.asarray(x, dtype=np.float64)
+    if not np.any(x[1:] != 0.0):
+        return float(x[0]), np.zeros_like(x)
+    nrm = float(np.sqrt(np.sum(x * x)))
+    alpha = -nrm if x[0] >= 0.0 else nrm
+    y = x.copy()
+    y[0] -= alpha
+    return alpha, y / float(np.sqrt(np.sum(y * y)))
+
+
+def bhu_repr(d, e, b, c, Y, W):
+    """The factors (U, M, V) of Theorem 1 for A = B + b c^T after the left
+    reflectors in the columns of Y (m x i) and the right ones in W (n x j):
+    Q_i^T A P_j = B - U M^{-1} V^T with U = [b, Y, B W], V = [c, B^T Y, W]
+    and M = [[-1, 0, c^T W], [Y^T b, T^T / 2, Y^T B W], [0, 0, R / 2]],
+    T and R the unit upper triangular matrices of eq. (TR)."""
+    m, i = Y.shape
+    n, j = W.shape
+    BW = np.column_stack([_bd_mul(d, e, W[:, q], m) for q in range(j)]) if j else np.zeros((m, 0))
+    BtY = np.column_stack([_bd_tmul(d, e, Y[:, q]) for q in range(i)]) if i else np.zeros((n, 0))
+    T = np.eye(i) + np.triu(2.0 * (Y.T @ Y), 1)
+    R = np.eye(j) + np.triu(2.0 * (W.T @ W), 1)
+    M = np.zeros((1 + i + j, 1 + i + j))
+    M[0, 0] = -1.0
+    M[0, 1 + i:] = c @ W
+    M[1:1 + i, 0] = Y.T @ b
+    M[1:1 + i, 1:1 + i] = 0.5 * T.T
+    M[1:1 + i, 1 + i:] = Y.T @ BW
+    M[1 + i:, 1 + i:] = 0.5 * R
+    U = np.column_stack([b, Y, BW])
+    V = np.column_stack([c, BtY, W])
+    return U, M, V
+
+
+def bhu_bidiag(d, e, b, c, m: int):
+    """Algorithm 1 on B + b c^T (B the m x n upper bidiagonal (d, e); b of
+    length m, c of length n).  Each step takes column k (then row k) of the
+    current A_{kk} from the representation of Theorem 1, never forming A.
+    Returns (d+, e+, Y, W): the new bidiagonal and the unit essential vectors
+    (Y m x n_left, W n x n_right) so that B + b c^T = Q_k Bd+ P_k^T with
+    Q_k = I - 2 Y T^{-1} Y^T and P_k = I - 2 W R^{-1} W^T (eq. QP)."""
+    d = np.asarray(d, dtype=np.float64)
+    e = np.asarray(e, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64).ravel()
+    c = np.asarray(c, dtype=np.float64).ravel()
+    n = len(d)
+    kl = n - 1 if m == n else n
+    kr = n - 2
+    Y = np.zeros((m, 0))
+    W = np.zeros((n, 0))
+    dp = np.zeros(n)
+    ep = np.zeros(n - 1)
+
+    def column(k):  # column k (0-based) of the current A
+        U, M, V = bhu_repr(d, e, b, c, Y, W)
+        ek = np.zeros(n)
+        ek[k] = 1.0
+        return _bd_mul(d, e, ek, m) - U @ np.linalg.solve(M, V[k, :])
+
+    def row(k):  # row k (0-based) of the current A
+        U, M, V = bhu_repr(d, e, b, c, Y, W)
+        ek = np.zeros(m)
+        ek[k] = 1.0
+        return _bd_tmul(d, e, ek) - V @ np.linalg.solve(M.T, U[k, :])
+
+    for k in range(kl):
+        a = column(k)
+        alpha, y = _house(a[k:])
+        dp[k] = alpha
+        yk = np.zeros(m)
+        yk[k:] = y
+        Y = np.column_stack([Y, yk])
+        if k >= kr:
+            continue
+        ar = row(k)
+        beta, w = _house(ar[k + 1:])
+        ep[k] = beta
+        wk = np.zeros(n)
+        wk[k + 1:] = w
+        W = np.column_stack([W, wk])
+    last = column(n - 1)
+    ep[n - 2] = last[n - 2]
+    if m == n:
+        dp[n - 1] = last[n - 1]
+    return dp, ep, Y, W
+
+
+def bhu_update(Q, d, e, P, b, c):
+    """Rank-1 update of A = Q Bd P^T by Algorithm 1: returns (Q+, d+, e+, P+)
+    with Q+ Bd+ P+^T = A + b c^T, Q+ = Q Q_k and P+ = P P_k (eq. QP)."""
+    Q = np.asarray(Q, dtype=np.float64)
+    P = np.asarray(P, dtype=np.float64)
+    m, n = Q.shape[0], P.shape[0]
+    bb = Q.T @ np.asarray(b, dtype=np.float64).ravel()
+    cc = P.T @ np.asarray(c, dtype=np.float64).ravel()
+    dp, ep, Y, W = bhu_bidiag(d, e, bb, cc, m)
+    T = np.eye(Y.shape[1]) + np.triu(2.0 * (Y.T @ Y), 1)
+    R = np.eye(W.shape[1]) + np.triu(2.0 * (W.T @ W), 1)
+    Qk = np.eye(m) - 2.0 * Y @ np.linalg.solve(T, Y.T)
+    Pk = np.eye(n) - 2.0 * W @ np.linalg.solve(R, W.T) if W.shape[1] else np.eye(n)
+    return Q @ Qk, dp, ep, P @ Pk
