@@ -389,6 +389,88 @@ def orth(torch, bdu, args) -> int:
     return 0
 
 
+def bhu_stream_bytes(m: int, n: int) -> float:
+    """Algorithmic bytes the Householder update streams at m x n: per step k
+    (0-based) the column reads Rv (j x j triangle), W (n x j), Y (m x i)
+    twice and S (i x i triangle); the reflector bookkeeping reads Y (m x k)
+    and S (k x k triangle); the row (k < n - 2) reads S (triangle), Y, W
+    twice and Rv (triangle), W and Rv again, with i = k, j = min(k, n - 2).
+    Vectors are counted too (a few per product)."""
+    kl = n - 1 if m == n else n
+    kr = n - 2
+    tri = lambda k: k * (k + 1) / 2
+    tot = 0.0
+    for k in range(kl + 1):  # the last pass is the final column
+        i, j = min(k, kl), min(k, kr)
+        tot += tri(j) + n * j + 2 * m * i + tri(i) + 4 * (m + n)
+        if k == kl:
+            break
+        tot += m * k + tri(k) + 2 * m
+        if k < kr:
+            tot += tri(k + 1) + m * (k + 1) + 2 * n * j + tri(j) + n * k + tri(k) + 4 * (m + n)
+    return 8.0 * tot
+
+
+def bhu(torch, bdu, args) -> int:
+    """Householder bidiagonal update (Algorithm 1) of one stream at
+    m = n = args.n, each update waited for, beside the Givens update of the
+    same stream; the oracle's Householder update at n = 256 as the CPU
+    baseline (its dense solves make larger sizes take minutes)."""
+    n = args.n
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(args.seed)
+    out = {}
+    for size in (n, 256):
+        Q, d, e, P = random_stream(torch, gen, size)
+        hh = bdu.Handle(Q, d, e, P)
+        hg = bdu.Handle(Q, d, e, P)
+        del Q, P
+        k = args.bhu_steps
+        bs, cs = make_updates(torch, gen, size, k + 1)
+        hh.update_householder(bs[0], cs[0])
+        hh.sync()
+        lat = []
+        for t in range(1, k + 1):
+            ta = time.perf_counter()
+            hh.update_householder(bs[t], cs[t])
+            hh.sync()
+            lat.append(time.perf_counter() - ta)
+        glat = []
+        for t in range(1, k + 1):
+            ta = time.perf_counter()
+            hg.update(bs[t], cs[t])
+            hg.sync()
+            glat.append(time.perf_counter() - ta)
+        hh.close()
+        hg.close()
+        out[size] = (float(np.median(lat)), float(np.median(glat)))
+    t_bhu, t_bgu = out[n]
+    byts = bhu_stream_bytes(n, n)
+    line = {
+        "metric": "FP64 Householder (BHU) rank-1 updates/sec, one stream",
+        "value": 1.0 / t_bhu, "unit": "updates/s", "n": n, "ms_per_update": 1e3 * t_bhu,
+        "givens_ms_per_update": 1e3 * t_bgu, "n256_ms_per_update": 1e3 * out[256][0],
+        "roofline": {"bound": "hbm", "achieved": byts / t_bhu / 1e9, "peak": 8000.0, "unit": "GB/s",
+                     "frac": byts / t_bhu / 1e9 / 8000.0, "traffic": None,
+                     "kernel": "whole update (reflector products)", "bytes_per_update": byts},
+        "dtype": "f64", "data": "synthetic", "config": {"workload": f"one stream, m = n = {n}, BHU rank-1 updates"},
+    }
+    if not args.no_cpu_baseline:
+        sys.path.insert(0, ROOT)
+        from oracle import oracle as O
+        from paper_2509_02840_amd import workloads as W
+        f = W.factorization(256, 256, args.seed)
+        rng = np.random.default_rng(args.seed)
+        b, c = rng.standard_normal(256), rng.standard_normal(256)
+        t0 = time.perf_counter()
+        O.bhu_update(f.Q, f.d, f.e, f.P, b, c)
+        tc = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": 1.0 / tc, "unit": "updates/s", "cores": 1, "kind": "oracle",
+                                "sample": "one oracle Householder update at m = n = 256 (compare n256_ms_per_update)"}
+    print(json.dumps(line))
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -417,6 +499,9 @@ def main() -> int:
     ap.add_argument("--orth", action="store_true",
                     help="time the orthogonality monitor and correction at m = n = --n")
     ap.add_argument("--orth-steps", type=int, default=10)
+    ap.add_argument("--bhu", action="store_true",
+                    help="instead: the Householder update (Algorithm 1) beside the Givens one (prints its own JSON line)")
+    ap.add_argument("--bhu-steps", type=int, default=4)
     ap.add_argument("--track", action="store_true",
                     help="subspace tracking (Section 4) instead of the full-factorization benchmark")
     ap.add_argument("--track-m", type=int, default=10000)
@@ -443,6 +528,8 @@ def main() -> int:
         return track(torch, bdu, args)
     if args.orth:
         return orth(torch, bdu, args)
+    if args.bhu:
+        return bhu(torch, bdu, args)
     if args.hetero:
         return hetero(torch, bdu, args)
     if args.serve > 0:

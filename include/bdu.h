@@ -277,6 +277,26 @@ int bdu_reorthogonalize(bdu_handle h, double tol, double *eq, double *ep);
  * pointers.  1 <= r <= n.  Synchronizes the handle's stream. */
 int bdu_truncated_bd(bdu_handle h, int64_t r, int64_t *idx, double *err2, double *Qr, double *Pr);
 
+/* ---- Householder bidiagonal update (Section 3.3) ---------------------- */
+
+/* The paper's second update method, BHU (Algorithm 1 on the compact
+ * representation of Theorem 1, with eqs. (house), (TR), (QP)): replaces the
+ * handle's A = Q Bd P^T by Q+ Bd+ P+^T = A + b c^T, where Bd+ is the
+ * Householder bidiagonalization of Bd + (Q^T b)(P^T c)^T computed without
+ * forming that matrix, Q+ = Q Q_k and P+ = P P_k.  b: m doubles, c: n
+ * doubles, host or device.  Reflectors H = I - 2 y y^T with unit y and
+ * leading value -sign(x_1) ||x|| (sign(0) = +1); the identity where the
+ * entries to annihilate are already zero; left reflectors on columns 1..n-1
+ * (m = n) or 1..n (m > n), right ones on rows 1..n-2 (so the first column of
+ * P is kept).  Not bit-identical to a CPU run: products are summed in a
+ * different order, and agreement is within a tolerance.  Device scratch of
+ * (3 ldq + 3 ldp) n + 10 ldq + 2 ldp + 64 doubles (ldq, ldp = m, n rounded
+ * up to 128) is allocated on the first call and kept by the handle
+ * (BDU_ENOMEM if it does not fit).  Errors: BDU_EINVAL (null argument),
+ * BDU_ENONFINITE (with the input check on), BDU_EDEVICE.  Stream-ordered on
+ * the handle's stream. */
+int bdu_update_householder(bdu_handle h, const double *b, const double *c);
+
 /* ---- subspace tracking (Section 4, eqs. (lrup)-(bdlrup)) ------------ */
 
 /* A thin rank-r factorization A = U B V^T (U m x r and V n x r with

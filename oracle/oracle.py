@@ -383,8 +383,11 @@ def bhu_repr(d, e, b, c, Y, W):
     T and R the unit upper triangular matrices of eq. (TR)."""
     m, i = Y.shape
     n, j = W.shape
-    BW = np.column_stack([_bd_mul(d, e, W[:, q], m) for q in range(j)]) if j else np.zeros((m, 0))
-    BtY = np.column_stack([_bd_tmul(d, e, Y[:, q]) for q in range(i)]) if i else np.zeros((n, 0))
+    BW = np.zeros((m, j))  # B W
+    BW[:n] = d[:, None] * W
+    BW[:n - 1] += e[:, None] * W[1:]
+    BtY = d[:, None] * Y[:n]  # B^T Y
+    BtY[1:] += e[:, None] * Y[:n - 1]
     T = np.eye(i) + np.triu(2.0 * (Y.T @ Y), 1)
     R = np.eye(j) + np.triu(2.0 * (W.T @ W), 1)
     M = np.zeros((1 + i + j, 1 + i + j))

@@ -69,6 +69,7 @@ def lib():
         L.bdu_set_generation_in_lds.argtypes = [i32]
         L.bdu_set_finite_check.argtypes = [i32]
         L.bdu_set_split_pass.argtypes = [i32]
+        L.bdu_update_householder.argtypes = [vp, vp, vp]
         L.bdu_orth_error.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.bdu_reorthogonalize.argtypes = [vp, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_double)]
@@ -104,7 +105,7 @@ def lib():
                   "bdu_get_tiling", "bdu_plan_stats", "bdu_givens_device", "bdu_timing_enable",
                   "bdu_timing_read", "bdu_batch_create", "bdu_batch_update", "bdu_batch_sync",
                   "bdu_batch_info", "bdu_batch_destroy", "bdu_autotune", "bdu_tune_save", "bdu_tune_load",
-                  "bdu_handle_tiling", "bdu_set_generation_in_lds", "bdu_set_finite_check", "bdu_set_split_pass", "bdu_server_create", "bdu_server_open", "bdu_server_submit",
+                  "bdu_handle_tiling", "bdu_set_generation_in_lds", "bdu_set_finite_check", "bdu_set_split_pass", "bdu_update_householder", "bdu_server_create", "bdu_server_open", "bdu_server_submit",
                   "bdu_server_wait", "bdu_server_poll", "bdu_server_drain", "bdu_server_pause",
                   "bdu_server_read", "bdu_server_close", "bdu_server_stats", "bdu_server_destroy"):
             getattr(L, f).restype = i32
@@ -255,6 +256,10 @@ class Handle:
 
     def update_projected(self, u, v) -> None:
         _check(lib().bdu_update_projected(self._h, _ptr(u), _ptr(v)), "bdu_update_projected")
+
+    def update_householder(self, b, c) -> None:
+        """A <- A + b c^T by the Householder bidiagonal update (Algorithm 1)."""
+        _check(lib().bdu_update_householder(self._h, _ptr(b), _ptr(c)), "bdu_update_householder")
 
     def project(self, b, c):
         u = np.empty(self.m)
