@@ -42,7 +42,7 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CUs x 128 FP64 flop/clk x 2.4 GHz
 # the workload named; otherwise the traffic is reported as null.
 TRAFFIC_SOURCES = ["paper_2509_02840_amd/csrc/kernels.hip", "paper_2509_02840_amd/csrc/primitives.h",
                    "paper_2509_02840_amd/csrc/schedule.h", "paper_2509_02840_amd/csrc/device.h",
-                   "paper_2509_02840_amd/csrc/plan.cpp"]
+                   "paper_2509_02840_amd/csrc/plan.cpp", "paper_2509_02840_amd/csrc/bdu.cpp"]
 MEASURED_TRAFFIC = {"sha256": "9c11764c8d76ff203d78a19691814d805435a9f2e186333c2dc9d0ab8715339b",
                     "n": 2048, "streams": 64, "tiling": (12, 7, 1), "bytes": 467469476270.2}
 
@@ -630,9 +630,13 @@ def main() -> int:
         x.close()
 
     value = S * args.steps / batched_time
+    # a split pass applies phase 1 and phase 2 in two launches, each with
+    # its share of the rotations (about half): flops per launch are the
+    # step's divided by the launches per step
     apply_ms, apply_launches = stages["apply"]
     avg_apply_s = apply_ms / 1e3 / max(apply_launches, 1)
-    flops_per_launch = S * applier_flops(bdu, n, n)
+    launches_per_step = max(apply_launches, 1) / args.steps
+    flops_per_launch = S * applier_flops(bdu, n, n) / launches_per_step
     achieved = flops_per_launch / avg_apply_s / 1e12
     k0, nw, rpl = tiling
 
@@ -664,7 +668,9 @@ def main() -> int:
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
                      "traffic": measured_traffic(n, S, (k0, nw, rpl)),
-                     "kernel": "apply_kernel", "flops_per_launch": flops_per_launch,
+                     "kernel": f"apply_staged_kernel<{k0}, {nw}, {rpl}>" if nw in (3, 5, 7, 15)
+                     else f"apply_kernel<{k0}, {nw}, {rpl}>",
+                     "flops_per_launch": flops_per_launch, "launches_per_step": launches_per_step,
                      "avg_launch_ms": avg_apply_s * 1e3},
     }
     if not args.no_cpu_baseline:

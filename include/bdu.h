@@ -166,9 +166,10 @@ int bdu_set_generation_in_lds(int allow);
  * term) at a tick where no rotation chain is in flight generates each pass
  * in two launches and applies the phase-1 rotations to Q and P on a stream
  * of its own while the phase-2 rotations are generated; the handle's stream
- * waits for both.  Same rotations in the same order, so results do not
- * depend on it.  Applies to handles created afterwards; batches never
- * split. */
+ * waits for both.  A batch does the same for each group of handles that all
+ * split, on a second stream of the batch.  Same rotations in the same order,
+ * so results do not depend on it.  Applies to handles and batches created
+ * afterwards. */
 int bdu_set_split_pass(int on);
 
 /* Input check: with on = 1, bdu_create, bdu_update, bdu_update_projected,

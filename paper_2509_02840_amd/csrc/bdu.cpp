@@ -307,6 +307,37 @@ hipError_t run_rotation_stages(HandleDev *const *hs, int count, bool any_spike, 
     return e;
 }
 
+// The same stages for passes that split after phase 1 (every listed handle's
+// schedule has a split tick): phase 1 is applied on `sd` while phase 2 is
+// generated on st, and st waits for the application.
+//   st: [spike] gen 1 -> e1 -> gen 2 -> e2 ............ wait e3
+//   sd:          wait e1 -> apply 1 -> wait e2 -> apply 2 -> e3
+hipError_t run_split_stages(HandleDev *const *hs, int count, bool any_spike, int64_t lds_bytes, bool in_lds,
+                            int gen_threads, int max_panels, int k0, int nw, int rpl, Gate gate, hipStream_t st,
+                            hipStream_t sd, hipEvent_t e1, hipEvent_t e2, hipEvent_t e3)
+{
+    Gate g1 = gate, g2 = gate;
+    g1.part = 1;
+    g2.part = 2;
+    hipError_t e = hipSuccess;
+    if (any_spike) e = timed(ST_SPIKE, st, [&] { return launch_spike(hs, count, g1, st); });
+    if (e == hipSuccess)
+        e = timed(ST_GEN, st, [&] { return launch_gen(hs, count, lds_bytes, in_lds, gen_threads, g1, st); });
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess)
+        e = timed(ST_GEN, st, [&] { return launch_gen(hs, count, lds_bytes, in_lds, gen_threads, g2, st); });
+    if (e == hipSuccess) e = hipEventRecord(e2, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(sd, e1, 0);
+    if (e == hipSuccess)
+        e = timed(ST_APPLY, sd, [&] { return launch_apply(hs, count, max_panels, k0, nw, rpl, g1, sd); });
+    if (e == hipSuccess) e = hipStreamWaitEvent(sd, e2, 0);
+    if (e == hipSuccess)
+        e = timed(ST_APPLY, sd, [&] { return launch_apply(hs, count, max_panels, k0, nw, rpl, g2, sd); });
+    if (e == hipSuccess) e = hipEventRecord(e3, sd);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, e3, 0);
+    return e;
+}
+
 int tiles_of(const bdu_ctx *h) { return (int)((h->m + 63) / 64 + (h->n + 63) / 64); }
 int panels_of(const bdu_ctx *h)
 {
@@ -323,27 +354,8 @@ int pass_single(bdu_ctx *h, int pass, bool project)
     const int64_t lds = gen_lds_bytes(h->n, h->plan->N);
     const int L = h->plan->L, np = panels_of(h), k0 = h->plan->K0, nw = h->plan->NW;
     if (e == hipSuccess && h->side) {
-        // Phase 1 ends with no chain in flight: generate it, then apply it on
-        // the side stream while phase 2 is generated.
-        //   stream: [spike] gen 1 -> sp1 -> gen 2 -> sp2 -> wait sp3
-        //   side:   wait sp1 -> apply 1 -> wait sp2 -> apply 2 -> sp3
-        const Gate g1{nullptr, pass, 1}, g2{nullptr, pass, 2};
-        hipStream_t sd = h->side;
-        if (h->m > h->n) e = timed(ST_SPIKE, st, [&] { return launch_spike(h->d_self, 1, g1, st); });
-        if (e == hipSuccess)
-            e = timed(ST_GEN, st, [&] { return launch_gen(h->d_self, 1, lds, h->lds_gen, L, g1, st); });
-        if (e == hipSuccess) e = hipEventRecord(h->sp1, st);
-        if (e == hipSuccess)
-            e = timed(ST_GEN, st, [&] { return launch_gen(h->d_self, 1, lds, h->lds_gen, L, g2, st); });
-        if (e == hipSuccess) e = hipEventRecord(h->sp2, st);
-        if (e == hipSuccess) e = hipStreamWaitEvent(sd, h->sp1, 0);
-        if (e == hipSuccess)
-            e = timed(ST_APPLY, sd, [&] { return launch_apply(h->d_self, 1, np, k0, nw, h->rpl, g1, sd); });
-        if (e == hipSuccess) e = hipStreamWaitEvent(sd, h->sp2, 0);
-        if (e == hipSuccess)
-            e = timed(ST_APPLY, sd, [&] { return launch_apply(h->d_self, 1, np, k0, nw, h->rpl, g2, sd); });
-        if (e == hipSuccess) e = hipEventRecord(h->sp3, sd);
-        if (e == hipSuccess) e = hipStreamWaitEvent(st, h->sp3, 0);
+        e = run_split_stages(h->d_self, 1, h->m > h->n, lds, h->lds_gen, L, np, k0, nw, h->rpl, Gate{nullptr, pass, 0},
+                             st, h->side, h->sp1, h->sp2, h->sp3);
     } else if (e == hipSuccess) {
         e = run_rotation_stages(h->d_self, 1, h->m > h->n, lds, h->lds_gen, L, np, k0, nw, h->rpl,
                                 Gate{nullptr, pass}, st);
@@ -433,12 +445,16 @@ struct bdu_batch_ctx {
         int64_t lds;
         int tiles, panels, off, cnt;
         int gen_threads;  // largest plan thread count of the group
+        bool split;       // every member's pass splits after phase 1
     };
     std::vector<Group> groups;  // handles of one applier tiling, contiguous in the arrays
     HandleDev **d_ptrs = nullptr;
     int32_t *d_ranks = nullptr;
     int32_t *h_ranks = nullptr;  // pinned staging of the ranks
     hipEvent_t ranks_copied = nullptr, done = nullptr;
+    // split passes: phase 1 applied on `side` while phase 2 is generated
+    hipStream_t side = nullptr;
+    hipEvent_t sp1 = nullptr, sp2 = nullptr, sp3 = nullptr;
     bool use_graph = false;
     int64_t steps = 0;
     hipGraphExec_t exec = nullptr;
@@ -456,6 +472,10 @@ void batch_free(bdu_batch b)
     if (b->ranks_copied) (void)hipEventDestroy(b->ranks_copied);
     if (b->done) (void)hipEventDestroy(b->done);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    if (b->sp1) (void)hipEventDestroy(b->sp1);
+    if (b->sp2) (void)hipEventDestroy(b->sp2);
+    if (b->sp3) (void)hipEventDestroy(b->sp3);
+    if (b->side) (void)hipStreamDestroy(b->side);
     delete b;
 }
 
@@ -492,7 +512,7 @@ int batch_build(const bdu_handle *hs, int count, int maxr, bool graph, bdu_batch
             if (x.k0 == h->plan->K0 && x.nw == h->plan->NW && x.rpl == h->rpl && x.in_lds == h->lds_gen) break;
         }
         if (g == b->groups.size()) {
-            b->groups.push_back({h->plan->K0, h->plan->NW, h->rpl, false, h->lds_gen, 0, 0, 0, 0, 0, 64});
+            b->groups.push_back({h->plan->K0, h->plan->NW, h->rpl, false, h->lds_gen, 0, 0, 0, 0, 0, 64, split_on()});
             members.emplace_back();
         }
         auto &x = b->groups[g];
@@ -502,7 +522,10 @@ int batch_build(const bdu_handle *hs, int count, int maxr, bool graph, bdu_batch
         x.gen_threads = std::max(x.gen_threads, h->plan->L);
         x.tiles = std::max(x.tiles, tiles_of(h));
         x.panels = std::max(x.panels, panels_of(h));
+        x.split = x.split && h->plan->split > 0;
     }
+    bool any_split = false;
+    for (auto &x : b->groups) any_split |= x.split;
     std::vector<HandleDev *> flat;
     b->pos.assign(count, 0);
     for (size_t g = 0; g < b->groups.size(); ++g) {
@@ -518,6 +541,12 @@ int batch_build(const bdu_handle *hs, int count, int maxr, bool graph, bdu_batch
     if (e == hipSuccess) e = hipHostMalloc(&b->h_ranks, sizeof(int32_t) * count, hipHostMallocDefault);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ranks_copied, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
+    if (e == hipSuccess && any_split) {
+        e = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->sp1, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->sp2, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->sp3, hipEventDisableTiming);
+    }
     if (e == hipSuccess) e = prepare_kernels();
     if (e == hipSuccess) e = hipMemcpy(b->d_ptrs, flat.data(), sizeof(HandleDev *) * count, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
@@ -539,7 +568,10 @@ hipError_t batch_launch(bdu_batch b)
             HandleDev **arr = b->d_ptrs + g.off;
             const Gate gate{b->d_ranks + g.off, p};
             hipError_t e = timed(ST_PROJECT, st, [&] { return launch_project(arr, g.cnt, g.tiles, gate, st); });
-            if (e == hipSuccess)
+            if (e == hipSuccess && g.split && b->side)
+                e = run_split_stages(arr, g.cnt, g.spike, g.lds, g.in_lds, g.gen_threads, g.panels, g.k0, g.nw,
+                                     g.rpl, gate, st, b->side, b->sp1, b->sp2, b->sp3);
+            else if (e == hipSuccess)
                 e = run_rotation_stages(arr, g.cnt, g.spike, g.lds, g.in_lds, g.gen_threads, g.panels, g.k0, g.nw,
                                         g.rpl, gate, st);
             if (e != hipSuccess) return e;
