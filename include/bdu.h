@@ -161,15 +161,18 @@ int bdu_autotune(int64_t m, int64_t n, int streams, int64_t *out);
  * it. */
 int bdu_set_generation_in_lds(int allow);
 
-/* Split passes: with on = 1 (default), a handle whose schedule ends phase 1
+/* Split passes: with on >= 1, a handle whose schedule ends phase 1
  * (Section 3.4: the upper-left chase, with the fold of the remaining rank-1
  * term) at a tick where no rotation chain is in flight generates each pass
- * in two launches and applies the phase-1 rotations to Q and P on a stream
- * of its own while the phase-2 rotations are generated; the handle's stream
- * waits for both.  A batch does the same for each group of handles that all
- * split, on a second stream of the batch.  Same rotations in the same order,
- * so results do not depend on it.  Applies to handles and batches created
- * afterwards. */
+ * in parts and applies the phase-1 rotations to Q and P on a stream of its
+ * own while the phase-2 rotations are generated; the handle's stream waits
+ * for both.  With on = 2 (default) a single handle also generates phase 2 in
+ * segments (bdu_plan_segments), each applied while the next is generated
+ * (the generator keeps the carried pairs of chains in flight across a
+ * segment end); on = 1 generates phase 2 in one launch.  A batch splits after
+ * phase 1 (on >= 1) for each group of handles that all split, on a second
+ * stream of the batch.  Same rotations in the same order, so results do not
+ * depend on it.  Applies to handles and batches created afterwards. */
 int bdu_set_split_pass(int on);
 
 /* Input check: with on = 1, bdu_create, bdu_update, bdu_update_projected,
@@ -363,6 +366,15 @@ int bdu_plan_stats(int64_t m, int64_t n, int64_t *out);
  * total count. */
 int64_t bdu_plan_rotations(int64_t m, int64_t n, int32_t *side, int64_t *idx,
                            int32_t *phase, int64_t *tick, int64_t cap);
+
+/* Phase-2 segments of a split single-handle pass: returns their number
+ * (0: none, at most 8); segment k generates the ticks below tcut[k] not
+ * generated before, and then its application runs over the applier blocks
+ * below bcut[k] (counted from the first phase-2 block) not applied before.
+ * block (optional, at most cap entries) receives the applier block of each
+ * rotation in the order of bdu_plan_rotations (phase-1 blocks first, then
+ * phase-2 blocks, on either side; -1 for spike rotations and the fold). */
+int bdu_plan_segments(int64_t m, int64_t n, int32_t *tcut, int32_t *bcut, int32_t *block, int64_t cap);
 
 #ifdef __cplusplus
 }

@@ -69,6 +69,7 @@ def lib():
         L.bdu_set_generation_in_lds.argtypes = [i32]
         L.bdu_set_finite_check.argtypes = [i32]
         L.bdu_set_split_pass.argtypes = [i32]
+        L.bdu_plan_segments.argtypes = [i64, i64, vp, vp, vp, i64]
         L.bdu_update_householder.argtypes = [vp, vp, vp]
         L.bdu_orth_error.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.bdu_reorthogonalize.argtypes = [vp, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
@@ -105,7 +106,7 @@ def lib():
                   "bdu_get_tiling", "bdu_plan_stats", "bdu_givens_device", "bdu_timing_enable",
                   "bdu_timing_read", "bdu_batch_create", "bdu_batch_update", "bdu_batch_sync",
                   "bdu_batch_info", "bdu_batch_destroy", "bdu_autotune", "bdu_tune_save", "bdu_tune_load",
-                  "bdu_handle_tiling", "bdu_set_generation_in_lds", "bdu_set_finite_check", "bdu_set_split_pass", "bdu_update_householder", "bdu_server_create", "bdu_server_open", "bdu_server_submit",
+                  "bdu_handle_tiling", "bdu_set_generation_in_lds", "bdu_set_finite_check", "bdu_set_split_pass", "bdu_plan_segments", "bdu_update_householder", "bdu_server_create", "bdu_server_open", "bdu_server_submit",
                   "bdu_server_wait", "bdu_server_poll", "bdu_server_drain", "bdu_server_pause",
                   "bdu_server_read", "bdu_server_close", "bdu_server_stats", "bdu_server_destroy"):
             getattr(L, f).restype = i32
@@ -159,9 +160,21 @@ def set_generation_in_lds(allow: bool) -> None:
     _check(lib().bdu_set_generation_in_lds(1 if allow else 0), "bdu_set_generation_in_lds")
 
 
-def set_split_pass(on: bool) -> None:
-    """Apply phase 1 on a side stream while phase 2 is generated (handles created afterwards)."""
-    _check(lib().bdu_set_split_pass(1 if on else 0), "bdu_set_split_pass")
+def set_split_pass(mode) -> None:
+    """0 / False: off; 1: phase 1 applied while phase 2 is generated; 2 / True
+    (the default): also phase 2 in segments (handles created afterwards)."""
+    _check(lib().bdu_set_split_pass(2 if mode is True else int(mode)), "bdu_set_split_pass")
+
+
+def plan_segments(m: int, n: int):
+    """(tcut, bcut, block) of the phase-2 segments; block in plan_rotations order."""
+    L = lib()
+    cnt = _check(L.bdu_plan_rotations(m, n, None, None, None, None, 0), "bdu_plan_rotations")
+    tc = np.zeros(8, np.int32)
+    bc = np.zeros(8, np.int32)
+    blk = np.empty(cnt, np.int32)
+    ns = _check(L.bdu_plan_segments(m, n, tc.ctypes.data, bc.ctypes.data, blk.ctypes.data, cnt), "bdu_plan_segments")
+    return tc[:ns], bc[:ns], blk
 
 
 def set_tiling_auto() -> None:

@@ -42,6 +42,7 @@ std::map<std::pair<int64_t, int64_t>, Tuned> g_tuned;
 bool g_gen_lds = true;  // generation keeps its band in LDS when it fits
 bool g_check_finite = false;  // reject NaN / Inf inputs (one extra pass and a sync per call)
 bool g_split = true;          // single-handle passes apply phase 1 while phase 2 is generated
+bool g_segments = true;       // ... and phase 2 in segments, each applied while the next is generated
 
 struct PlanEntry {
     std::unique_ptr<Plan> plan;
@@ -168,6 +169,7 @@ struct bdu_ctx {
     // end of the application
     hipStream_t side = nullptr;
     hipEvent_t sp1 = nullptr, sp2 = nullptr, sp3 = nullptr;
+    hipEvent_t seg[kMaxSeg] = {};  // ends of the phase-2 segments
     // orthogonality monitor scratch (allocated on first use)
     double *orthE = nullptr, *orthY = nullptr, *orthPart = nullptr, *orthOut = nullptr;
     // Householder update scratch (allocated on first use)
@@ -353,7 +355,34 @@ int pass_single(bdu_ctx *h, int pass, bool project)
         e = timed(ST_PROJECT, st, [&] { return launch_project(h->d_self, 1, tiles_of(h), Gate{nullptr, pass}, st); });
     const int64_t lds = gen_lds_bytes(h->n, h->plan->N);
     const int L = h->plan->L, np = panels_of(h), k0 = h->plan->K0, nw = h->plan->NW;
-    if (e == hipSuccess && h->side) {
+    if (e == hipSuccess && h->side && h->plan->nseg > 0 && h->seg[0]) {
+        // phase 1, then the phase-2 segments; each part's application on
+        // the side stream once its generation is done, the next part's
+        // generation beside it
+        hipStream_t sd = h->side;
+        const int nseg = h->plan->nseg;
+        const Gate g1{nullptr, pass, 1};
+        if (h->m > h->n) e = timed(ST_SPIKE, st, [&] { return launch_spike(h->d_self, 1, g1, st); });
+        if (e == hipSuccess)
+            e = timed(ST_GEN, st, [&] { return launch_gen(h->d_self, 1, lds, h->lds_gen, L, g1, st); });
+        if (e == hipSuccess) e = hipEventRecord(h->sp1, st);
+        for (int k = 0; k < nseg && e == hipSuccess; ++k) {
+            const Gate gk{nullptr, pass, 3 + k};
+            e = timed(ST_GEN, st, [&] { return launch_gen(h->d_self, 1, lds, h->lds_gen, L, gk, st); });
+            if (e == hipSuccess) e = hipEventRecord(h->seg[k], st);
+        }
+        if (e == hipSuccess) e = hipStreamWaitEvent(sd, h->sp1, 0);
+        if (e == hipSuccess)
+            e = timed(ST_APPLY, sd, [&] { return launch_apply(h->d_self, 1, np, k0, nw, h->rpl, g1, sd); });
+        for (int k = 0; k < nseg && e == hipSuccess; ++k) {
+            const Gate gk{nullptr, pass, 3 + k};
+            e = hipStreamWaitEvent(sd, h->seg[k], 0);
+            if (e == hipSuccess)
+                e = timed(ST_APPLY, sd, [&] { return launch_apply(h->d_self, 1, np, k0, nw, h->rpl, gk, sd); });
+        }
+        if (e == hipSuccess) e = hipEventRecord(h->sp3, sd);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, h->sp3, 0);
+    } else if (e == hipSuccess && h->side) {
         e = run_split_stages(h->d_self, 1, h->m > h->n, lds, h->lds_gen, L, np, k0, nw, h->rpl, Gate{nullptr, pass, 0},
                              st, h->side, h->sp1, h->sp2, h->sp3);
     } else if (e == hipSuccess) {
@@ -382,6 +411,12 @@ int64_t slot_of(const Plan &P, const GenChain &g, const Rot &r)
 
 namespace {
 
+bool segments_on()
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g_segments;
+}
+
 bool split_on()
 {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -394,8 +429,11 @@ void release_streams(bdu_ctx *h)
     if (h->sp1) (void)hipEventDestroy(h->sp1);
     if (h->sp2) (void)hipEventDestroy(h->sp2);
     if (h->sp3) (void)hipEventDestroy(h->sp3);
+    for (int k = 0; k < kMaxSeg; ++k)
+        if (h->seg[k]) (void)hipEventDestroy(h->seg[k]);
     if (h->side) (void)hipStreamDestroy(h->side);
     h->ev = h->sp1 = h->sp2 = h->sp3 = nullptr;
+    for (int k = 0; k < kMaxSeg; ++k) h->seg[k] = nullptr;
     h->side = nullptr;
 }
 
@@ -660,9 +698,10 @@ int bdu_set_generation_in_lds(int allow)
 
 int bdu_set_split_pass(int on)
 {
-    if (on != 0 && on != 1) return BDU_EINVAL;
+    if (on < 0 || on > 2) return BDU_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
     g_split = on != 0;
+    g_segments = on == 2;
     return BDU_OK;
 }
 
@@ -712,6 +751,7 @@ int create_impl(int64_t m, int64_t n, const double *Q, const double *d, const do
     // the band in device memory (large n), or the image of the LDS band
     // kept between the two parts of a split generation
     A(dalloc(h.get(), &hd.band, gen_lds_bytes(n, plan->N) / 8));
+    A(dalloc(h.get(), &hd.carry, 4 * kGenThreads));
     A(dalloc(h.get(), &h->d_hd, 1));
     A(dalloc(h.get(), &h->d_self, 1));
     A(dalloc(h.get(), &h->flag, 1));
@@ -726,6 +766,11 @@ int create_impl(int64_t m, int64_t n, const double *Q, const double *d, const do
     hd.blkR = plan->d_blocks[1];
     hd.ticks = plan->ticks;
     hd.split = plan->split;
+    hd.nseg = plan->nseg;
+    for (int k = 0; k < kMaxSeg; ++k) {
+        hd.tcut[k] = plan->tcut[k];
+        hd.bcut[k] = plan->bcut[k];
+    }
     hd.m = (int32_t)m;
     hd.n = (int32_t)n;
     hd.ldq = (int32_t)ldq;
@@ -765,6 +810,8 @@ int create_impl(int64_t m, int64_t n, const double *Q, const double *d, const do
              hipEventCreateWithFlags(&hp->sp1, hipEventDisableTiming) == hipSuccess &&
              hipEventCreateWithFlags(&hp->sp2, hipEventDisableTiming) == hipSuccess &&
              hipEventCreateWithFlags(&hp->sp3, hipEventDisableTiming) == hipSuccess;
+        for (int k = 0; ok && segments_on() && k < plan->nseg; ++k)
+            ok = hipEventCreateWithFlags(&hp->seg[k], hipEventDisableTiming) == hipSuccess;
     }
     if (!ok) {
         release_streams(hp);
@@ -1229,6 +1276,35 @@ int bdu_plan_stats(int64_t m, int64_t n, int64_t *out)
     out[7] = p->L;
     out[8] = p->split;
     return BDU_OK;
+}
+
+int bdu_plan_segments(int64_t m, int64_t n, int32_t *tcut, int32_t *bcut, int32_t *block, int64_t cap)
+{
+    if (m < n || n < 2) return BDU_EINVAL;
+    int k0, nw, rpl;
+    tiling_for(m, n, &k0, &nw, &rpl);
+    hipError_t e;
+    Plan *p = get_plan(m, n, k0, nw, false, &e);
+    for (int k = 0; k < p->nseg; ++k) {
+        if (tcut) tcut[k] = p->tcut[k];
+        if (bcut) bcut[k] = p->bcut[k];
+    }
+    // applier block of each rotation, in the order of bdu_plan_rotations
+    int64_t k = 0;
+    auto emit = [&](int b) {
+        if (block && k < cap) block[k] = b;
+        ++k;
+    };
+    for (int64_t t = 0; t < p->nspike; ++t) emit(-1);
+    for (const GenChain &g : p->chains) {
+        if (g.type == CH_FOLD) {
+            emit(-1);
+            continue;
+        }
+        const int b = chain_in_phase(g.type, g.param) / p->K + (chain_phase(g.type) == 1 ? 0 : p->nb1);
+        for (int q = 0; q < g.len; ++q) emit(b);
+    }
+    return p->nseg;
 }
 
 int64_t bdu_plan_rotations(int64_t m, int64_t n, int32_t *side, int64_t *idx, int32_t *phase, int64_t *tick,

@@ -8,6 +8,8 @@
 
 namespace bdu {
 
+constexpr int kMaxSeg = 8;  // most phase-2 segments of a split pass
+
 // Everything a kernel needs to update one factorization A = Q Bd P^T.
 // Q is m x m and P is n x n, column-major; their leading dimensions ldq, ldp
 // are m and n rounded up to a multiple of 128 (the padding rows are zero).
@@ -25,18 +27,41 @@ struct HandleDev {
     int32_t ldq, ldp;
     int32_t K0, NW, K, S;
     int64_t split;          // generation split tick (Plan::split)
+    // phase-2 segments of a split pass: segment k generates ticks
+    // [tcut[k-1], tcut[k]) (tcut[-1] = split) and applies phase-2 blocks
+    // [bcut[k-1], bcut[k]) (bcut[-1] = 0); nseg == 0: no segments
+    int32_t nseg;
+    int32_t tcut[kMaxSeg], bcut[kMaxSeg];
+    double *carry;          // register carries of chains in flight at a segment end (4 per thread)
 };
 
 // Per-launch gate of a batch in which streams take different ranks: the
 // handle at position i of a launch takes part in pass `pass` only if
 // pass < ranks[i] (ranks == nullptr: every handle takes part).
 // part: 0 the whole pass; 1 generation up to the end of phase 1 (with the
-// fold) and application of the spike and the phase-1 blocks; 2 the rest.
+// fold) and application of the spike and the phase-1 blocks; 2 the rest;
+// 3 + k phase-2 segment k (HandleDev::tcut, bcut).
 struct Gate {
     const int32_t *ranks;
     int32_t pass;
     int32_t part;
 };
+
+// Applier blocks [*bbeg, *bend) of a part, and whether it applies the spike.
+template <typename H>
+__host__ __device__ inline bool part_blocks(const H *h, int part, int *bbeg, int *bend)
+{
+    const int nb1 = h->nb1, nb2 = h->nb2;
+    if (part >= 3) {
+        const int k = part - 3;
+        *bbeg = nb1 + (k == 0 ? 0 : h->bcut[k - 1]);
+        *bend = nb1 + h->bcut[k];
+    } else {
+        *bbeg = part == 2 ? nb1 : 0;
+        *bend = part == 1 ? nb1 : nb1 + nb2;
+    }
+    return part <= 1;
+}
 
 constexpr int kGenThreads = 1024;  // at n = 2048, 256 threads leave chains waiting for a free thread
 

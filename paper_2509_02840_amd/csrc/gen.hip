@@ -166,13 +166,21 @@ __global__ __launch_bounds__(kGenThreads) void gen_kernel(HandleDev *const *hs, 
     const int tid = threadIdx.x;
     const int nt = blockDim.x;
     const int total = VO + (n + 8);
-    // part 2 continues from the band part 1 left (in device memory, or the
-    // image of the LDS band part 1 saved there); otherwise start from d, e,
-    // u and v
+    // A part after the first continues from the band the previous one left
+    // (in device memory, or the image of the LDS band saved there);
+    // otherwise start from d, e, u and v.  Parts: 0 all ticks, 1 phase 1,
+    // 2 phase 2, 3 + k phase-2 segment k.
     const int part = gate.part;
-    const int t_begin = part == 2 ? (int)h->split : 0;
-    const int t_end = part == 1 ? (int)h->split : (int)h->ticks;
-    if (part == 2) {
+    const int ticks = (int)h->ticks, split = (int)h->split;
+    int t_begin = 0, t_end = ticks;
+    if (part == 1) t_end = split;
+    if (part == 2) t_begin = split;
+    if (part >= 3) {
+        const int k = part - 3;
+        t_begin = k == 0 ? split : h->tcut[k - 1];
+        t_end = h->tcut[k];
+    }
+    if (part >= 2) {
         if (IN_LDS)
             for (int k = tid; k < total; k += nt) S[k] = h->band[k];
         __syncthreads();
@@ -231,9 +239,24 @@ __global__ __launch_bounds__(kGenThreads) void gen_kernel(HandleDev *const *hs, 
         du = m1 ? -3 : 3;
         tend = g.tau0 + g.len - 1;
     };
-    if (ci < nch) start();
-
     double kx0 = 0.0, kx1 = 0.0, ky0 = 0.0, ky1 = 0.0;  // slots 0, 1 carried from the previous rotation
+    if (ci < nch) {
+        start();
+        if (g.tau0 < t_begin) {
+            // in flight since an earlier segment: resume at rotation q with
+            // the carried pairs that segment saved
+            const int q = t_begin - g.tau0;
+            const RotAddr<BP> aq = decode(SB, g, q, K, UO, VO, csL, csR),
+                              aq1 = decode(SB, g, q + 1, K, UO, VO, csL, csR);
+            const bool oddq = t_begin & 1;
+            ae = oddq ? aq1 : aq;
+            ao = oddq ? aq : aq1;
+            kx0 = h->carry[4 * tid];
+            kx1 = h->carry[4 * tid + 1];
+            ky0 = h->carry[4 * tid + 2];
+            ky1 = h->carry[4 * tid + 3];
+        }
+    }
     // One rotation with its window, for one phase (the phase is uniform
     // across a wavefront except where phase 2 starts, so a wavefront
     // normally runs one of the two bodies).
@@ -348,9 +371,17 @@ __global__ __launch_bounds__(kGenThreads) void gen_kernel(HandleDev *const *hs, 
     }
     if (t < t_end) tick(ae, t);
 
-    if (part == 1) {
+    if (t_end < ticks) {
+        // a later part continues: keep the band and the carries of a chain
+        // still in flight (none at the end of phase 1)
         if (IN_LDS)
             for (int k = tid; k < total; k += nt) h->band[k] = S[k];
+        if (ci < nch && g.tau0 < t_end) {
+            h->carry[4 * tid] = kx0;
+            h->carry[4 * tid + 1] = kx1;
+            h->carry[4 * tid + 2] = ky0;
+            h->carry[4 * tid + 3] = ky1;
+        }
         return;
     }
     for (int i = 1 + tid; i <= n; i += nt) {

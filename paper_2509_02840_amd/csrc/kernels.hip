@@ -334,24 +334,26 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(K0 * R 
     const int lane = threadIdx.x & 63;
     // the ring starts finite (stale slots may meet identity rotations)
     for (int i = threadIdx.x; i < RING; i += 64 * NW) ring[i] = 0.0;
-    const int nb1 = h->nb1, nb2 = h->nb2;
-    // blocks of this part: phase 1 = [0, nb1), phase 2 = [nb1, nb1 + nb2)
-    const int b1a = gate.part == 2 ? nb1 : 0;         // phase-1 blocks [b1a, nb1)
-    const int b2e = gate.part == 1 ? nb1 : nb1 + nb2;  // phase-2 blocks [nb1, b2e)
+    const int nb1 = h->nb1;
+    // blocks of this part (phase 1 = [0, nb1), phase 2 = [nb1, nb1 + nb2))
+    int bbeg, bend;
+    const bool spike_part = part_blocks(h, gate.part, &bbeg, &bend);
+    const int b1a = bbeg < nb1 ? bbeg : nb1, b1e = bend < nb1 ? bend : nb1;  // phase-1 blocks [b1a, b1e)
+    const int b2a = bbeg > nb1 ? bbeg : nb1, b2e = bend;                     // phase-2 blocks [b2a, b2e)
     if (pid < qp) {
         const int row0 = pid * PH + lane;
         GLOBAL double *Q = gptr(h->Q);
-        if (m > n && w == 0 && gate.part != 2) {
+        if (m > n && w == 0 && spike_part) {
 #pragma unroll
             for (int r = 0; r < R; ++r) spike_apply(Q, h->ldq, m, n, row0 + 64 * r, kptr((const double *)h->csSp));
         }
         __syncthreads();
-        for (int b = b1a; b < nb1; ++b) {
+        for (int b = b1a; b < b1e; ++b) {
             const BlockDesc bd = load_block(h->blkL, b);
             sweep<K0, NW, R, 0>(Q, h->ldq, m, row0, kptr((const double *)h->csL) + 2 * bd.off, bd, ring, w, lane);
             __syncthreads();
         }
-        for (int b = nb1; b < b2e; ++b) {
+        for (int b = b2a; b < b2e; ++b) {
             const BlockDesc bd = load_block(h->blkL, b);
             sweep<K0, NW, R, 2>(Q, h->ldq, m, row0, kptr((const double *)h->csL) + 2 * bd.off, bd, ring, w, lane);
             __syncthreads();
@@ -359,12 +361,12 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(K0 * R 
     } else {
         const int row0 = (pid - qp) * PH + lane;
         GLOBAL double *P = gptr(h->P);
-        for (int b = b1a; b < nb1; ++b) {
+        for (int b = b1a; b < b1e; ++b) {
             const BlockDesc bd = load_block(h->blkR, b);
             sweep<K0, NW, R, 1>(P, h->ldp, n, row0, kptr((const double *)h->csR) + 2 * bd.off, bd, ring, w, lane);
             __syncthreads();
         }
-        for (int b = nb1; b < b2e; ++b) {
+        for (int b = b2a; b < b2e; ++b) {
             const BlockDesc bd = load_block(h->blkR, b);
             sweep<K0, NW, R, 3>(P, h->ldp, n, row0, kptr((const double *)h->csR) + 2 * bd.off, bd, ring, w, lane);
             __syncthreads();
@@ -585,7 +587,7 @@ void apply_staged_kernel(HandleDev *const *hs, Gate gate)
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     for (int i = threadIdx.x; i < T::LDS_DOUBLES; i += 64 * (NW + 1)) lds[i] = 0.0;
-    const int nb1 = h->nb1, nb2 = h->nb2;
+    const int nb1 = h->nb1;
     const bool onQ = pid < qp;
     const int row0 = (onQ ? pid : pid - qp) * PH + lane;
     GLOBAL double *X = gptr(onQ ? h->Q : h->P);
@@ -593,13 +595,13 @@ void apply_staged_kernel(HandleDev *const *hs, Gate gate)
     const int ncols = onQ ? m : n;
     const BlockDesc *blk = onQ ? h->blkL : h->blkR;
     const CONSTANT double *cs = kptr((const double *)(onQ ? h->csL : h->csR));
-    if (onQ && m > n && w == 0 && gate.part != 2) {
+    int bbeg, bend;
+    const bool spike_part = part_blocks(h, gate.part, &bbeg, &bend);
+    if (onQ && m > n && w == 0 && spike_part) {
 #pragma unroll
         for (int r = 0; r < R; ++r) spike_apply(X, ld, m, n, row0 + 64 * r, kptr((const double *)h->csSp));
     }
     __syncthreads();
-    // blocks of this part: phase 1 = [0, nb1), phase 2 = [nb1, nb1 + nb2)
-    const int bbeg = gate.part == 2 ? nb1 : 0, bend = gate.part == 1 ? nb1 : nb1 + nb2;
     for (int b = bbeg; b < bend; ++b) {
         const BlockDesc bd = load_block(blk, b);
         const CONSTANT double *cb = cs + 2 * bd.off;

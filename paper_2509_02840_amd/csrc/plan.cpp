@@ -26,6 +26,11 @@ static void add_chain(std::vector<GenChain> &v, int type, int param, int len)
     v.push_back(c);
 }
 
+// Phase-2 segments of a split single-handle pass (more segments hide more of
+// the phase-2 application behind generation, each costs a generation launch
+// with its band save and reload and an applier launch).
+constexpr int kPhase2Segments = 4;
+
 std::unique_ptr<Plan> build_plan(int64_t m, int64_t n, int K0, int NW, int gen_threads)
 {
     auto P = std::make_unique<Plan>();
@@ -178,6 +183,36 @@ std::unique_ptr<Plan> build_plan(int64_t m, int64_t n, int K0, int NW, int gen_t
             const int pos = front_order(2 * (ph - 1) + r.side, K, K0).pos[tl];
             g.slot[r.side] = bd.off + (int64_t)(lam0 / 3 + tl + w * S) * K + w * K0 + pos;
         }
+    }
+    // ---- phase-2 segments of a split pass --------------------------------
+    // Phase-2 block b holds the chains of phase-2 index [bK, bK + K) on both
+    // sides; blocks [0, c) are complete at the tick their last chain ends.
+    // Segment k ends at such a tick for the block cut c_k (cuts spread
+    // evenly over the blocks, the last at all of them), so its application
+    // can run while the next segment is generated.  Chains may be in flight
+    // at a segment end: the generator saves their carried pairs.
+    if (P->split > 0 && P->nb2 > 0) {
+        std::vector<int64_t> done(P->nb2, P->split);
+        for (const GenChain &g : ch) {
+            if (g.type == CH_FOLD || chain_phase(g.type) != 2) continue;
+            const int b = chain_in_phase(g.type, g.param) / K;
+            done[b] = std::max<int64_t>(done[b], g.tau0 + g.len);
+        }
+        for (int b = 1; b < P->nb2; ++b) done[b] = std::max(done[b], done[b - 1]);
+        const int want = std::min(kPhase2Segments, P->nb2);
+        int64_t prev_t = P->split;
+        int prev_c = 0;
+        for (int k = 1; k <= want; ++k) {
+            const int c = k == want ? P->nb2 : (int)((int64_t)P->nb2 * k / want);
+            const int64_t t = k == want ? P->ticks : done[c - 1];
+            if (c <= prev_c || t <= prev_t || (k < want && t >= P->ticks)) continue;
+            P->bcut[P->nseg] = c;
+            P->tcut[P->nseg] = (int32_t)t;
+            ++P->nseg;
+            prev_c = c;
+            prev_t = t;
+        }
+        if (P->nseg == 0 || P->bcut[P->nseg - 1] != P->nb2 || P->tcut[P->nseg - 1] != P->ticks) P->nseg = 0;
     }
     return P;
 }

@@ -68,14 +68,16 @@ def test_large_n_sampled_rows(bdu, oracle, m, n):
     _eq("P rows", P1[pr], Pr)
 
 
+@pytest.mark.parametrize("mode", [0, 1])
 @pytest.mark.parametrize("in_lds", [True, False])
 @pytest.mark.parametrize("m,n,r", [(2, 2, 1), (14, 12, 2), (65, 64, 1), (257, 191, 2)])
-def test_unsplit_pass_bit_exact(bdu, oracle, m, n, r, in_lds):
-    """Passes generated in one launch and applied after it (split passes
-    off) give the oracle's result too; the other tests run split passes."""
+def test_unsplit_pass_bit_exact(bdu, oracle, m, n, r, in_lds, mode):
+    """Passes generated in one launch and applied after it (mode 0), or
+    split after phase 1 only (mode 1), give the oracle's result too; the
+    other tests run the default (phase 2 in segments)."""
     f = W.factorization(m, n, 610 + m)
     (B, C), = W.gaussian_updates(m, n, 1, 611 + n, r=r)
-    bdu.set_split_pass(False)
+    bdu.set_split_pass(mode)
     bdu.set_generation_in_lds(in_lds)
     try:
         h = bdu.Handle(f.Q, f.d, f.e, f.P)
