@@ -513,8 +513,8 @@ def main() -> int:
                     help="only run a plain 1 GiB device copy three times (scale for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(streams shard across GPUs with no communication; see the design notes)",
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(independent streams would shard across GPUs with no communication)",
               file=sys.stderr)
         return 2
 
