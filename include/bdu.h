@@ -166,10 +166,10 @@ int bdu_set_generation_in_lds(int allow);
  * term) at a tick where no rotation chain is in flight generates each pass
  * in parts and applies the phase-1 rotations to Q and P on a stream of its
  * own while the phase-2 rotations are generated; the handle's stream waits
- * for both.  With on = 2 (default) a single handle also generates phase 2 in
- * segments (bdu_plan_segments), each applied while the next is generated
- * (the generator keeps the carried pairs of chains in flight across a
- * segment end); on = 1 generates phase 2 in one launch.  A batch splits after
+ * for both.  With on = 2 (default) a single handle instead generates the
+ * whole pass in segments (bdu_plan_segments), each applied while the next is
+ * generated (the generator keeps the carried pairs of chains in flight
+ * across a segment end); on = 1 splits only after phase 1.  A batch splits after
  * phase 1 (on >= 1) for each group of handles that all split, on a second
  * stream of the batch.  Same rotations in the same order, so results do not
  * depend on it.  Applies to handles and batches created afterwards. */
@@ -367,13 +367,14 @@ int bdu_plan_stats(int64_t m, int64_t n, int64_t *out);
 int64_t bdu_plan_rotations(int64_t m, int64_t n, int32_t *side, int64_t *idx,
                            int32_t *phase, int64_t *tick, int64_t cap);
 
-/* Phase-2 segments of a split single-handle pass: returns their number
- * (0: none, at most 8); segment k generates the ticks below tcut[k] not
- * generated before, and then its application runs over the applier blocks
- * below bcut[k] (counted from the first phase-2 block) not applied before.
- * block (optional, at most cap entries) receives the applier block of each
- * rotation in the order of bdu_plan_rotations (phase-1 blocks first, then
- * phase-2 blocks, on either side; -1 for spike rotations and the fold). */
+/* Segments of a single-handle pass: returns their number (0: none, at most
+ * 8); segment k generates the ticks below tcut[k] not generated before, and
+ * then its application runs over the applier blocks below bcut[k] not
+ * applied before (phase-1 blocks first, then phase-2 blocks; the first
+ * segment also applies the spike).  block (optional, at most cap entries)
+ * receives the applier block of each rotation in the order of
+ * bdu_plan_rotations (numbered the same way, on either side; -1 for spike
+ * rotations and the fold). */
 int bdu_plan_segments(int64_t m, int64_t n, int32_t *tcut, int32_t *bcut, int32_t *block, int64_t cap);
 
 #ifdef __cplusplus

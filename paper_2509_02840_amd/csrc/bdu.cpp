@@ -356,24 +356,18 @@ int pass_single(bdu_ctx *h, int pass, bool project)
     const int64_t lds = gen_lds_bytes(h->n, h->plan->N);
     const int L = h->plan->L, np = panels_of(h), k0 = h->plan->K0, nw = h->plan->NW;
     if (e == hipSuccess && h->side && h->plan->nseg > 0 && h->seg[0]) {
-        // phase 1, then the phase-2 segments; each part's application on
-        // the side stream once its generation is done, the next part's
-        // generation beside it
+        // the pass in segments; each segment's application on the side
+        // stream once its generation is done, the next segment's generation
+        // beside it
         hipStream_t sd = h->side;
         const int nseg = h->plan->nseg;
-        const Gate g1{nullptr, pass, 1};
-        if (h->m > h->n) e = timed(ST_SPIKE, st, [&] { return launch_spike(h->d_self, 1, g1, st); });
-        if (e == hipSuccess)
-            e = timed(ST_GEN, st, [&] { return launch_gen(h->d_self, 1, lds, h->lds_gen, L, g1, st); });
-        if (e == hipSuccess) e = hipEventRecord(h->sp1, st);
+        if (h->m > h->n)
+            e = timed(ST_SPIKE, st, [&] { return launch_spike(h->d_self, 1, Gate{nullptr, pass, 3}, st); });
         for (int k = 0; k < nseg && e == hipSuccess; ++k) {
             const Gate gk{nullptr, pass, 3 + k};
             e = timed(ST_GEN, st, [&] { return launch_gen(h->d_self, 1, lds, h->lds_gen, L, gk, st); });
             if (e == hipSuccess) e = hipEventRecord(h->seg[k], st);
         }
-        if (e == hipSuccess) e = hipStreamWaitEvent(sd, h->sp1, 0);
-        if (e == hipSuccess)
-            e = timed(ST_APPLY, sd, [&] { return launch_apply(h->d_self, 1, np, k0, nw, h->rpl, g1, sd); });
         for (int k = 0; k < nseg && e == hipSuccess; ++k) {
             const Gate gk{nullptr, pass, 3 + k};
             e = hipStreamWaitEvent(sd, h->seg[k], 0);

@@ -27,9 +27,9 @@ struct HandleDev {
     int32_t ldq, ldp;
     int32_t K0, NW, K, S;
     int64_t split;          // generation split tick (Plan::split)
-    // phase-2 segments of a split pass: segment k generates ticks
-    // [tcut[k-1], tcut[k]) (tcut[-1] = split) and applies phase-2 blocks
-    // [bcut[k-1], bcut[k]) (bcut[-1] = 0); nseg == 0: no segments
+    // segments of a pass: segment k generates ticks [tcut[k-1], tcut[k])
+    // and applies blocks [bcut[k-1], bcut[k]) (phase-1 blocks, then
+    // phase-2 blocks; tcut[-1] = bcut[-1] = 0); nseg == 0: no segments
     int32_t nseg;
     int32_t tcut[kMaxSeg], bcut[kMaxSeg];
     double *carry;          // register carries of chains in flight at a segment end (4 per thread)
@@ -40,7 +40,7 @@ struct HandleDev {
 // pass < ranks[i] (ranks == nullptr: every handle takes part).
 // part: 0 the whole pass; 1 generation up to the end of phase 1 (with the
 // fold) and application of the spike and the phase-1 blocks; 2 the rest;
-// 3 + k phase-2 segment k (HandleDev::tcut, bcut).
+// 3 + k segment k (HandleDev::tcut, bcut; segment 0 also applies the spike).
 struct Gate {
     const int32_t *ranks;
     int32_t pass;
@@ -54,12 +54,12 @@ __host__ __device__ inline bool part_blocks(const H *h, int part, int *bbeg, int
     const int nb1 = h->nb1, nb2 = h->nb2;
     if (part >= 3) {
         const int k = part - 3;
-        *bbeg = nb1 + (k == 0 ? 0 : h->bcut[k - 1]);
-        *bend = nb1 + h->bcut[k];
-    } else {
-        *bbeg = part == 2 ? nb1 : 0;
-        *bend = part == 1 ? nb1 : nb1 + nb2;
+        *bbeg = k == 0 ? 0 : h->bcut[k - 1];
+        *bend = h->bcut[k];
+        return k == 0;
     }
+    *bbeg = part == 2 ? nb1 : 0;
+    *bend = part == 1 ? nb1 : nb1 + nb2;
     return part <= 1;
 }
 

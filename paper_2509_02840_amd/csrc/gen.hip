@@ -169,7 +169,7 @@ __global__ __launch_bounds__(kGenThreads) void gen_kernel(HandleDev *const *hs, 
     // A part after the first continues from the band the previous one left
     // (in device memory, or the image of the LDS band saved there);
     // otherwise start from d, e, u and v.  Parts: 0 all ticks, 1 phase 1,
-    // 2 phase 2, 3 + k phase-2 segment k.
+    // 2 phase 2, 3 + k segment k.
     const int part = gate.part;
     const int ticks = (int)h->ticks, split = (int)h->split;
     int t_begin = 0, t_end = ticks;
@@ -177,10 +177,10 @@ __global__ __launch_bounds__(kGenThreads) void gen_kernel(HandleDev *const *hs, 
     if (part == 2) t_begin = split;
     if (part >= 3) {
         const int k = part - 3;
-        t_begin = k == 0 ? split : h->tcut[k - 1];
+        t_begin = k == 0 ? 0 : h->tcut[k - 1];
         t_end = h->tcut[k];
     }
-    if (part >= 2) {
+    if (t_begin > 0) {
         if (IN_LDS)
             for (int k = tid; k < total; k += nt) S[k] = h->band[k];
         __syncthreads();

@@ -26,10 +26,11 @@ static void add_chain(std::vector<GenChain> &v, int type, int param, int len)
     v.push_back(c);
 }
 
-// Phase-2 segments of a split single-handle pass (more segments hide more of
-// the phase-2 application behind generation, each costs a generation launch
-// with its band save and reload and an applier launch).
-constexpr int kPhase2Segments = 4;
+// Segments of a single-handle pass (more segments hide more of the
+// application behind generation; each costs a generation launch with its
+// band save and reload and an applier launch).  Measured on one stream:
+// 8 are best from n = 257 up, 4 below (n = 129: 0.82 ms against 0.85).
+constexpr int kSegments = 8, kSegmentsSmall = 4;
 
 std::unique_ptr<Plan> build_plan(int64_t m, int64_t n, int K0, int NW, int gen_threads)
 {
@@ -184,26 +185,28 @@ std::unique_ptr<Plan> build_plan(int64_t m, int64_t n, int K0, int NW, int gen_t
             g.slot[r.side] = bd.off + (int64_t)(lam0 / 3 + tl + w * S) * K + w * K0 + pos;
         }
     }
-    // ---- phase-2 segments of a split pass --------------------------------
-    // Phase-2 block b holds the chains of phase-2 index [bK, bK + K) on both
-    // sides; blocks [0, c) are complete at the tick their last chain ends.
-    // Segment k ends at such a tick for the block cut c_k (cuts spread
-    // evenly over the blocks, the last at all of them), so its application
-    // can run while the next segment is generated.  Chains may be in flight
-    // at a segment end: the generator saves their carried pairs.
-    if (P->split > 0 && P->nb2 > 0) {
-        std::vector<int64_t> done(P->nb2, P->split);
+    // ---- segments of a pass ---------------------------------------------
+    // Applier block b (phase-1 blocks, then phase-2 blocks) holds the chains
+    // of in-phase index [bK, bK + K) of its phase on both sides; blocks
+    // [0, c) are complete at the tick their last chain ends.  Segment k ends
+    // at such a tick for the block cut c_k (cuts spread evenly over the
+    // blocks, the last at all of them), so its application can run while
+    // the next segment is generated.  Chains may be in flight at a segment
+    // end: the generator saves their carried pairs.
+    {
+        const int nbt = P->nb1 + P->nb2;
+        std::vector<int64_t> done(nbt, 0);
         for (const GenChain &g : ch) {
-            if (g.type == CH_FOLD || chain_phase(g.type) != 2) continue;
-            const int b = chain_in_phase(g.type, g.param) / K;
+            if (g.type == CH_FOLD) continue;
+            const int b = chain_in_phase(g.type, g.param) / K + (chain_phase(g.type) == 1 ? 0 : P->nb1);
             done[b] = std::max<int64_t>(done[b], g.tau0 + g.len);
         }
-        for (int b = 1; b < P->nb2; ++b) done[b] = std::max(done[b], done[b - 1]);
-        const int want = std::min(kPhase2Segments, P->nb2);
-        int64_t prev_t = P->split;
+        for (int b = 1; b < nbt; ++b) done[b] = std::max(done[b], done[b - 1]);
+        const int want = std::min(nn >= 256 ? kSegments : kSegmentsSmall, nbt);
+        int64_t prev_t = 0;
         int prev_c = 0;
         for (int k = 1; k <= want; ++k) {
-            const int c = k == want ? P->nb2 : (int)((int64_t)P->nb2 * k / want);
+            const int c = k == want ? nbt : (int)((int64_t)nbt * k / want);
             const int64_t t = k == want ? P->ticks : done[c - 1];
             if (c <= prev_c || t <= prev_t || (k < want && t >= P->ticks)) continue;
             P->bcut[P->nseg] = c;
@@ -212,7 +215,7 @@ std::unique_ptr<Plan> build_plan(int64_t m, int64_t n, int K0, int NW, int gen_t
             prev_c = c;
             prev_t = t;
         }
-        if (P->nseg == 0 || P->bcut[P->nseg - 1] != P->nb2 || P->tcut[P->nseg - 1] != P->ticks) P->nseg = 0;
+        if (P->nseg == 0 || P->bcut[P->nseg - 1] != nbt || P->tcut[P->nseg - 1] != P->ticks) P->nseg = 0;
     }
     return P;
 }

@@ -301,20 +301,21 @@ def test_split_switch_validates_its_argument():
 
 @pytest.mark.parametrize("m,n", [(2, 2), (3, 2), (8, 6), (17, 13), (65, 65), (300, 257), (1000, 999),
                                  (2048, 2048), (4096, 2048)])
-def test_phase2_segments_apply_only_generated_blocks(m, n):
-    """Segment k's application covers the phase-2 blocks below bcut[k]:
-    every rotation of those blocks must have been generated before tcut[k],
-    the tick segment k's generation stops at; the segments cover phase 2
-    exactly, in increasing ticks and blocks."""
+def test_segments_apply_only_generated_blocks(m, n):
+    """Segment k's application covers the applier blocks below bcut[k]
+    (phase-1 blocks, then phase-2 blocks): every rotation of those blocks must
+    have been generated before tcut[k], the tick segment k's generation stops
+    at; the segments cover the pass exactly, in increasing ticks and blocks."""
     side, idx, ph, tick = bdu.plan_rotations(m, n)
     tcut, bcut, blk = bdu.plan_segments(m, n)
     st = bdu.plan_stats(m, n)
     assert len(tcut) >= 1
-    nb1 = int(blk[ph == 1].max()) + 1
-    nb2_used = int(blk[ph == 2].max()) - nb1 + 1
-    assert tcut[-1] == st["ticks"] and bcut[-1] >= nb2_used
-    assert np.all(np.diff(tcut) > 0) and np.all(np.diff(bcut) > 0) and tcut[0] > st["split"]
-    p2 = ph == 2
+    assert tcut[-1] == st["ticks"] and bcut[-1] > blk.max()
+    assert np.all(np.diff(tcut) > 0) and np.all(np.diff(bcut) > 0)
+    rot = (ph == 1) | (ph == 2)
+    assert np.all(blk[rot] >= 0) and np.all(blk[~rot] == -1)
     for k in range(len(tcut)):
-        inside = p2 & (blk - nb1 < bcut[k])
+        inside = rot & (blk < bcut[k])
         assert np.all(tick[inside] < tcut[k]), k
+    # phase-1 blocks come before phase-2 blocks
+    assert blk[ph == 1].max() < blk[ph == 2].min()
