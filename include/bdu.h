@@ -169,9 +169,10 @@ int bdu_set_generation_in_lds(int allow);
  * for both.  With on = 2 (default) a single handle instead generates the
  * whole pass in segments (bdu_plan_segments), each applied while the next is
  * generated (the generator keeps the carried pairs of chains in flight
- * across a segment end); on = 1 splits only after phase 1.  A batch splits after
- * phase 1 (on >= 1) for each group of handles that all split, on a second
- * stream of the batch.  Same rotations in the same order, so results do not
+ * across a segment end); on = 1 splits only after phase 1.  A batch does the
+ * same on a second stream of the batch, for each group of handles (one
+ * applier tiling) whose plans have the same number of segments (else it
+ * splits after phase 1 when they all can).  Same rotations in the same order, so results do not
  * depend on it.  Applies to handles and batches created afterwards. */
 int bdu_set_split_pass(int on);
 

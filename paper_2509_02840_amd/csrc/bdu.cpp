@@ -340,6 +340,35 @@ hipError_t run_split_stages(HandleDev *const *hs, int count, bool any_spike, int
     return e;
 }
 
+// The stages of a pass in nseg segments (every listed handle's plan has
+// that many): segment k's application on sd once its generation is done,
+// the next segment's generation beside it; st waits for the application.
+hipError_t run_segment_stages(HandleDev *const *hs, int count, bool any_spike, int64_t lds_bytes, bool in_lds,
+                              int gen_threads, int max_panels, int k0, int nw, int rpl, Gate gate, int nseg,
+                              hipStream_t st, hipStream_t sd, const hipEvent_t *ev, hipEvent_t done)
+{
+    hipError_t e = hipSuccess;
+    Gate g0 = gate;
+    g0.part = 3;
+    if (any_spike) e = timed(ST_SPIKE, st, [&] { return launch_spike(hs, count, g0, st); });
+    for (int k = 0; k < nseg && e == hipSuccess; ++k) {
+        Gate gk = gate;
+        gk.part = 3 + k;
+        e = timed(ST_GEN, st, [&] { return launch_gen(hs, count, lds_bytes, in_lds, gen_threads, gk, st); });
+        if (e == hipSuccess) e = hipEventRecord(ev[k], st);
+    }
+    for (int k = 0; k < nseg && e == hipSuccess; ++k) {
+        Gate gk = gate;
+        gk.part = 3 + k;
+        e = hipStreamWaitEvent(sd, ev[k], 0);
+        if (e == hipSuccess)
+            e = timed(ST_APPLY, sd, [&] { return launch_apply(hs, count, max_panels, k0, nw, rpl, gk, sd); });
+    }
+    if (e == hipSuccess) e = hipEventRecord(done, sd);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, done, 0);
+    return e;
+}
+
 int tiles_of(const bdu_ctx *h) { return (int)((h->m + 63) / 64 + (h->n + 63) / 64); }
 int panels_of(const bdu_ctx *h)
 {
@@ -356,26 +385,8 @@ int pass_single(bdu_ctx *h, int pass, bool project)
     const int64_t lds = gen_lds_bytes(h->n, h->plan->N);
     const int L = h->plan->L, np = panels_of(h), k0 = h->plan->K0, nw = h->plan->NW;
     if (e == hipSuccess && h->side && h->plan->nseg > 0 && h->seg[0]) {
-        // the pass in segments; each segment's application on the side
-        // stream once its generation is done, the next segment's generation
-        // beside it
-        hipStream_t sd = h->side;
-        const int nseg = h->plan->nseg;
-        if (h->m > h->n)
-            e = timed(ST_SPIKE, st, [&] { return launch_spike(h->d_self, 1, Gate{nullptr, pass, 3}, st); });
-        for (int k = 0; k < nseg && e == hipSuccess; ++k) {
-            const Gate gk{nullptr, pass, 3 + k};
-            e = timed(ST_GEN, st, [&] { return launch_gen(h->d_self, 1, lds, h->lds_gen, L, gk, st); });
-            if (e == hipSuccess) e = hipEventRecord(h->seg[k], st);
-        }
-        for (int k = 0; k < nseg && e == hipSuccess; ++k) {
-            const Gate gk{nullptr, pass, 3 + k};
-            e = hipStreamWaitEvent(sd, h->seg[k], 0);
-            if (e == hipSuccess)
-                e = timed(ST_APPLY, sd, [&] { return launch_apply(h->d_self, 1, np, k0, nw, h->rpl, gk, sd); });
-        }
-        if (e == hipSuccess) e = hipEventRecord(h->sp3, sd);
-        if (e == hipSuccess) e = hipStreamWaitEvent(st, h->sp3, 0);
+        e = run_segment_stages(h->d_self, 1, h->m > h->n, lds, h->lds_gen, L, np, k0, nw, h->rpl,
+                               Gate{nullptr, pass, 0}, h->plan->nseg, st, h->side, h->seg, h->sp3);
     } else if (e == hipSuccess && h->side) {
         e = run_split_stages(h->d_self, 1, h->m > h->n, lds, h->lds_gen, L, np, k0, nw, h->rpl, Gate{nullptr, pass, 0},
                              st, h->side, h->sp1, h->sp2, h->sp3);
@@ -478,6 +489,7 @@ struct bdu_batch_ctx {
         int tiles, panels, off, cnt;
         int gen_threads;  // largest plan thread count of the group
         bool split;       // every member's pass splits after phase 1
+        int nseg;         // segments every member's plan has (0: members differ)
     };
     std::vector<Group> groups;  // handles of one applier tiling, contiguous in the arrays
     HandleDev **d_ptrs = nullptr;
@@ -487,6 +499,7 @@ struct bdu_batch_ctx {
     // split passes: phase 1 applied on `side` while phase 2 is generated
     hipStream_t side = nullptr;
     hipEvent_t sp1 = nullptr, sp2 = nullptr, sp3 = nullptr;
+    hipEvent_t seg[kMaxSeg] = {};
     bool use_graph = false;
     int64_t steps = 0;
     hipGraphExec_t exec = nullptr;
@@ -507,6 +520,8 @@ void batch_free(bdu_batch b)
     if (b->sp1) (void)hipEventDestroy(b->sp1);
     if (b->sp2) (void)hipEventDestroy(b->sp2);
     if (b->sp3) (void)hipEventDestroy(b->sp3);
+    for (int k = 0; k < kMaxSeg; ++k)
+        if (b->seg[k]) (void)hipEventDestroy(b->seg[k]);
     if (b->side) (void)hipStreamDestroy(b->side);
     delete b;
 }
@@ -544,7 +559,8 @@ int batch_build(const bdu_handle *hs, int count, int maxr, bool graph, bdu_batch
             if (x.k0 == h->plan->K0 && x.nw == h->plan->NW && x.rpl == h->rpl && x.in_lds == h->lds_gen) break;
         }
         if (g == b->groups.size()) {
-            b->groups.push_back({h->plan->K0, h->plan->NW, h->rpl, false, h->lds_gen, 0, 0, 0, 0, 0, 64, split_on()});
+            b->groups.push_back({h->plan->K0, h->plan->NW, h->rpl, false, h->lds_gen, 0, 0, 0, 0, 0, 64, split_on(),
+                                 segments_on() ? h->plan->nseg : 0});
             members.emplace_back();
         }
         auto &x = b->groups[g];
@@ -555,9 +571,14 @@ int batch_build(const bdu_handle *hs, int count, int maxr, bool graph, bdu_batch
         x.tiles = std::max(x.tiles, tiles_of(h));
         x.panels = std::max(x.panels, panels_of(h));
         x.split = x.split && h->plan->split > 0;
+        if (x.nseg != h->plan->nseg) x.nseg = 0;
     }
     bool any_split = false;
-    for (auto &x : b->groups) any_split |= x.split;
+    int max_seg = 0;
+    for (auto &x : b->groups) {
+        any_split |= x.split || x.nseg > 0;
+        max_seg = std::max(max_seg, x.nseg);
+    }
     std::vector<HandleDev *> flat;
     b->pos.assign(count, 0);
     for (size_t g = 0; g < b->groups.size(); ++g) {
@@ -578,6 +599,8 @@ int batch_build(const bdu_handle *hs, int count, int maxr, bool graph, bdu_batch
         if (e == hipSuccess) e = hipEventCreateWithFlags(&b->sp1, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&b->sp2, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&b->sp3, hipEventDisableTiming);
+        for (int k = 0; e == hipSuccess && k < max_seg; ++k)
+            e = hipEventCreateWithFlags(&b->seg[k], hipEventDisableTiming);
     }
     if (e == hipSuccess) e = prepare_kernels();
     if (e == hipSuccess) e = hipMemcpy(b->d_ptrs, flat.data(), sizeof(HandleDev *) * count, hipMemcpyHostToDevice);
@@ -600,7 +623,10 @@ hipError_t batch_launch(bdu_batch b)
             HandleDev **arr = b->d_ptrs + g.off;
             const Gate gate{b->d_ranks + g.off, p};
             hipError_t e = timed(ST_PROJECT, st, [&] { return launch_project(arr, g.cnt, g.tiles, gate, st); });
-            if (e == hipSuccess && g.split && b->side)
+            if (e == hipSuccess && g.nseg > 0 && b->side)
+                e = run_segment_stages(arr, g.cnt, g.spike, g.lds, g.in_lds, g.gen_threads, g.panels, g.k0, g.nw,
+                                       g.rpl, gate, g.nseg, st, b->side, b->seg, b->sp3);
+            else if (e == hipSuccess && g.split && b->side)
                 e = run_split_stages(arr, g.cnt, g.spike, g.lds, g.in_lds, g.gen_threads, g.panels, g.k0, g.nw,
                                      g.rpl, gate, st, b->side, b->sp1, b->sp2, b->sp3);
             else if (e == hipSuccess)
