@@ -35,17 +35,17 @@ sys.path.insert(0, ROOT)
 METRIC = "FP64 rank-1 updates/sec + p50/p99 latency, batched vs plain, n=2048"
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CUs x 128 FP64 flop/clk x 2.4 GHz
 
-# HBM bytes of one applier launch (the average over a pass's two launches,
-# phase 1 and phase 2), from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs
-# of this script (profiles/apply_staged_kernel_n2048_s64_traffic.md),
+# HBM bytes of one applier launch (the average over a pass's launches, one
+# per segment of the pass), from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
+# runs of this script (profiles/apply_staged_kernel_n2048_s64_traffic.md),
 # each scaled by what the counter reads for a plain 1 GiB device copy
 # (bench.py --copy-probe).  Valid only for the sources with this digest and
 # the workload named; otherwise the traffic is reported as null.
 TRAFFIC_SOURCES = ["paper_2509_02840_amd/csrc/kernels.hip", "paper_2509_02840_amd/csrc/primitives.h",
                    "paper_2509_02840_amd/csrc/schedule.h", "paper_2509_02840_amd/csrc/device.h",
                    "paper_2509_02840_amd/csrc/plan.cpp", "paper_2509_02840_amd/csrc/bdu.cpp"]
-MEASURED_TRAFFIC = {"sha256": "f6028185cdb29db63e879526b1814561e80c821f445f6517131899c4e3d5ba03",
-                    "n": 2048, "streams": 64, "tiling": (12, 7, 1), "bytes": 221993241630.1}
+MEASURED_TRAFFIC = {"sha256": "701182790ff21d51e4718920865059f6b6f71e2994c91ac3841582f91390f8e3",
+                    "n": 2048, "streams": 64, "tiling": (12, 7, 1), "bytes": 54770725441.0}
 
 
 def sources_digest() -> str:
