@@ -36,16 +36,18 @@ METRIC = "FP64 rank-1 updates/sec + p50/p99 latency, batched vs plain, n=2048"
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CUs x 128 FP64 flop/clk x 2.4 GHz
 
 # HBM bytes of one applier launch (the average over a pass's launches, one
-# per segment of the pass), from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
-# runs of this script (profiles/apply_staged_kernel_n2048_s64_traffic.md),
+# per segment of the pass) for the tilings the batched autotuner picks, from
+# rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of this script
+# (profiles/apply_staged_kernel_n2048_s64_traffic.md,
+# profiles/apply_staged_kernel_12_15_1_n2048_s64_traffic.md),
 # each scaled by what the counter reads for a plain 1 GiB device copy
 # (bench.py --copy-probe).  Valid only for the sources with this digest and
 # the workload named; otherwise the traffic is reported as null.
 TRAFFIC_SOURCES = ["paper_2509_02840_amd/csrc/kernels.hip", "paper_2509_02840_amd/csrc/primitives.h",
                    "paper_2509_02840_amd/csrc/schedule.h", "paper_2509_02840_amd/csrc/device.h",
                    "paper_2509_02840_amd/csrc/plan.cpp", "paper_2509_02840_amd/csrc/bdu.cpp"]
-MEASURED_TRAFFIC = {"sha256": "701182790ff21d51e4718920865059f6b6f71e2994c91ac3841582f91390f8e3",
-                    "n": 2048, "streams": 64, "tiling": (12, 7, 1), "bytes": 54770725441.0}
+MEASURED_TRAFFIC = {"sha256": "701182790ff21d51e4718920865059f6b6f71e2994c91ac3841582f91390f8e3", "n": 2048, "streams": 64,
+                    "bytes": {(12, 7, 1): 54770725441.0, (12, 15, 1): 27058865981.3}}
 
 
 def sources_digest() -> str:
@@ -59,9 +61,9 @@ def sources_digest() -> str:
 
 def measured_traffic(n: int, streams: int, tiling) -> float | None:
     t = MEASURED_TRAFFIC
-    if t["bytes"] is None or (n, streams, tuple(tiling)) != (t["n"], t["streams"], t["tiling"]):
+    if (n, streams) != (t["n"], t["streams"]) or tuple(tiling) not in t["bytes"]:
         return None
-    return t["bytes"] if sources_digest() == t["sha256"] else None
+    return t["bytes"][tuple(tiling)] if sources_digest() == t["sha256"] else None
 
 
 class StreamFactory:
