@@ -156,7 +156,7 @@ int bdu_autotune(int64_t m, int64_t n, int streams, int64_t *out);
 
 /* Where the rotation generator keeps the working band (offsets -2..3) and
  * u, v, about 64 bytes per row: allow = 1 (default) in LDS when they fit
- * (n up to about 2550), else in device memory; allow = 0 always in device
+ * (n up to 2449 for square shapes), else in device memory; allow = 0 always in device
  * memory.  Applies to handles created afterwards; results do not depend on
  * it. */
 int bdu_set_generation_in_lds(int allow);
