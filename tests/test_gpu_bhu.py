@@ -40,8 +40,8 @@ def _bd(d, e, m):
     return B
 
 
-@pytest.mark.parametrize("m,n", [(2, 2), (3, 2), (3, 3), (5, 5), (14, 12), (65, 64), (66, 64), (130, 97),
-                                 (200, 200), (257, 191)])
+@pytest.mark.parametrize("m,n", [(2, 2), (3, 2), (5, 2), (3, 3), (5, 5), (14, 12), (65, 64), (66, 64), (130, 97),
+                                 (200, 200), (257, 191), (300, 17), (500, 3)])
 def test_householder_update_matches_oracle(bdu, oracle, m, n):
     f = W.factorization(m, n, 500 + m)
     rng = np.random.default_rng(501 + n)

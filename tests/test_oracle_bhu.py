@@ -91,7 +91,8 @@ def _dense_bhu(A):
     return np.diag(A)[:n].copy(), np.diag(A, 1)[:n - 1].copy(), Y, Wr, A
 
 
-@pytest.mark.parametrize("m,n", [(2, 2), (3, 2), (3, 3), (6, 6), (9, 6), (20, 20), (41, 30), (60, 60)])
+@pytest.mark.parametrize("m,n", [(2, 2), (3, 2), (5, 2), (3, 3), (6, 6), (9, 6), (20, 20), (41, 30), (60, 60),
+                                 (80, 7), (120, 3)])
 def test_algorithm1_matches_dense_householder(m, n):
     rng = np.random.default_rng(200 + m + n)
     d, e = rng.standard_normal(n), rng.standard_normal(n - 1)
