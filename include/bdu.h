@@ -161,7 +161,7 @@ int bdu_autotune(int64_t m, int64_t n, int streams, int64_t *out);
  * it. */
 int bdu_set_generation_in_lds(int allow);
 
-/* Split passes: with on >= 1, a handle whose schedule ends phase 1
+/* Split passes: with on >= 1, a handle with n >= 32 whose schedule ends phase 1
  * (Section 3.4: the upper-left chase, with the fold of the remaining rank-1
  * term) at a tick where no rotation chain is in flight generates each pass
  * in parts and applies the phase-1 rotations to Q and P on a stream of its

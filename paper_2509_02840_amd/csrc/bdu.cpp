@@ -41,6 +41,7 @@ struct Tuned {
 std::map<std::pair<int64_t, int64_t>, Tuned> g_tuned;
 bool g_gen_lds = true;  // generation keeps its band in LDS when it fits
 bool g_check_finite = false;  // reject NaN / Inf inputs (one extra pass and a sync per call)
+constexpr int64_t kSplitMinN = 32;  // smallest n whose single-handle passes split
 bool g_split = true;          // single-handle passes apply phase 1 while phase 2 is generated
 bool g_segments = true;       // ... and phase 2 in segments, each applied while the next is generated
 
@@ -825,7 +826,9 @@ int create_impl(int64_t m, int64_t n, const double *Q, const double *d, const do
     HIPCHK(hp, hipMemcpyAsync(h->d_self, &self, sizeof(self), hipMemcpyHostToDevice, hp->stream));
     HIPCHK(hp, hipStreamSynchronize(hp->stream));
     bool ok = hipEventCreateWithFlags(&hp->ev, hipEventDisableTiming) == hipSuccess;
-    if (ok && plan->split > 0 && split_on()) {
+    // below n = 32 a pass is a few hundred microseconds at most and the
+    // second stream's event waits cost about what the overlap saves
+    if (ok && plan->split > 0 && split_on() && n >= kSplitMinN) {
         ok = hipStreamCreateWithFlags(&hp->side, hipStreamNonBlocking) == hipSuccess &&
              hipEventCreateWithFlags(&hp->sp1, hipEventDisableTiming) == hipSuccess &&
              hipEventCreateWithFlags(&hp->sp2, hipEventDisableTiming) == hipSuccess &&
