@@ -187,3 +187,42 @@ def test_autotune_records_the_tiling_auto_handles_use(bdu, oracle):
         h2.close()
     finally:
         bdu.set_tiling(*saved)
+
+
+@pytest.mark.parametrize("tk", [(12, 7, 1), (12, 15, 1)])
+def test_bench_launch_configuration_full_size(bdu, oracle, tk):
+    """The benchmark's batched configuration: 64 streams at m = n = 2048 in
+    one batch with the tilings its autotuner picks, passes in segments, the
+    step replayed from the captured graph (an empty step first makes the
+    real one the first replay).  Three streams are checked against the
+    oracle: d, e and 16 sampled rows of Q and P, bit for bit."""
+    n, S = 2048, 64
+    f = W.factorization(n, n, 700)
+    rng = np.random.default_rng(701)
+    bs = [rng.standard_normal(n) for _ in range(S)]
+    cs = [rng.standard_normal(n) for _ in range(S)]
+    saved = bdu.get_tiling()
+    bdu.set_tiling(*tk)
+    try:
+        hs = [bdu.Handle(f.Q, f.d, f.e, f.P) for _ in range(S)]
+    finally:
+        bdu.set_tiling(*saved)
+    batch = bdu.Batch(hs, max_rank=1)
+    batch.update([None] * S, [None] * S, ranks=[0] * S)
+    batch.update(bs, cs)
+    batch.sync()
+    assert batch.info()["graph"] == 1
+    for s in (0, S // 2, S - 1):
+        Q1, d1, e1, P1 = hs[s].read()
+        u = oracle.project(f.Q, bs[s])
+        v = oracle.project(f.P, cs[s])
+        qr = np.sort(rng.choice(n, 16, replace=False))
+        pr = np.sort(rng.choice(n, 16, replace=False))
+        Qr, d, e, Pr = oracle.bgu_pass_rows(n, n, f.Q[qr], f.d, f.e, f.P[pr], u, v)
+        _eq(f"{tk} stream {s} d", d1, d)
+        _eq(f"{tk} stream {s} e", e1, e)
+        _eq(f"{tk} stream {s} Q rows", Q1[qr], Qr)
+        _eq(f"{tk} stream {s} P rows", P1[pr], Pr)
+    batch.close()
+    for h in hs:
+        h.close()
