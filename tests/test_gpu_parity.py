@@ -355,3 +355,32 @@ def test_nonfinite_inputs_are_rejected(bdu, oracle):
         h2.close()
     finally:
         bdu.set_finite_check(False)
+
+
+def test_plain_bench_configuration_full_size(bdu, oracle):
+    """The benchmark's plain leg: one stream at m = n = 2048 with tiling
+    (12, 15, 1), the pass in eight segments; d, e and 32 sampled rows of Q
+    and P against the oracle, bit for bit."""
+    n = 2048
+    f = W.factorization(n, n, 710)
+    rng = np.random.default_rng(711)
+    b, c = rng.standard_normal(n), rng.standard_normal(n)
+    saved = bdu.get_tiling()
+    bdu.set_tiling(12, 15, 1)
+    try:
+        h = bdu.Handle(f.Q, f.d, f.e, f.P)
+    finally:
+        bdu.set_tiling(*saved)
+    assert len(bdu.plan_segments(n, n)[0]) == 8
+    h.update(b.reshape(n, 1), c.reshape(n, 1))
+    Q1, d1, e1, P1 = h.read()
+    h.close()
+    u = oracle.project(f.Q, b)
+    v = oracle.project(f.P, c)
+    qr = np.sort(rng.choice(n, 32, replace=False))
+    pr = np.sort(rng.choice(n, 32, replace=False))
+    Qr, d, e, Pr = oracle.bgu_pass_rows(n, n, f.Q[qr], f.d, f.e, f.P[pr], u, v)
+    _eq("d", d1, d)
+    _eq("e", e1, e)
+    _eq("Q rows", Q1[qr], Qr)
+    _eq("P rows", P1[pr], Pr)
