@@ -1,10 +1,10 @@
 """Generation with the working band in device memory (large n).
 
 The band (offsets -2..3) and u, v of the rotation generator live in LDS up
-to n of about 2550 and in device memory beyond.  The device-memory variant
+to n = 2449 (square) and in device memory beyond.  The device-memory variant
 is checked bit-exactly on small shapes (forced), then on shapes that need it
-(n = 3000 and 4096) against the oracle on sampled rows of Q and P and on all
-of d and e.
+(n = 3000, 4096 and the largest served size, 8192) against the oracle on
+sampled rows of Q and P and on all of d and e.
 """
 import numpy as np
 import pytest
@@ -90,3 +90,34 @@ def test_unsplit_pass_bit_exact(bdu, oracle, m, n, r, in_lds, mode):
     for nm, x, y in zip("QdeP", h.read(), (ref.Q, ref.d, ref.e, ref.P)):
         _eq(nm, x, y)
     h.close()
+
+
+def test_largest_served_size(bdu, oracle):
+    """n = 8192, the largest size of the serving workload: one update with
+    the band in device memory and the pass in segments; d, e and 16 sampled
+    rows of Q and P bit for bit.  The factors are single Householder
+    reflections (orthogonal and cheap to form at this size)."""
+    n = 8192
+    rng = np.random.default_rng(720)
+    q = rng.standard_normal(n)
+    q /= np.linalg.norm(q)
+    p = rng.standard_normal(n)
+    p /= np.linalg.norm(p)
+    Q = np.asfortranarray(np.eye(n) - 2.0 * np.outer(q, q))
+    P = np.asfortranarray(np.eye(n) - 2.0 * np.outer(p, p))
+    d = rng.uniform(1.0, 10.0, n)
+    e = rng.uniform(0.0, 1.0, n - 1)
+    b, c = rng.standard_normal(n), rng.standard_normal(n)
+    h = bdu.Handle(Q, d, e, P)
+    h.update(b.reshape(n, 1), c.reshape(n, 1))
+    Q1, d1, e1, P1 = h.read()
+    h.close()
+    u = oracle.project(Q, b)
+    v = oracle.project(P, c)
+    qr = np.sort(rng.choice(n, 16, replace=False))
+    pr = np.sort(rng.choice(n, 16, replace=False))
+    Qr, dr, er, Pr = oracle.bgu_pass_rows(n, n, Q[qr], d, e, P[pr], u, v)
+    _eq("d", d1, dr)
+    _eq("e", e1, er)
+    _eq("Q rows", Q1[qr], Qr)
+    _eq("P rows", P1[pr], Pr)
