@@ -171,8 +171,8 @@ int bdu_set_generation_in_lds(int allow);
  * generated (the generator keeps the carried pairs of chains in flight
  * across a segment end); on = 1 splits only after phase 1.  A batch does the
  * same on a second stream of the batch, for each group of handles (one
- * applier tiling) whose plans have the same number of segments (else it
- * splits after phase 1 when they all can).  Same rotations in the same order, so results do not
+ * applier tiling), running as many segments as the group's largest plan
+ * has (a handle with fewer has nothing to do in the extra ones).  Same rotations in the same order, so results do not
  * depend on it.  Applies to handles and batches created afterwards. */
 int bdu_set_split_pass(int on);
 

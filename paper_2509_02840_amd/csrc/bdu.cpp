@@ -490,7 +490,7 @@ struct bdu_batch_ctx {
         int tiles, panels, off, cnt;
         int gen_threads;  // largest plan thread count of the group
         bool split;       // every member's pass splits after phase 1
-        int nseg;         // segments every member's plan has (0: members differ)
+        int nseg;         // segments of the group: the largest member's count (0: no segments)
     };
     std::vector<Group> groups;  // handles of one applier tiling, contiguous in the arrays
     HandleDev **d_ptrs = nullptr;
@@ -572,7 +572,9 @@ int batch_build(const bdu_handle *hs, int count, int maxr, bool graph, bdu_batch
         x.tiles = std::max(x.tiles, tiles_of(h));
         x.panels = std::max(x.panels, panels_of(h));
         x.split = x.split && h->plan->split > 0;
-        if (x.nseg != h->plan->nseg) x.nseg = 0;
+        // the group runs as many segments as its largest plan has (the
+        // kernels skip a handle's segments past its own count)
+        if (x.nseg > 0) x.nseg = segments_on() && h->plan->nseg > 0 ? std::max(x.nseg, h->plan->nseg) : 0;
     }
     bool any_split = false;
     int max_seg = 0;

@@ -54,6 +54,10 @@ __host__ __device__ inline bool part_blocks(const H *h, int part, int *bbeg, int
     const int nb1 = h->nb1, nb2 = h->nb2;
     if (part >= 3) {
         const int k = part - 3;
+        if (k >= h->nseg) {  // a batch runs as many segments as its largest plan has
+            *bbeg = *bend = 0;
+            return false;
+        }
         *bbeg = k == 0 ? 0 : h->bcut[k - 1];
         *bend = h->bcut[k];
         return k == 0;

@@ -156,6 +156,9 @@ __global__ __launch_bounds__(kGenThreads) void gen_kernel(HandleDev *const *hs, 
     extern __shared__ double smem[];
     if (gate.ranks && gate.pass >= gate.ranks[blockIdx.x]) return;
     const CONSTANT HandleDev *h = kptr(hs[blockIdx.x]);
+    // a batch runs as many segments as its largest plan has; this
+    // handle's pass may have ended already
+    if (gate.part >= 3 && gate.part - 3 >= h->nseg) return;
     const int n = h->n, N = h->N;
     double *S = IN_LDS ? smem : h->band;
     // band pointers of the tick loop: LDS (32-bit) or global
