@@ -380,11 +380,20 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(K0 * R 
 // The compute wavefronts run the register-window sweep above with LDS
 // traffic only: wavefront w takes its new columns from ring w and hands its
 // finished columns to ring w + 1; the coefficients of each front come from a
-// coefficient ring in LDS (one broadcast read per rotation).  The memory
-// wavefront feeds ring 0 and the coefficient ring from global memory, DL
-// fronts ahead, and writes the columns arriving in ring NW back to Q or P.
-// Compute wavefronts therefore issue no global or scalar memory operation in
-// their loop, and none of their waits depends on a global-memory latency.
+// coefficient ring in LDS.  The memory wavefront feeds ring 0 and the
+// coefficient ring from global memory, DL fronts ahead, and writes the
+// columns arriving in ring NW back to Q or P.  Compute wavefronts therefore
+// issue no global or scalar memory operation in their loop, and none of their
+// waits depends on a global-memory latency.
+//
+// Coefficient delivery.  A (c, s) pair is uniform across the rows.  Read
+// with one broadcast LDS load per rotation it would move 1 KB through the
+// LDS data path (64 lanes x 16 bytes) for 16 bytes of data, which at one
+// rotation per 16 FP64 lane-cycles is more than the LDS can deliver.  So a
+// compute wavefront reads the pairs of its next front once, lane l holding
+// pair l mod 16 (each row of 16 lanes holds the same copy), and broadcasts
+// pair p to all lanes with a 64-bit DPP move (row_newbcast:p), which costs
+// one VALU instruction per 8 bytes and no LDS bandwidth.
 template <int K0, int NW, int R>
 struct Staged {
     static constexpr int U = K0 + 3, WSZ = 3 * U, S = U, K = K0 * NW;
@@ -394,15 +403,59 @@ struct Staged {
     static constexpr int LDS_DOUBLES = COEF + 3 * K * 2;      // 3 fronts of K pairs
     static constexpr int DL = U / 3;                          // memory prefetch depth, U % DL == 0
     static constexpr int NCI = (K + 63) / 64;                 // coefficient loads per front
+    static constexpr int NCR = (K0 + 15) / 16;                // coefficient registers per compute lane
     static_assert(U % 3 == 0 && U % DL == 0 && (3 * U) % RC == 0, "static ring slots");
 };
+
+// Value of v in lane 16 * (lane / 16) + P (row_newbcast:P, a 64-bit DPP move).
+template <int P>
+__device__ __forceinline__ double row_bcast(double v)
+{
+    static_assert(P >= 0 && P < 16, "row lane");
+    long x = __builtin_bit_cast(long, v);
+    long y = __builtin_amdgcn_mov_dpp(x, 0x150 + P, 0xf, 0xf, true);
+    return __builtin_bit_cast(double, y);
+}
+
+// Pairs [16 j, 16 j + 16) of a compute wavefront's K0 pairs of one front,
+// lane l holding pair 16 j + (l mod 16) (clamped to the last pair).
+template <int K0>
+__device__ __forceinline__ double2 coef_lane(const double2 *front, int j, int lane)
+{
+    const int q = 16 * j + (lane & 15);
+    return front[q < K0 ? q : K0 - 1];
+}
+
+template <int P, int K0, int NCR>
+__device__ __forceinline__ void coef_bcast(const double2 (&cv)[NCR], double &c, double &s)
+{
+    c = row_bcast<P % 16>(cv[P / 16].x);
+    s = row_bcast<P % 16>(cv[P / 16].y);
+}
+
+template <int K0, int NCR, int R, int MODE, int K, int WSZ, int P = 0>
+__device__ __forceinline__ void front_rotations(const double2 (&cv)[NCR], double (&buf)[R][WSZ], int phi)
+{
+    if constexpr (P < K0) {
+        constexpr FrontOrder ord = front_order(MODE, K, K0);
+        constexpr bool DESC = MODE < 2;
+        constexpr int t = ord.t[P];
+        const int l0 = 3 * (phi - t) + rho_of(MODE, K, t);
+        const int sx = pmod(l0 + (DESC ? 1 : 0), WSZ);
+        const int sy = pmod(l0 + (DESC ? 0 : 1), WSZ);
+        double c, sn;
+        coef_bcast<P, K0, NCR>(cv, c, sn);
+#pragma unroll
+        for (int r = 0; r < R; ++r) rot(c, sn, buf[r][sx], buf[r][sy]);
+        front_rotations<K0, NCR, R, MODE, K, WSZ, P + 1>(cv, buf, phi);
+    }
+}
 
 template <int K0, int NW, int R, int MODE>
 __device__ __forceinline__ void sweep_compute(const BlockDesc bd, double *lds, int w, int lane)
 {
     using T = Staged<K0, NW, R>;
-    constexpr int U = T::U, WSZ = T::WSZ, S = T::S, K = T::K, RC = T::RC;
-    constexpr bool DESC = MODE < 2;
+    constexpr int U = T::U, WSZ = T::WSZ, S = T::S, K = T::K, RC = T::RC, NCR = T::NCR;
     const int lmax = bd.lmax;
     if (lmax < 0) return;
     const int nfront = bd.nfront;
@@ -415,7 +468,6 @@ __device__ __forceinline__ void sweep_compute(const BlockDesc bd, double *lds, i
     const double *rin = lds + w * T::RING + lane;
     double *rout = lds + (w + 1) * T::RING + lane;
     const double2 *coef = (const double2 *)(lds + T::COEF) + w * K0;
-    constexpr FrontOrder ord = front_order(MODE, K, K0);
     const int flush_end = lam_hi / 3 + K0 - 1;
     const int nchunk = nfront / U;
     int live_end = w + (flush_end + U) / U;
@@ -425,6 +477,12 @@ __device__ __forceinline__ void sweep_compute(const BlockDesc bd, double *lds, i
     };
     __syncthreads();  // the memory wavefront's prologue is in LDS
     idle(w);
+    // front F's pairs sit in slot F mod 3 of the coefficient ring (the
+    // memory wavefront writes them during front F - 2); the first live
+    // front w S is a multiple of 3
+    double2 cv[NCR];
+#pragma unroll
+    for (int j = 0; j < NCR; ++j) cv[j] = coef_lane<K0>(coef, j, lane);
     for (int F0 = w * S; F0 < live_end * U; F0 += U) {
 #pragma unroll
         for (int phi = 0; phi < U; ++phi) {
@@ -444,18 +502,16 @@ __device__ __forceinline__ void sweep_compute(const BlockDesc bd, double *lds, i
 #pragma unroll
                 for (int r = 0; r < R; ++r)
                     buf[r][pmod(3 * phi + k, WSZ)] = rin[(pmod(3 * phi + k, RC) * R + r) * 64];
-            // front F's coefficients sit in slot F mod 3 (F0 is a multiple of 3)
-            const double2 *cf = coef + (phi % 3) * K;
+            // the next front's pairs, read a front early (written during
+            // front F - 1, overwritten during front F + 2)
+            double2 cn[NCR];
 #pragma unroll
-            for (int p = 0; p < K0; ++p) {
-                const int t = ord.t[p];
-                const int l0 = 3 * (phi - t) + rho_of(MODE, K, t);
-                const int sx = pmod(l0 + (DESC ? 1 : 0), WSZ);
-                const int sy = pmod(l0 + (DESC ? 0 : 1), WSZ);
-                const double2 cv = cf[p];
+            for (int j = 0; j < NCR; ++j) cn[j] = coef_lane<K0>(coef + ((phi + 1) % 3) * K, j, lane);
+            // this wavefront's K0 rotations at front F, in front_order (their
+            // coefficients are stored in that order)
+            front_rotations<K0, NCR, R, MODE, K, WSZ>(cv, buf, phi);
 #pragma unroll
-                for (int r = 0; r < R; ++r) rot(cv.x, cv.y, buf[r][sx], buf[r][sy]);
-            }
+            for (int j = 0; j < NCR; ++j) cv[j] = cn[j];
 #pragma unroll
             for (int k = 0; k < 3; ++k)
 #pragma unroll
@@ -497,7 +553,8 @@ __device__ __forceinline__ void sweep_memory(GLOBAL double *__restrict__ X, int 
     };
     // FIFO entry for front Fl (written to LDS during front Fl): the columns
     // 3 Fl + 7 .. 3 Fl + 9 that wavefront 0 reads at front Fl + 1 (for its
-    // front Fl + 2), and the coefficients of front Fl + 1.
+    // front Fl + 2), and the coefficients of front Fl + 2 (the compute
+    // wavefronts read them during front Fl + 1).
     double colf[DL][3][R];
     double cof[DL][NCI][2];
     auto load_entry = [&](int slot, int Fl) {
@@ -507,7 +564,7 @@ __device__ __forceinline__ void sweep_memory(GLOBAL double *__restrict__ X, int 
 #pragma unroll
             for (int r = 0; r < R; ++r) colf[slot][k][r] = cp[row0 + 64 * r];
         }
-        int Fc = Fl + 1 < nfront ? Fl + 1 : nfront - 1;
+        int Fc = Fl + 2 < nfront ? Fl + 2 : nfront - 1;
         const GLOBAL double *cp = cg + 2 * (int64_t)Fc * K;
 #pragma unroll
         for (int i = 0; i < NCI; ++i) {
@@ -516,7 +573,8 @@ __device__ __forceinline__ void sweep_memory(GLOBAL double *__restrict__ X, int 
             cof[slot][i][1] = cp[2 * q + 1];
         }
     };
-    // prologue: columns 0..6 and front 0's coefficients, then the FIFO
+    // prologue: columns 0..6 and the coefficients of fronts 0 and 1 (slots
+    // 0 and 1), then the FIFO
     {
 #pragma unroll
         for (int k = 0; k <= 6; ++k) {
@@ -525,11 +583,16 @@ __device__ __forceinline__ void sweep_memory(GLOBAL double *__restrict__ X, int 
             for (int r = 0; r < R; ++r) rw[(k * R + r) * 64] = cp[row0 + 64 * r];
         }
 #pragma unroll
-        for (int i = 0; i < NCI; ++i)
-            if (lane + 64 * i < K) {
-                coef[2 * (lane + 64 * i)] = cg[2 * (lane + 64 * i)];
-                coef[2 * (lane + 64 * i) + 1] = cg[2 * (lane + 64 * i) + 1];
-            }
+        for (int f = 0; f < 2; ++f) {
+            const int Fc = f < nfront ? f : nfront - 1;
+#pragma unroll
+            for (int i = 0; i < NCI; ++i)
+                if (lane + 64 * i < K) {
+                    const int q = f * K + lane + 64 * i;
+                    coef[2 * q] = cg[2 * ((int64_t)Fc * K + lane + 64 * i)];
+                    coef[2 * q + 1] = cg[2 * ((int64_t)Fc * K + lane + 64 * i) + 1];
+                }
+        }
     }
 #pragma unroll
     for (int j = 0; j < DL; ++j) load_entry(j, j);
@@ -539,7 +602,7 @@ __device__ __forceinline__ void sweep_memory(GLOBAL double *__restrict__ X, int 
         for (int phi = 0; phi < U; ++phi) {
             const int F = F0 + phi;
             const int slot = phi % DL;
-            // columns wavefront 0 reads at front F + 1, coefficients of front F + 1
+            // columns wavefront 0 reads at front F + 1, coefficients of front F + 2
 #pragma unroll
             for (int k = 0; k < 3; ++k)
 #pragma unroll
@@ -547,7 +610,7 @@ __device__ __forceinline__ void sweep_memory(GLOBAL double *__restrict__ X, int 
 #pragma unroll
             for (int i = 0; i < NCI; ++i)
                 if (lane + 64 * i < K) {
-                    double *d = coef + 2 * (((phi + 1) % 3) * K + lane + 64 * i);
+                    double *d = coef + 2 * (((phi + 2) % 3) * K + lane + 64 * i);
                     d[0] = cof[slot][i][0];
                     d[1] = cof[slot][i][1];
                 }
@@ -568,7 +631,7 @@ __device__ __forceinline__ void sweep_memory(GLOBAL double *__restrict__ X, int 
 }
 
 template <int K0, int NW, int R>
-__global__ __launch_bounds__(64 * (NW + 1)) __attribute__((amdgpu_waves_per_eu(R == 2 ? 2 : (K0 > 12 ? 3 : 4))))
+__global__ __launch_bounds__(64 * (NW + 1)) __attribute__((amdgpu_waves_per_eu(R == 2 || K0 > 12 ? 2 : 4)))
 void apply_staged_kernel(HandleDev *const *hs, Gate gate)
 {
     using T = Staged<K0, NW, R>;
