@@ -306,36 +306,52 @@ int bdu_update_householder(bdu_handle h, const double *b, const double *c);
 
 /* A thin rank-r factorization A = U B V^T (U m x r and V n x r with
  * orthonormal columns, B upper bidiagonal r x r) tracked under rank-1
- * updates A + b c^T, each followed by truncation back to rank r. */
+ * updates A + b c^T, kept at rank r. */
 typedef struct bdu_track_ctx *bdu_track;
 
 /* U (m x r), V (n x r): column-major, leading dimension m (n); d r entries,
  * e r-1 (may be NULL when r = 1).  Host or device pointers; the library
- * keeps device copies.  Requires 1 <= r, r + 1 <= m, r + 1 <= n.
+ * keeps device copies.  Requires 1 <= r <= m, r <= n.
  * BDU_EINVAL for bad sizes or NULL inputs, BDU_ENOMEM, BDU_EDEVICE;
  * BDU_ENONFINITE with the input check on. */
 int bdu_track_create(int64_t m, int64_t n, int64_t r, const double *U, const double *d,
                      const double *e, const double *V, bdu_track *out);
 
-/* One tracking update with b (m) and c (n), host or device:
- *   b_hat = U^T b and delta^2 = sum_i b_perp_i^2 are chunked row sums
- *   (chunks of 256 rows: a sequential fma from 0 inside a chunk, rows
- *   ascending; the chunk partials added in ascending order from 0),
- *   b_perp_i = b_i - sum_j U(i,j) b_hat_j (fma, j ascending); the same for
- *   c, V and gamma (eq. (defup));
- *   one BGU pass (bdu_update_projected) on the (r+1) x (r+1) middle matrix
- *   [B 0; 0 0] + [b_hat; delta][c_hat; gamma]^T from identity factors
- *   (eq. (equivlrup)), giving Q2 Bbar P2^T;
- *   removal of the row and column k of Bbar with the smallest column norm
- *   (d_k^2 + e_{k-1}^2 as fma(d_k, d_k, e_{k-1} e_{k-1}); ties: the highest
- *   k; the superdiagonal entry joining k-1 and k+1 becomes 0);
- *   U <- [U, b_perp/delta] Q2(:, kept), V <- [V, c_perp/gamma] P2(:, kept),
- *   each entry a sequential fma over the r+1 terms in column order
- *   (eq. (bdlrup)).
- * BDU_ESPAN, changing nothing, when delta or gamma is 0 (b or c lies in the
- * span of U or V; the paper then does not augment that side, which this
- * mode does not implement).  Inputs are consumed before returning; the work
- * is queued on the tracker's stream. */
+/* One tracking update with b (m) and c (n), host or device.
+ * Complements (eq. (defup)): b_hat = U^T b, b_perp = b - U b_hat; row sums
+ *   run in chunks of 256 rows (a sequential fma from 0 inside a chunk, rows
+ *   ascending, the chunk partials added in ascending order from 0) and
+ *   (U b_hat)_i = sum_j U(i,j) b_hat_j as fma, j ascending.  With s0 = b^T b
+ *   and s1 = b_perp^T b_perp: if 2 s1 < s0 a second pass projects b_perp
+ *   again (b_hat += U^T b_perp, b_perp -= U (U^T b_perp), s2 its squared
+ *   norm).  delta = sqrt(s1) after one pass, sqrt(s2) after two if
+ *   2 s2 >= s1, else 0: b lies in span(U) to working precision (the "twice
+ *   is enough" test of Kahan and Parlett).  delta is also 0 when its square
+ *   would be at most tau^2 s0, tau = m 2^-53 (the worst-case rounding error
+ *   of the projection sums).  The same for c, V (tau = n 2^-53) and gamma.
+ * A side with a positive norm is augmented by its unit complement (eq.
+ *   (qrlr)); the middle matrix (eq. (equivlrup)) is
+ *     both sides:  [B 0; 0 0] + [b_hat; delta][c_hat; gamma]^T, (r+1)^2;
+ *     left only:   [B; 0] + [b_hat; delta] c_hat^T, (r+1) x r;
+ *     right only:  [B 0] + b_hat [c_hat; gamma]^T, run as its transpose with
+ *                  rows and columns reversed (upper bidiagonal plus rank 1,
+ *                  (r+1) x r);
+ *     neither:     B + b_hat c_hat^T, r x r;
+ *   one BGU pass (bdu_update_projected) from identity factors gives
+ *   Q2 Bbar P2^T.
+ * Both sides augmented: the row and column k of Bbar with the smallest
+ *   column norm are removed (d_k^2 + e_{k-1}^2 as fma(d_k, d_k, e_{k-1}
+ *   e_{k-1}); ties: the highest k; the superdiagonal entry joining k-1 and
+ *   k+1 becomes 0).  Otherwise the result is exactly rank r and nothing is
+ *   removed (the paper's unaugmented case after eq. (bdlrup)).
+ * U <- [U, b_perp/delta] Q2(:, kept), V <- [V, c_perp/gamma] P2(:, kept),
+ *   each entry a sequential fma over U's (V's) columns in order, the
+ *   appended column last and absent on an unaugmented side (eq. (bdlrup));
+ *   in the reversed case U <- U J P2 J and V <- [V, c_perp/gamma] diag(J, 1)
+ *   Q2(:, 1:r) J, J the reversal of r entries, and d, e are reversed back.
+ * BDU_ESPAN, changing nothing, when r = 1 and a side is not augmented (a
+ * 2 x 1 or 1 x 1 middle matrix has no BGU pass).  Inputs are consumed
+ * before returning; the work is queued on the tracker's stream. */
 int bdu_track_update(bdu_track t, const double *b, const double *c);
 
 /* Wait for the tracker's queued work. */
@@ -344,9 +360,18 @@ int bdu_track_sync(bdu_track t);
 /* Copy the tracked factors out (any pointer may be NULL; host or device). */
 int bdu_track_read(bdu_track t, double *U, double *d, double *e, double *V);
 
-/* delta, gamma and the removed index (0-based, of the r+1 columns) of the
- * last successful update; BDU_EINVAL before the first one. */
+/* delta, gamma and the removed index (0-based, of the r+1 columns; -1 when
+ * a side was not augmented) of the last successful update; BDU_EINVAL
+ * before the first one. */
 int bdu_track_last(bdu_track t, double *delta, double *gamma, int64_t *dropped);
+
+/* The last successful update's projections b_hat, c_hat (r each) and unit
+ * complements b_perp/delta (m) and c_perp/gamma (n; unspecified on a side
+ * that was not augmented).  Any pointer may be NULL; host or device.
+ * BDU_EINVAL before the first update.  Lets a caller check the update
+ * from its inputs (the rest of the update depends only on these, delta
+ * and gamma). */
+int bdu_track_last_projection(bdu_track t, double *bh, double *ch, double *qb, double *qc);
 
 int bdu_track_destroy(bdu_track t);
 

@@ -47,7 +47,9 @@ enum {
     MUT_PHASE2_SKIP_2B = 7, /* phase 2 skips the second-superdiagonal elimination */
     MUT_TRACK_RESID = 8,    /* tracking: b_perp = b + Q1 b_hat */
     MUT_TRACK_NO_DELTA = 9, /* tracking: the middle update vector ends in 0, not delta */
-    MUT_TRACK_KEEP = 10     /* tracking: drops the column of largest norm */
+    MUT_TRACK_KEEP = 10,    /* tracking: drops the column of largest norm */
+    MUT_TRACK_ONE_PASS = 11,/* tracking: never a second orthogonalization pass */
+    MUT_TRACK_FLIP_E = 12   /* tracking, right side only augmented: e not reversed */
 };
 static int g_mut = MUT_NONE;
 void orc_set_mutation(int which) { g_mut = which; }
@@ -446,43 +448,80 @@ int orc_bgu_update(int64_t m, int64_t n, double *Q, int64_t ldq, double *d,
 
 /* ---- subspace tracking: Section 4, eqs. (lrup)-(bdlrup) ----------------- */
 
-/* Sums over the rows of a tracked basis run in chunks of ORC_TRACK_CHUNK
- * rows: inside a chunk a sequential fma from 0, rows ascending; the chunk
- * partials then added in ascending order from 0. */
-static double chunk_dot(int64_t rows, const double *a, const double *b)
+/* a^T b over rows entries: a sequential fma from 0, rows ascending. */
+static double plain_dot(int64_t rows, const double *a, const double *b)
 {
-    double total = 0.0;
-    for (int64_t i0 = 0; i0 < rows; i0 += ORC_TRACK_CHUNK) {
-        const int64_t i1 = i0 + ORC_TRACK_CHUNK < rows ? i0 + ORC_TRACK_CHUNK : rows;
-        double p = 0.0;
-        for (int64_t i = i0; i < i1; ++i)
-            p = fma(a[i], b[i], p);
-        total = total + p;
-    }
-    return total;
+    double p = 0.0;
+    for (int64_t i = 0; i < rows; ++i)
+        p = fma(a[i], b[i], p);
+    return p;
 }
 
-/* x_hat = A^T x (chunked sums), x_perp = x - A x_hat with
- * (A x_hat)_i = sum_j A(i,j) x_hat_j as fma, j ascending from 0, and
- * norm = sqrt(x_perp^T x_perp) (chunked sum). */
-static void track_complement(int64_t rows, int64_t r, const double *A, int64_t lda,
-                             const double *x, double *xhat, double *xperp, double *norm)
+/* y = x - A z with (A z)_i = sum_j A(i,j) z_j as fma, j ascending from 0. */
+static void minus_span(int64_t rows, int64_t r, const double *A, int64_t lda,
+                       const double *x, const double *z, double *y)
 {
-    for (int64_t j = 0; j < r; ++j)
-        xhat[j] = chunk_dot(rows, A + j * lda, x);
     for (int64_t i = 0; i < rows; ++i) {
         double s = 0.0;
         for (int64_t j = 0; j < r; ++j)
-            s = fma(A[i + j * lda], xhat[j], s);
-        xperp[i] = (g_mut == MUT_TRACK_RESID) ? x[i] + s : x[i] - s;
+            s = fma(A[i + j * lda], z[j], s);
+        y[i] = (g_mut == MUT_TRACK_RESID) ? x[i] + s : x[i] - s;
     }
-    *norm = sqrt(chunk_dot(rows, xperp, xperp));
 }
 
-/* out(:, j) = [A, w] M(:, keep_j): sequential fma over the r + 1 terms,
- * the appended column w last. */
+int orc_track_complement(int64_t rows, int64_t r, const double *A, int64_t lda,
+                         const double *x, double *xhat, double *xperp, double *norm,
+                         double *sums)
+{
+    if (rows < 1 || r < 1 || lda < rows || !A || !x || !xhat || !xperp || !norm)
+        return ORC_EINVAL;
+    double *s = (double *)malloc(sizeof(double) * (size_t)r);
+    double *y = (double *)malloc(sizeof(double) * (size_t)rows);
+    if (!s || !y) {
+        free(s);
+        free(y);
+        return ORC_ENOMEM;
+    }
+    /* first pass (eq. defup) */
+    for (int64_t j = 0; j < r; ++j)
+        xhat[j] = plain_dot(rows, A + j * lda, x);
+    minus_span(rows, r, A, lda, x, xhat, xperp);
+    const double s0 = plain_dot(rows, x, x);
+    const double s1 = plain_dot(rows, xperp, xperp);
+    double s2 = -1.0;
+    /* a complement no larger than the worst-case rounding error of the
+     * projection sums, rows * 2^-53 * ||x||, carries no direction */
+    const double tau = (double)rows * 0x1p-53;
+    const double floor2 = tau * tau * s0;
+    if (2.0 * s1 >= s0 || g_mut == MUT_TRACK_ONE_PASS) {
+        *norm = s1 > floor2 ? sqrt(s1) : 0.0;
+    } else {
+        /* second pass against the same basis ("twice is enough") */
+        for (int64_t j = 0; j < r; ++j)
+            s[j] = plain_dot(rows, A + j * lda, xperp);
+        minus_span(rows, r, A, lda, xperp, s, y);
+        for (int64_t j = 0; j < r; ++j)
+            xhat[j] = xhat[j] + s[j];
+        s2 = plain_dot(rows, y, y);
+        for (int64_t i = 0; i < rows; ++i)
+            xperp[i] = y[i];
+        *norm = (s2 > floor2 && 2.0 * s2 >= s1) ? sqrt(s2) : 0.0;
+    }
+    if (sums) {
+        sums[0] = s0;
+        sums[1] = s1;
+        sums[2] = s2;
+    }
+    free(s);
+    free(y);
+    return ORC_OK;
+}
+
+/* out(:, j) = sum_l A(:, l) M(rmap(l), cmap(j)) over l = 0..r-1 (fma, l
+ * ascending), then + w M(r, cmap(j)) when w is given.  rmap is the
+ * identity, or l -> r-1-l when rev; cmap is j -> keep[j]. */
 static void track_product(int64_t rows, int64_t r, const double *A, int64_t lda,
-                          const double *w, const double *M, int64_t ldm,
+                          const double *w, const double *M, int64_t ldm, int rev,
                           const int64_t *keep, int64_t ncols, double *out, int64_t ldo)
 {
     for (int64_t j = 0; j < ncols; ++j) {
@@ -490,10 +529,140 @@ static void track_product(int64_t rows, int64_t r, const double *A, int64_t lda,
         for (int64_t i = 0; i < rows; ++i) {
             double acc = 0.0;
             for (int64_t l = 0; l < r; ++l)
-                acc = fma(A[i + l * lda], mc[l], acc);
-            out[i + j * ldo] = fma(w[i], mc[r], acc);
+                acc = fma(A[i + l * lda], mc[rev ? r - 1 - l : l], acc);
+            out[i + j * ldo] = w ? fma(w[i], mc[r], acc) : acc;
         }
     }
+}
+
+int orc_track_finish(int64_t m, int64_t n, int64_t r, const double *U, int64_t ldu,
+                     const double *d, const double *e, const double *V, int64_t ldv,
+                     const double *bh, const double *ch, double delta, double gamma,
+                     const double *qb, const double *qc, int flags, double *U2,
+                     int64_t ldu2, double *d2, double *e2, double *V2, int64_t ldv2,
+                     double *info)
+{
+    const int keep_all = (flags & ORC_TRACK_KEEP_ALL) != 0;
+    const int ab = delta > 0.0, ac = gamma > 0.0;
+    if (r < 1 || m < r || n < r || ldu < m || ldv < n || ldu2 < m || ldv2 < n || !U || !d ||
+        !V || !bh || !ch || !U2 || !d2 || !V2 || (r > 1 && !e) || (ab && !qb) || (ac && !qc) ||
+        !(delta >= 0.0) || !(gamma >= 0.0) || (((r > 1) || (keep_all && ab && ac)) && !e2))
+        return ORC_EINVAL;
+    if ((!ab || !ac) && r < 2)
+        return ORC_ESPAN; /* a 1 x 1 or 2 x 1 middle matrix has no BGU pass */
+    const int64_t R = r + 1;
+    const int64_t mm = ab ? R : r, mn = ac ? R : r; /* middle matrix mm x mn */
+    /* the BGU pass runs on a tall or square matrix: the wide case (left
+     * side not augmented, right side augmented) runs on its transpose with
+     * rows and columns reversed, which is again upper bidiagonal plus a
+     * rank-1 term */
+    const int flip = !ab && ac;
+    const int64_t pm = flip ? R : mm, pn = flip ? r : mn;
+    double *Qm = (double *)calloc((size_t)(pm * pm), sizeof(double));
+    double *Pm = (double *)calloc((size_t)(pn * pn), sizeof(double));
+    double *dm = (double *)calloc((size_t)R, sizeof(double));
+    double *em = (double *)calloc((size_t)R, sizeof(double));
+    double *u = (double *)calloc((size_t)R, sizeof(double));
+    double *v = (double *)calloc((size_t)R, sizeof(double));
+    int64_t *keep = (int64_t *)malloc(sizeof(int64_t) * (size_t)R);
+    int st = ORC_OK;
+    if (!Qm || !Pm || !dm || !em || !u || !v || !keep) {
+        st = ORC_ENOMEM;
+        goto out;
+    }
+    for (int64_t i = 0; i < pm; ++i)
+        Qm[i + i * pm] = 1.0;
+    for (int64_t i = 0; i < pn; ++i)
+        Pm[i + i * pn] = 1.0;
+    if (!flip) {
+        /* eq. (equivlrup): [B 0; 0 0] + [b_hat; delta][c_hat; gamma]^T, the
+         * row (column) of the unaugmented side left out */
+        for (int64_t i = 0; i < r; ++i) {
+            dm[i] = d[i];
+            u[i] = bh[i];
+            v[i] = ch[i];
+        }
+        for (int64_t i = 0; i + 1 < r; ++i)
+            em[i] = e[i];
+        if (ab)
+            u[r] = (g_mut == MUT_TRACK_NO_DELTA) ? 0.0 : delta;
+        if (ac)
+            v[r] = gamma;
+    } else {
+        /* M = [B 0] + b_hat [c_hat; gamma]^T (r x (r+1)); with J the
+         * reversal of r entries, M^T = diag(J, 1) ([J B^T J; 0] + [J c_hat;
+         * gamma] (J b_hat)^T) J and J B^T J is upper bidiagonal with d and e
+         * reversed */
+        for (int64_t i = 0; i < r; ++i) {
+            dm[i] = d[r - 1 - i];
+            u[i] = ch[r - 1 - i];
+            v[i] = bh[r - 1 - i];
+        }
+        for (int64_t i = 0; i + 1 < r; ++i)
+            em[i] = (g_mut == MUT_TRACK_FLIP_E) ? e[i] : e[r - 2 - i];
+        u[r] = gamma;
+    }
+    st = orc_bgu_pass(pm, pn, Qm, pm, dm, em, Pm, pn, u, v, 0, NULL, 0, NULL);
+    if (st != ORC_OK)
+        goto out;
+    int64_t kdrop = -1, nk = 0;
+    if (ab && ac && !keep_all) {
+        /* truncation: drop the row and column of smallest column norm
+         * (squared norm d_k^2 + e_{k-1}^2 as fma(d_k, d_k, e_{k-1} * e_{k-1}));
+         * ties drop the highest index */
+        kdrop = R - 1;
+        double best = fma(dm[R - 1], dm[R - 1], em[R - 2] * em[R - 2]);
+        for (int64_t k = R - 2; k >= 0; --k) {
+            double nk2 = (k == 0) ? dm[0] * dm[0] : fma(dm[k], dm[k], em[k - 1] * em[k - 1]);
+            if (g_mut == MUT_TRACK_KEEP ? nk2 > best : nk2 < best) {
+                best = nk2;
+                kdrop = k;
+            }
+        }
+    }
+    const int64_t full = (ab && ac) ? R : r; /* columns of the updated bidiagonal */
+    for (int64_t k = 0; k < full; ++k)
+        if (k != kdrop)
+            keep[nk++] = k;
+    if (!flip) {
+        for (int64_t j = 0; j < nk; ++j)
+            d2[j] = dm[keep[j]];
+        for (int64_t j = 0; j + 1 < nk; ++j)
+            e2[j] = (keep[j + 1] == keep[j] + 1) ? em[keep[j]] : 0.0;
+        /* eq. (bdlrup): the thin factors [U, b_perp/delta] Q2(:, keep) and
+         * [V, c_perp/gamma] P2(:, keep); an unaugmented side has no
+         * appended column */
+        track_product(m, r, U, ldu, ab ? qb : NULL, Qm, pm, 0, keep, nk, U2, ldu2);
+        track_product(n, r, V, ldv, ac ? qc : NULL, Pm, pn, 0, keep, nk, V2, ldv2);
+    } else {
+        /* the pass gave M^T = diag(J,1) Q3 [Bbar; 0] P3^T J, so
+         * M = (J P3 J) (J Bbar^T J) (diag(J,1) Q3(:, 1:r) J)^T with
+         * J Bbar^T J upper bidiagonal: d, e reversed back, U2 = U J P3 J,
+         * V2 = [V, c_perp/gamma] diag(J,1) Q3(:, 1:r) J */
+        for (int64_t j = 0; j < r; ++j) {
+            d2[j] = dm[r - 1 - j];
+            keep[j] = r - 1 - j;
+        }
+        for (int64_t j = 0; j + 1 < r; ++j)
+            e2[j] = em[r - 2 - j];
+        track_product(m, r, U, ldu, NULL, Pm, pn, 1, keep, r, U2, ldu2);
+        track_product(n, r, V, ldv, qc, Qm, pm, 1, keep, r, V2, ldv2);
+    }
+    if (info) {
+        info[0] = delta;
+        info[1] = gamma;
+        info[2] = (double)kdrop;
+        info[3] = (double)nk;
+    }
+out:
+    free(Qm);
+    free(Pm);
+    free(dm);
+    free(em);
+    free(u);
+    free(v);
+    free(keep);
+    return st;
 }
 
 int orc_track_update(int64_t m, int64_t n, int64_t r, const double *U, int64_t ldu,
@@ -502,94 +671,38 @@ int orc_track_update(int64_t m, int64_t n, int64_t r, const double *U, int64_t l
                      int64_t ldu2, double *d2, double *e2, double *V2, int64_t ldv2,
                      double *info)
 {
-    const int keep_all = (flags & ORC_TRACK_KEEP_ALL) != 0;
-    if (r < 1 || m < r + 1 || n < r + 1 || ldu < m || ldv < n || ldu2 < m || ldv2 < n ||
-        !U || !d || !V || !b || !c || !U2 || !d2 || !V2 || (r > 1 && !e) || (!keep_all && r > 1 && !e2) ||
-        (keep_all && !e2))
+    if (r < 1 || m < r || n < r || ldu < m || ldv < n || !U || !V || !b || !c)
         return ORC_EINVAL;
-    const int64_t R = r + 1;
-    double *bh = (double *)calloc((size_t)R, sizeof(double));
-    double *ch = (double *)calloc((size_t)R, sizeof(double));
+    double *bh = (double *)calloc((size_t)r, sizeof(double));
+    double *ch = (double *)calloc((size_t)r, sizeof(double));
     double *bp = (double *)malloc(sizeof(double) * (size_t)m);
     double *cp = (double *)malloc(sizeof(double) * (size_t)n);
-    double *Qm = (double *)calloc((size_t)(R * R), sizeof(double));
-    double *Pm = (double *)calloc((size_t)(R * R), sizeof(double));
-    double *dm = (double *)calloc((size_t)R, sizeof(double));
-    double *em = (double *)calloc((size_t)R, sizeof(double));
-    int64_t *keep = (int64_t *)malloc(sizeof(int64_t) * (size_t)R);
     int st = ORC_OK;
-    if (!bh || !ch || !bp || !cp || !Qm || !Pm || !dm || !em || !keep) {
+    double delta = 0.0, gamma = 0.0;
+    if (!bh || !ch || !bp || !cp) {
         st = ORC_ENOMEM;
         goto out;
     }
     /* eq. (defup): projections onto the tracked bases and their complements */
-    double delta, gamma;
-    track_complement(m, r, U, ldu, b, bh, bp, &delta);
-    track_complement(n, r, V, ldv, c, ch, cp, &gamma);
-    if (info) {
-        info[0] = delta;
-        info[1] = gamma;
-    }
-    if (!(delta > 0.0) || !(gamma > 0.0)) { /* not augmented: outside this mode */
-        st = ORC_ESPAN;
-        goto out;
-    }
-    /* eq. (qrlr): the appended columns b_perp / delta and c_perp / gamma */
-    for (int64_t i = 0; i < m; ++i)
-        bp[i] = bp[i] / delta;
-    for (int64_t i = 0; i < n; ++i)
-        cp[i] = cp[i] / gamma;
-    /* eq. (equivlrup): BGU on [B 0; 0 0] + [b_hat; delta][c_hat; gamma]^T */
-    for (int64_t i = 0; i < R; ++i)
-        Qm[i + i * R] = Pm[i + i * R] = 1.0;
-    for (int64_t i = 0; i < r; ++i)
-        dm[i] = d[i];
-    for (int64_t i = 0; i + 1 < r; ++i)
-        em[i] = e[i];
-    bh[r] = (g_mut == MUT_TRACK_NO_DELTA) ? 0.0 : delta;
-    ch[r] = gamma;
-    st = orc_bgu_update(R, R, Qm, R, dm, em, Pm, R, bh, R, ch, R, 1, 0);
+    st = orc_track_complement(m, r, U, ldu, b, bh, bp, &delta, NULL);
+    if (st == ORC_OK)
+        st = orc_track_complement(n, r, V, ldv, c, ch, cp, &gamma, NULL);
     if (st != ORC_OK)
         goto out;
-    /* truncation: drop the row and column of smallest column norm
-     * (squared norm d_k^2 + e_{k-1}^2 as fma(d_k, d_k, e_{k-1} * e_{k-1}));
-     * ties drop the highest index */
-    int64_t kdrop = R;
-    if (!keep_all) {
-        kdrop = R - 1;
-        double best = fma(dm[R - 1], dm[R - 1], em[R - 2] * em[R - 2]);
-        for (int64_t k = R - 2; k >= 0; --k) {
-            double nk = (k == 0) ? dm[0] * dm[0] : fma(dm[k], dm[k], em[k - 1] * em[k - 1]);
-            if (g_mut == MUT_TRACK_KEEP ? nk > best : nk < best) {
-                best = nk;
-                kdrop = k;
-            }
-        }
-    }
-    if (info)
-        info[2] = (double)kdrop;
-    int64_t nk = 0;
-    for (int64_t k = 0; k < R; ++k)
-        if (k != kdrop)
-            keep[nk++] = k;
-    for (int64_t j = 0; j < nk; ++j)
-        d2[j] = dm[keep[j]];
-    for (int64_t j = 0; j + 1 < nk; ++j)
-        e2[j] = (keep[j + 1] == keep[j] + 1) ? em[keep[j]] : 0.0;
-    /* eq. (bdlrup): the thin factors [Q1, b_perp/delta] Q2(:, keep) and
-     * [P1, c_perp/gamma] P2(:, keep) */
-    track_product(m, r, U, ldu, bp, Qm, R, keep, nk, U2, ldu2);
-    track_product(n, r, V, ldv, cp, Pm, R, keep, nk, V2, ldv2);
+    /* eq. (qrlr): the appended columns b_perp / delta and c_perp / gamma */
+    if (delta > 0.0)
+        for (int64_t i = 0; i < m; ++i)
+            bp[i] = bp[i] / delta;
+    if (gamma > 0.0)
+        for (int64_t i = 0; i < n; ++i)
+            cp[i] = cp[i] / gamma;
+    st = orc_track_finish(m, n, r, U, ldu, d, e, V, ldv, bh, ch, delta, gamma, bp, cp, flags,
+                          U2, ldu2, d2, e2, V2, ldv2, info);
 out:
     free(bh);
     free(ch);
     free(bp);
     free(cp);
-    free(Qm);
-    free(Pm);
-    free(dm);
-    free(em);
-    free(keep);
     return st;
 }
 

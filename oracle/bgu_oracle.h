@@ -29,7 +29,7 @@ extern "C" {
 #define ORC_EINVAL (-1)
 #define ORC_ENOMEM (-2)
 #define ORC_ESTRUCT (-10) /* a band/zero-pattern assertion failed */
-#define ORC_ESPAN (-11)   /* tracking: b or c lies in the span of the tracked basis */
+#define ORC_ESPAN (-11)   /* tracking: r = 1 with b or c in the span of the tracked basis */
 
 /* flags for orc_bgu_pass / orc_bgu_update */
 #define ORC_CHECK_PHASES 1 /* assert the zero pattern after each phase */
@@ -93,30 +93,65 @@ int orc_bgu_update(int64_t m, int64_t n, double *Q, int64_t ldq, double *d,
                    double *e, double *P, int64_t ldp, const double *B,
                    int64_t ldb, const double *C, int64_t ldc, int r, int flags);
 
-/* flags for orc_track_update */
-#define ORC_TRACK_KEEP_ALL 1 /* return the rank r+1 factorization (no truncation) */
-#define ORC_TRACK_CHUNK 256  /* rows per chunk of the tracking update's row sums */
+/* flags for orc_track_update / orc_track_finish */
+#define ORC_TRACK_KEEP_ALL 1 /* both sides augmented: return the rank r+1 factorization */
 
 /* Subspace tracking (Section 4, eqs. (lrup)-(bdlrup)): the thin rank-r
  * factorization A = U B V^T (U m x r, V n x r orthonormal columns, B upper
  * bidiagonal with d (r), e (r-1)) updated with b c^T.
- *   b_hat_j = sum_i U(i,j) b_i and delta^2 = sum_i b_perp_i^2 are chunked
- *   sums: rows in chunks of ORC_TRACK_CHUNK, a sequential fma from 0 inside
- *   a chunk, the partials added in ascending order from 0;
- *   b_perp_i = b_i - sum_j U(i,j) b_hat_j (fma, j ascending);
- *   the same for c, V, gamma.
- *   One BGU pass (orc_bgu_update with Q = P = I) on the (r+1) x (r+1) matrix
- *   [B 0; 0 0] + [b_hat; delta][c_hat; gamma]^T gives Q2 Bbar P2^T.
- *   Unless ORC_TRACK_KEEP_ALL: the row and column k of Bbar with the smallest
- *   column norm (d_k^2 + e_{k-1}^2 as fma(d_k, d_k, e_{k-1}*e_{k-1}); ties:
- *   the highest k) are removed; the superdiagonal entry joining k-1 and k+1
- *   is 0.
- *   U2(:, j) = [U, b_perp/delta] Q2(:, keep_j), each entry a sequential fma
- *   over the r+1 terms in column order; V2 the same with P2.
- * U2 is m x (r or r+1), V2 n x (r or r+1), d2 r or r+1 entries, e2 one fewer.
- * info (optional, 3 entries): delta, gamma, the removed index (r+1 if none).
- * Requires m, n >= r + 1.  Returns ORC_ESPAN, changing no output, when delta
- * or gamma is 0 (the paper then does not augment that side). */
+ *
+ * orc_track_complement: x_hat = A^T x, x_perp = x - A x_hat, its norm
+ * (eq. defup).  Every sum is a sequential fma from 0, rows ascending;
+ * (A z)_i = sum_j A(i,j) z_j as fma, j ascending.  With s0 = x^T x and
+ * s1 = x_perp^T x_perp: if 2 s1 >= s0 the first pass stands; otherwise one
+ * more pass against the same basis (s = A^T x_perp, x_perp <- x_perp - A s,
+ * x_hat <- x_hat + s, s2 the new squared norm) and the norm is sqrt(s2) if
+ * 2 s2 >= s1, else 0: x lies in span(A) to working precision (the "twice
+ * is enough" test of Kahan and Parlett; Parlett, The Symmetric Eigenvalue
+ * Problem, section 6-9).  The norm is also 0 when the squared norm it
+ * would take is at most (tau ||x||)^2 = tau * tau * s0 with tau = rows *
+ * 2^-53 (the worst-case rounding error of the projection sums: such a
+ * complement has no meaningful direction).  sums (optional, 3 entries):
+ * s0, s1, s2 (-1 without a second pass).
+ *
+ * orc_track_finish: the rest of the update from given projections b_hat,
+ * c_hat (r each), norms delta, gamma >= 0 and unit complements qb =
+ * b_perp/delta (m), qc = c_perp/gamma (n; each read only when its norm is
+ * positive).  A side with a positive norm is augmented by its complement
+ * (eq. qrlr); the middle matrix of eq. (equivlrup) is
+ *   both augmented:  [B 0; 0 0] + [b_hat; delta][c_hat; gamma]^T, (r+1)^2;
+ *   only the left:   [B; 0] + [b_hat; delta] c_hat^T, (r+1) x r;
+ *   only the right:  [B 0] + b_hat [c_hat; gamma]^T, r x (r+1), run as its
+ *                    transpose with rows and columns reversed (again upper
+ *                    bidiagonal plus rank 1, (r+1) x r);
+ *   neither:         B + b_hat c_hat^T, r x r;
+ * one BGU pass (orc_bgu_pass, Q = P = I) factors it.  Only when both sides
+ * are augmented is the result of rank r+1; unless ORC_TRACK_KEEP_ALL the
+ * row and column k of Bbar with the smallest column norm (d_k^2 + e_{k-1}^2
+ * as fma(d_k, d_k, e_{k-1}*e_{k-1}); ties: the highest k) are removed and
+ * the superdiagonal entry joining k-1 and k+1 is 0.  Otherwise the result
+ * is rank r with nothing removed (the paper's unaugmented case).
+ * U2(:, j) = [U, qb] Q2(:, keep_j), each entry a sequential fma over U's
+ * columns in order and the appended column last (none for an unaugmented
+ * side); V2 the same with P2; in the reversed case U2 = U J P3 J and
+ * V2 = [V, qc] diag(J,1) Q3(:, 1:r) J (J: reversal of r entries).
+ * info (optional, 4 entries): delta, gamma, the removed index (-1 if none),
+ * the output rank.  Requires m, n >= r.  Returns ORC_ESPAN, changing no
+ * output, when r = 1 and a side is not augmented (no pass on a 2 x 1 or
+ * 1 x 1 matrix).
+ *
+ * orc_track_update: orc_track_complement on both sides, the complements
+ * divided by their norms, then orc_track_finish.
+ * U2 is m x k, V2 n x k, d2 k entries, e2 k-1, k = r or r+1. */
+int orc_track_complement(int64_t rows, int64_t r, const double *A, int64_t lda,
+                         const double *x, double *xhat, double *xperp, double *norm,
+                         double *sums);
+int orc_track_finish(int64_t m, int64_t n, int64_t r, const double *U, int64_t ldu,
+                     const double *d, const double *e, const double *V, int64_t ldv,
+                     const double *bh, const double *ch, double delta, double gamma,
+                     const double *qb, const double *qc, int flags, double *U2,
+                     int64_t ldu2, double *d2, double *e2, double *V2, int64_t ldv2,
+                     double *info);
 int orc_track_update(int64_t m, int64_t n, int64_t r, const double *U, int64_t ldu,
                      const double *d, const double *e, const double *V, int64_t ldv,
                      const double *b, const double *c, int flags, double *U2,

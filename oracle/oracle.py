@@ -83,6 +83,9 @@ def lib():
         L.orc_set_mutation.argtypes = [ctypes.c_int]
         L.orc_track_update.argtypes = [i64, i64, i64, dp, i64, dp, dp, dp, i64, dp, dp, ctypes.c_int,
                                        dp, i64, dp, dp, dp, i64, dp]
+        L.orc_track_complement.argtypes = [i64, i64, dp, i64, dp, dp, dp, dp, dp]
+        L.orc_track_finish.argtypes = [i64, i64, i64, dp, i64, dp, dp, dp, i64, dp, dp, ctypes.c_double,
+                                       ctypes.c_double, dp, dp, ctypes.c_int, dp, i64, dp, dp, dp, i64, dp]
         L.orc_set_mutation.restype = None
         _lib = L
     return _lib
@@ -244,10 +247,59 @@ ORC_ESPAN = -11
 TRACK_KEEP_ALL = 1
 
 
+def _track_out(m, n, r, k):
+    return (np.zeros((m, k), order="F"), np.zeros(k), np.zeros(max(k - 1, 1)),
+            np.zeros((n, k), order="F"), np.zeros(4))
+
+
+def _track_rank(r, delta, gamma, keep_all):
+    return r + 1 if (keep_all and delta > 0 and gamma > 0) else r
+
+
+def track_complement(A, x):
+    """Projection of x onto the orthonormal columns of A and its complement
+    (Section 4, eq. (defup), with one reorthogonalization pass when needed):
+    returns (xhat, xperp, norm, (s0, s1, s2)); norm 0 means x is taken to lie
+    in span(A)."""
+    A = _f64(A)
+    rows, r = A.shape
+    x = np.ascontiguousarray(x, dtype=np.float64).ravel()
+    xhat, xperp, norm, sums = np.zeros(r), np.zeros(rows), np.zeros(1), np.zeros(3)
+    st = lib().orc_track_complement(rows, r, _p(A), rows, _p(x), _p(xhat), _p(xperp), _p(norm), _p(sums))
+    if st != ORC_OK:
+        raise ValueError(f"orc_track_complement failed with status {st}")
+    return xhat, xperp, float(norm[0]), tuple(sums)
+
+
+def track_finish(U, d, e, V, bh, ch, delta, gamma, qb, qc, keep_all: bool = False):
+    """The tracking update from given projections b_hat, c_hat, norms delta,
+    gamma and unit complements qb, qc (Section 4, eqs. (qrlr)-(bdlrup)):
+    returns (U2, d2, e2, V2, info), info = (delta, gamma, removed index or
+    -1, output rank)."""
+    U, V = _f64(U), _f64(V)
+    m, r = U.shape
+    n = V.shape[0]
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    e = np.ascontiguousarray(e, dtype=np.float64) if r > 1 else np.zeros(1)
+    bh = np.ascontiguousarray(bh, dtype=np.float64).ravel()
+    ch = np.ascontiguousarray(ch, dtype=np.float64).ravel()
+    qb = np.ascontiguousarray(qb if qb is not None else np.zeros(m), dtype=np.float64).ravel()
+    qc = np.ascontiguousarray(qc if qc is not None else np.zeros(n), dtype=np.float64).ravel()
+    k = _track_rank(r, delta, gamma, keep_all)
+    U2, d2, e2, V2, info = _track_out(m, n, r, k)
+    st = lib().orc_track_finish(m, n, r, _p(U), m, _p(d), _p(e), _p(V), n, _p(bh), _p(ch), float(delta),
+                                float(gamma), _p(qb), _p(qc), TRACK_KEEP_ALL if keep_all else 0, _p(U2), m,
+                                _p(d2), _p(e2), _p(V2), n, _p(info))
+    if st != ORC_OK:
+        raise ValueError(f"orc_track_finish failed with status {st}")
+    return U2, d2, e2[:k - 1], V2, (info[0], info[1], int(info[2]), int(info[3]))
+
+
 def track_update(U, d, e, V, b, c, keep_all: bool = False):
     """Subspace-tracking update (Section 4): returns (U2, d2, e2, V2, info)
-    with info = (delta, gamma, removed index).  Raises ValueError with the
-    status when b or c lies in the span of U or V (status ORC_ESPAN)."""
+    with info = (delta, gamma, removed index or -1, output rank).  Raises
+    ValueError with the status when r = 1 and a side is not augmented
+    (status ORC_ESPAN)."""
     U, V = _f64(U), _f64(V)
     m, r = U.shape
     n = V.shape[0]
@@ -255,18 +307,15 @@ def track_update(U, d, e, V, b, c, keep_all: bool = False):
     e = np.ascontiguousarray(e, dtype=np.float64) if r > 1 else np.zeros(1)
     b = np.ascontiguousarray(b, dtype=np.float64).ravel()
     c = np.ascontiguousarray(c, dtype=np.float64).ravel()
-    k = r + 1 if keep_all else r
-    U2 = np.zeros((m, k), order="F")
-    V2 = np.zeros((n, k), order="F")
-    d2 = np.zeros(k)
-    e2 = np.zeros(max(k - 1, 1))
-    info = np.zeros(3)
+    U2, d2, e2, V2, info = _track_out(m, n, r, r + 1)
     st = lib().orc_track_update(m, n, r, _p(U), m, _p(d), _p(e), _p(V), n, _p(b), _p(c),
                                 TRACK_KEEP_ALL if keep_all else 0, _p(U2), m, _p(d2), _p(e2),
                                 _p(V2), n, _p(info))
     if st != ORC_OK:
         raise ValueError(f"orc_track_update failed with status {st}")
-    return U2, d2, e2[:k - 1], V2, (info[0], info[1], int(info[2]))
+    k = int(info[3])
+    return (np.asfortranarray(U2[:, :k]), d2[:k], e2[:k - 1], np.asfortranarray(V2[:, :k]),
+            (info[0], info[1], int(info[2]), k))
 
 
 def set_mutation(k: int) -> None:

@@ -81,6 +81,7 @@ def lib():
         L.bdu_track_read.argtypes = [vp, vp, vp, vp, vp]
         L.bdu_track_last.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(i64)]
+        L.bdu_track_last_projection.argtypes = [vp, vp, vp, vp, vp]
         L.bdu_track_destroy.argtypes = [vp]
         L.bdu_tune_save.argtypes = [ctypes.c_char_p]
         L.bdu_tune_load.argtypes = [ctypes.c_char_p]
@@ -146,6 +147,49 @@ def _ptr(a, matrix: bool = False):
     if matrix and a.dim() == 2 and a.stride(0) != 1:
         raise ValueError("matrices must be column-major (stride(0) == 1)")
     return a.data_ptr()
+
+
+def _shape(a):
+    return tuple(int(x) for x in a.shape)
+
+
+def _packed(a) -> bool:
+    """Column-major with leading dimension = rows (matrices), unit stride (vectors)."""
+    if isinstance(a, np.ndarray):
+        return a.flags["F_CONTIGUOUS"]
+    st = a.stride()
+    if a.dim() == 1:
+        return a.shape[0] <= 1 or st[0] == 1
+    return (a.shape[0] <= 1 or st[0] == 1) and (a.shape[1] <= 1 or st[1] == a.shape[0])
+
+
+def _arg(a, shape, name: str):
+    """Pointer of a float64 array or CUDA tensor of exactly this shape, packed
+    column-major; None passes through.  The C side reads prod(shape) doubles
+    from the pointer, so every shape and stride is checked here."""
+    if a is None:
+        return None
+    if _shape(a) != tuple(shape):
+        raise ValueError(f"{name}: shape {_shape(a)}, expected {tuple(shape)}")
+    if not _packed(a):
+        raise ValueError(f"{name}: must be packed column-major (leading dimension = rows)")
+    return _ptr(a, len(shape) == 2)
+
+
+def _cols(a, rows: int, name: str):
+    """(pointer, r) of an update block: a vector of length rows (r = 1) or a
+    rows x r matrix."""
+    if a.ndim == 1:
+        return _arg(a, (rows,), name), 1
+    return _arg(a, (rows, int(a.shape[1])), name), int(a.shape[1])
+
+
+def _pair(B, C, m: int, n: int):
+    pb, rb = _cols(B, m, "B")
+    pc, rc = _cols(C, n, "C")
+    if rb != rc:
+        raise ValueError(f"B has {rb} columns and C has {rc}")
+    return pb, pc, rb
 
 
 def set_tiling(k0: int, nw: int, rpl: int = 1) -> None:
@@ -252,10 +296,10 @@ class Handle:
     """One factorization A = Q Bd P^T resident on the GPU."""
 
     def __init__(self, Q, d, e, P):
-        m, n = Q.shape[0], P.shape[0]
+        m, n = int(Q.shape[0]), int(P.shape[0])
         h = ctypes.c_void_p()
-        _check(lib().bdu_create(m, n, _ptr(Q, True), _ptr(d), _ptr(e), _ptr(P, True), ctypes.byref(h)),
-               "bdu_create")
+        _check(lib().bdu_create(m, n, _arg(Q, (m, m), "Q"), _arg(d, (n,), "d"), _arg(e, (n - 1,), "e"),
+                                _arg(P, (n, n), "P"), ctypes.byref(h)), "bdu_create")
         self._h = h
         self.m, self.n = m, n
 
@@ -264,20 +308,23 @@ class Handle:
         return self._h
 
     def update(self, B, C) -> None:
-        r = 1 if B.ndim == 1 else B.shape[1]
-        _check(lib().bdu_update(self._h, _ptr(B, True), _ptr(C, True), r), "bdu_update")
+        pb, pc, r = _pair(B, C, self.m, self.n)
+        _check(lib().bdu_update(self._h, pb, pc, r), "bdu_update")
 
     def update_projected(self, u, v) -> None:
-        _check(lib().bdu_update_projected(self._h, _ptr(u), _ptr(v)), "bdu_update_projected")
+        _check(lib().bdu_update_projected(self._h, _arg(u, (self.m,), "u"), _arg(v, (self.n,), "v")),
+               "bdu_update_projected")
 
     def update_householder(self, b, c) -> None:
         """A <- A + b c^T by the Householder bidiagonal update (Algorithm 1)."""
-        _check(lib().bdu_update_householder(self._h, _ptr(b), _ptr(c)), "bdu_update_householder")
+        _check(lib().bdu_update_householder(self._h, _arg(b, (self.m,), "b"), _arg(c, (self.n,), "c")),
+               "bdu_update_householder")
 
     def project(self, b, c):
         u = np.empty(self.m)
         v = np.empty(self.n)
-        _check(lib().bdu_project(self._h, _ptr(b), _ptr(c), u.ctypes.data, v.ctypes.data), "bdu_project")
+        _check(lib().bdu_project(self._h, _arg(b, (self.m,), "b"), _arg(c, (self.n,), "c"), u.ctypes.data,
+                                 v.ctypes.data), "bdu_project")
         return u, v
 
     def read(self):
@@ -289,7 +336,9 @@ class Handle:
         return Q, d, e[: self.n - 1], P
 
     def read_into(self, Q=None, d=None, e=None, P=None) -> None:
-        _check(lib().bdu_read(self._h, _ptr(Q, True), _ptr(d), _ptr(e), _ptr(P, True)), "bdu_read")
+        m, n = self.m, self.n
+        _check(lib().bdu_read(self._h, _arg(Q, (m, m), "Q"), _arg(d, (n,), "d"), _arg(e, (n - 1,), "e"),
+                              _arg(P, (n, n), "P")), "bdu_read")
 
     def last_rotations(self):
         L = lib()
@@ -354,10 +403,13 @@ class Handle:
 def update_batched(handles, Bs, Cs) -> None:
     """bdu_update_batched over distinct handles; Bs[i] is m_i x r_i, Cs[i] n_i x r_i."""
     n = len(handles)
+    if len(Bs) != n or len(Cs) != n:
+        raise ValueError("one B and one C per handle")
+    args = [_pair(B, C, h.m, h.n) for h, B, C in zip(handles, Bs, Cs)]
     hp = (ctypes.c_void_p * n)(*[h.ptr.value for h in handles])
-    bp = (ctypes.c_void_p * n)(*[_ptr(B, True) for B in Bs])
-    cp = (ctypes.c_void_p * n)(*[_ptr(C, True) for C in Cs])
-    rs = (ctypes.c_int * n)(*[1 if B.ndim == 1 else B.shape[1] for B in Bs])
+    bp = (ctypes.c_void_p * n)(*[a[0] for a in args])
+    cp = (ctypes.c_void_p * n)(*[a[1] for a in args])
+    rs = (ctypes.c_int * n)(*[a[2] for a in args])
     _check(lib().bdu_update_batched(hp, bp, cp, rs, n), "bdu_update_batched")
 
 
@@ -375,9 +427,19 @@ class Batch:
     def update(self, Bs, Cs, ranks=None) -> None:
         """Bs[i] is m_i x r_i (or a vector for r_i = 1), None for no update of handle i."""
         n = len(self.handles)
-        rs = ranks if ranks is not None else [0 if B is None else (1 if B.ndim == 1 else B.shape[1]) for B in Bs]
-        bp = (ctypes.c_void_p * n)(*[None if B is None else _ptr(B, True) for B in Bs])
-        cp = (ctypes.c_void_p * n)(*[None if C is None else _ptr(C, True) for C in Cs])
+        if len(Bs) != n or len(Cs) != n:
+            raise ValueError("one B and one C (or None) per handle")
+        args = []
+        for i, (h, B, C) in enumerate(zip(self.handles, Bs, Cs)):
+            if (B is None) != (C is None):
+                raise ValueError(f"handle {i}: B and C must both be given or both be None")
+            args.append((None, None, 0) if B is None else _pair(B, C, h.m, h.n))
+        rs = list(ranks) if ranks is not None else [a[2] for a in args]
+        for i, (rk, a) in enumerate(zip(rs, args)):
+            if rk > a[2]:
+                raise ValueError(f"handle {i}: rank {rk} exceeds the {a[2]} columns given")
+        bp = (ctypes.c_void_p * n)(*[a[0] for a in args])
+        cp = (ctypes.c_void_p * n)(*[a[1] for a in args])
         ra = (ctypes.c_int * n)(*rs)
         _check(lib().bdu_batch_update(self._b, bp, cp, ra), "bdu_batch_update")
 
@@ -415,19 +477,23 @@ class Server:
 
     def open(self, Q, d, e, P) -> int:
         """Stream id; raises BduError (status BDU_ENOMEM) when over the budget."""
-        m, n = Q.shape[0], P.shape[0]
+        m, n = int(Q.shape[0]), int(P.shape[0])
         sid = ctypes.c_int()
-        _check(lib().bdu_server_open(self._s, m, n, _ptr(Q, True), _ptr(d), _ptr(e), _ptr(P, True),
-                                     ctypes.byref(sid)), "bdu_server_open")
+        _check(lib().bdu_server_open(self._s, m, n, _arg(Q, (m, m), "Q"), _arg(d, (n,), "d"),
+                                     _arg(e, (n - 1,), "e"), _arg(P, (n, n), "P"), ctypes.byref(sid)),
+               "bdu_server_open")
         self.shapes[sid.value] = (m, n)
         return sid.value
 
     def submit(self, sid: int, B, C, detach: bool = False):
         """Ticket (None if detached); raises BduError (status BDU_EBUSY) when the stream's queue is full."""
-        r = 1 if B.ndim == 1 else B.shape[1]
+        if sid not in self.shapes:
+            raise ValueError(f"unknown stream {sid}")
+        m, n = self.shapes[sid]
+        pb, pc, r = _pair(B, C, m, n)
         t = ctypes.c_int64()
-        _check(lib().bdu_server_submit(self._s, sid, _ptr(B, True), _ptr(C, True), r,
-                                       None if detach else ctypes.byref(t)), "bdu_server_submit")
+        _check(lib().bdu_server_submit(self._s, sid, pb, pc, r, None if detach else ctypes.byref(t)),
+               "bdu_server_submit")
         return None if detach else t.value
 
     def wait(self, ticket: int) -> float:
@@ -486,14 +552,24 @@ class Tracker:
     def __init__(self, U, d, e, V):
         self.m, self.r = int(U.shape[0]), int(U.shape[1])
         self.n = int(V.shape[0])
+        m, n, r = self.m, self.n, self.r
         h = ctypes.c_void_p()
-        _check(lib().bdu_track_create(self.m, self.n, self.r, _ptr(U, True), _ptr(d),
-                                      _ptr(e) if self.r > 1 else None, _ptr(V, True), ctypes.byref(h)),
-               "bdu_track_create")
+        _check(lib().bdu_track_create(m, n, r, _arg(U, (m, r), "U"), _arg(d, (r,), "d"),
+                                      _arg(e, (r - 1,), "e") if r > 1 else None, _arg(V, (n, r), "V"),
+                                      ctypes.byref(h)), "bdu_track_create")
         self._h = h
 
     def update(self, b, c) -> None:
-        _check(lib().bdu_track_update(self._h, _ptr(b), _ptr(c)), "bdu_track_update")
+        _check(lib().bdu_track_update(self._h, _arg(b, (self.m,), "b"), _arg(c, (self.n,), "c")),
+               "bdu_track_update")
+
+    def last_projection(self):
+        """(b_hat, c_hat, b_perp/delta, c_perp/gamma) of the last update."""
+        bh, ch = np.empty(self.r), np.empty(self.r)
+        qb, qc = np.empty(self.m), np.empty(self.n)
+        _check(lib().bdu_track_last_projection(self._h, bh.ctypes.data, ch.ctypes.data, qb.ctypes.data,
+                                               qc.ctypes.data), "bdu_track_last_projection")
+        return bh, ch, qb, qc
 
     def sync(self) -> None:
         _check(lib().bdu_track_sync(self._h), "bdu_track_sync")

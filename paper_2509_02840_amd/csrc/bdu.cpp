@@ -11,6 +11,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -1591,19 +1592,25 @@ extern "C" int bdu_update_householder(bdu_handle h, const double *b, const doubl
 
 struct bdu_track_ctx {
     int64_t m = 0, n = 0, r = 0;
-    bdu_handle mid = nullptr;      // the (r+1) x (r+1) middle factorization
+    // middle factorizations: [0] (r+1) x (r+1) (both sides augmented),
+    // [1] (r+1) x r (one side augmented), [2] r x r (neither); [1] and [2]
+    // are created on first use.  All run on the stream of [0].
+    bdu_handle mid[3] = {nullptr, nullptr, nullptr};
     double *U[2] = {nullptr, nullptr}, *V[2] = {nullptr, nullptr};
     int cur = 0;                   // U[cur], V[cur] hold the tracked factors
     double *d = nullptr, *e = nullptr;
     double *b = nullptr, *c = nullptr;    // staged update vectors
-    double *bh = nullptr, *ch = nullptr;  // projections (r + 1: the last is delta / gamma)
+    double *bh = nullptr, *ch = nullptr;  // projections (r)
+    double *sh = nullptr;                 // second-pass projections (2 r)
     double *bp = nullptr, *cp = nullptr;  // complements, then unit vectors
+    double *mu = nullptr, *mv = nullptr;  // the middle pass's inputs (r + 1)
     double *part = nullptr;               // chunk partials of the projections
     double *npart = nullptr;              // chunk partials of the squared norms
-    double *norms = nullptr;              // delta, gamma (device)
+    double *sums = nullptr;               // squared norms, two passes (8, device)
     int *kdrop = nullptr;                 // removed index (device)
-    double *h_info = nullptr;             // pinned: delta, gamma
+    double *h_sums = nullptr;             // pinned: the squared norms
     int *h_k = nullptr;                   // pinned: removed index
+    double last_norm[2] = {0.0, 0.0};     // delta, gamma of the last update
     bool have_last = false;
     bool poisoned = false;
     std::vector<void *> allocs;
@@ -1626,10 +1633,11 @@ hipError_t talloc(bdu_track_ctx *t, T **p, int64_t count)
 
 void track_free(bdu_track_ctx *t)
 {
-    if (t->mid) (void)hipStreamSynchronize(t->mid->stream);
+    if (t->mid[0]) (void)hipStreamSynchronize(t->mid[0]->stream);
     for (void *p : t->allocs) (void)hipFree(p);
     for (void *p : t->pinned) (void)hipHostFree(p);
-    if (t->mid) bdu_destroy(t->mid);
+    for (bdu_handle h : t->mid)
+        if (h) bdu_destroy(h);
     delete t;
 }
 
@@ -1641,10 +1649,26 @@ TrackSides track_sides(bdu_track_ctx *t)
     return s;
 }
 
-TrackMiddle track_middle(bdu_track_ctx *t)
+// The middle handle of shape rows x cols (Q = P = I, B = 0; reset before
+// every pass), created on first use on the tracker's stream.
+int track_mid(bdu_track_ctx *t, int which, int64_t rows, int64_t cols)
 {
-    const HandleDev &hd = t->mid->hd;
-    return TrackMiddle{hd.Q, hd.P, hd.d, hd.e, hd.ldq, hd.ldp, (int)(t->r + 1)};
+    if (t->mid[which]) return BDU_OK;
+    std::vector<double> Iq((size_t)(rows * rows), 0.0), Ip((size_t)(cols * cols), 0.0), z((size_t)rows, 0.0);
+    for (int64_t i = 0; i < rows; ++i) Iq[(size_t)(i + i * rows)] = 1.0;
+    for (int64_t i = 0; i < cols; ++i) Ip[(size_t)(i + i * cols)] = 1.0;
+    bdu_handle h = nullptr;
+    int st = bdu_create(rows, cols, Iq.data(), z.data(), z.data(), Ip.data(), &h);
+    if (st != BDU_OK) return st;
+    if (which != 0) {
+        st = bdu_set_stream(h, t->mid[0]->stream);
+        if (st != BDU_OK) {
+            bdu_destroy(h);
+            return st;
+        }
+    }
+    t->mid[which] = h;
+    return BDU_OK;
 }
 
 }  // namespace
@@ -1654,22 +1678,17 @@ extern "C" {
 int bdu_track_create(int64_t m, int64_t n, int64_t r, const double *U, const double *d, const double *e,
                      const double *V, bdu_track *out)
 {
-    if (!out || !U || !d || !V || (r > 1 && !e) || r < 1 || m < r + 1 || n < r + 1 || r + 1 > 65535 ||
+    if (!out || !U || !d || !V || (r > 1 && !e) || r < 1 || m < r || n < r || r + 1 > 65535 ||
         m > (int64_t)1 << 30 || n > (int64_t)1 << 30)
         return BDU_EINVAL;
     *out = nullptr;
     const int64_t R = r + 1;
-    // the middle factorization starts as I [B 0; 0 0] I^T; its values are
-    // reset before every update
-    std::vector<double> I((size_t)(R * R), 0.0), dz((size_t)R, 0.0), ez((size_t)R, 0.0);
-    for (int64_t i = 0; i < R; ++i) I[(size_t)(i + i * R)] = 1.0;
     bdu_track_ctx *t = new bdu_track_ctx;
     t->m = m;
     t->n = n;
     t->r = r;
-    int st = bdu_create(R, R, I.data(), dz.data(), ez.data(), I.data(), &t->mid);
+    int st = track_mid(t, 0, R, R);
     if (st != BDU_OK) {
-        t->mid = nullptr;
         track_free(t);
         return st;
     }
@@ -1687,16 +1706,19 @@ int bdu_track_create(int64_t m, int64_t n, int64_t r, const double *U, const dou
     A(talloc(t, &t->c, n));
     A(talloc(t, &t->bh, R));
     A(talloc(t, &t->ch, R));
+    A(talloc(t, &t->sh, 2 * r));
     A(talloc(t, &t->bp, m));
     A(talloc(t, &t->cp, n));
+    A(talloc(t, &t->mu, R));
+    A(talloc(t, &t->mv, R));
     const int64_t nchunk = (std::max(m, n) + kTrackChunk - 1) / kTrackChunk;
     A(talloc(t, &t->part, 2 * nchunk * r));
-    A(talloc(t, &t->npart, 2 * nchunk));
-    A(talloc(t, &t->norms, 2));
+    A(talloc(t, &t->npart, 4 * nchunk));
+    A(talloc(t, &t->sums, 8));
     A(talloc(t, &t->kdrop, 1));
     if (e2 == hipSuccess) {
-        A(hipHostMalloc((void **)&t->h_info, 2 * sizeof(double), hipHostMallocDefault));
-        if (e2 == hipSuccess) t->pinned.push_back(t->h_info);
+        A(hipHostMalloc((void **)&t->h_sums, 8 * sizeof(double), hipHostMallocDefault));
+        if (e2 == hipSuccess) t->pinned.push_back(t->h_sums);
         A(hipHostMalloc((void **)&t->h_k, sizeof(int), hipHostMallocDefault));
         if (e2 == hipSuccess) t->pinned.push_back(t->h_k);
     }
@@ -1705,7 +1727,7 @@ int bdu_track_create(int64_t m, int64_t n, int64_t r, const double *U, const dou
         (void)hipGetLastError();
         return e2 == hipErrorOutOfMemory ? BDU_ENOMEM : BDU_EDEVICE;
     }
-    hipStream_t s = t->mid->stream;
+    hipStream_t s = t->mid[0]->stream;
     A(copy_in(t->U[0], U, sizeof(double) * m * r, s));
     A(copy_in(t->V[0], V, sizeof(double) * n * r, s));
     A(copy_in(t->d, d, sizeof(double) * r, s));
@@ -1715,7 +1737,7 @@ int bdu_track_create(int64_t m, int64_t n, int64_t r, const double *U, const dou
         track_free(t);
         return BDU_EDEVICE;
     }
-    st = check_finite(t->mid, {{t->U[0], m * r}, {t->V[0], n * r}, {t->d, r}, {t->e, r - 1}}, s);
+    st = check_finite(t->mid[0], {{t->U[0], m * r}, {t->V[0], n * r}, {t->d, r}, {t->e, r - 1}}, s);
     if (st != BDU_OK) {
         track_free(t);
         return st;
@@ -1727,8 +1749,11 @@ int bdu_track_create(int64_t m, int64_t n, int64_t r, const double *U, const dou
 int bdu_track_update(bdu_track t, const double *b, const double *c)
 {
     if (!t || !b || !c) return BDU_EINVAL;
-    if (t->poisoned || t->mid->poisoned) return BDU_EDEVICE;
-    hipStream_t s = t->mid->stream;
+    if (t->poisoned) return BDU_EDEVICE;
+    for (bdu_handle h : t->mid)
+        if (h && h->poisoned) return BDU_EDEVICE;
+    bdu_ctx *m0 = t->mid[0];
+    hipStream_t s = m0->stream;
 #define TCHK(expr)                        \
     do {                                  \
         if ((expr) != hipSuccess) {       \
@@ -1736,33 +1761,79 @@ int bdu_track_update(bdu_track t, const double *b, const double *c)
             return BDU_EDEVICE;           \
         }                                 \
     } while (0)
-    TCHK(wait_dep(t->mid));
+    for (bdu_handle h : t->mid)
+        if (h) TCHK(wait_dep(h));
     TCHK(copy_in(t->b, b, sizeof(double) * t->m, s));
     TCHK(copy_in(t->c, c, sizeof(double) * t->n, s));
-    int st = check_finite(t->mid, {{t->b, t->m}, {t->c, t->n}}, s);
+    int st = check_finite(m0, {{t->b, t->m}, {t->c, t->n}}, s);
     if (st != BDU_OK) return st;
     const TrackSides sides = track_sides(t);
-    const int64_t rows = std::max(t->m, t->n);
-    // eq. (defup): projections, complements and their norms
-    TCHK(launch_track_project(sides, rows, t->r, t->part, s));
-    TCHK(launch_track_complement(sides, rows, t->npart, t->norms, s));
-    TCHK(hipMemcpyAsync(t->h_info, t->norms, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    const int64_t rows = std::max(t->m, t->n), r = t->r;
+    // eq. (defup): projections, complements and their squared norms
+    TCHK(launch_track_project(sides, rows, r, t->part, s));
+    TCHK(launch_track_complement(sides, rows, t->npart, t->sums, s));
+    TCHK(hipMemcpyAsync(t->h_sums, t->sums, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
     TCHK(hipStreamSynchronize(s));
-    if (!(t->h_info[0] > 0.0) || !(t->h_info[1] > 0.0)) return BDU_ESPAN;
-    // eq. (qrlr) and (equivlrup): one BGU pass on the middle matrix
-    TCHK(launch_track_scale(sides, rows, s));
-    const TrackMiddle mid = track_middle(t);
-    TCHK(launch_track_reset(mid, t->d, t->e, s));
-    st = bdu_update_projected(t->mid, t->bh, t->ch);
+    // a second pass for each side whose first complement kept less than
+    // half of the squared norm ("twice is enough", Kahan and Parlett)
+    double sum2[2] = {-1.0, -1.0};
+    int mask = 0;
+    for (int k = 0; k < 2; ++k)
+        if (!(2.0 * t->h_sums[2 * k + 1] >= t->h_sums[2 * k])) mask |= 1 << k;
+    if (mask) {
+        TrackSides again = sides;
+        for (int k = 0; k < 2; ++k) {
+            TrackSide &x = again.side[k];
+            x.x = x.xperp;  // project the complement, subtract in place
+            x.xhat = t->sh + k * r;
+            if (!((mask >> k) & 1)) x.rows = 0;  // this side keeps its first pass
+        }
+        TCHK(launch_track_project(again, rows, r, t->part, s));
+        TCHK(launch_track_complement(again, rows, t->npart, t->sums + 4, s));
+        TCHK(launch_track_accumulate(sides, t->sh, r, mask, s));
+        TCHK(hipMemcpyAsync(t->h_sums + 4, t->sums + 4, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+        TCHK(hipStreamSynchronize(s));
+        for (int k = 0; k < 2; ++k)
+            if ((mask >> k) & 1) sum2[k] = t->h_sums[4 + 2 * k + 1];
+    }
+    // a complement no larger than the worst-case rounding error of the
+    // projection sums, rows * 2^-53 * ||x||, carries no direction
+    double nrm[2];
+    for (int k = 0; k < 2; ++k) {
+        const double s0 = t->h_sums[2 * k], s1 = t->h_sums[2 * k + 1];
+        const double tau = (double)(k == 0 ? t->m : t->n) * 0x1p-53;
+        const double floor2 = tau * tau * s0;
+        if (2.0 * s1 >= s0)
+            nrm[k] = s1 > floor2 ? std::sqrt(s1) : 0.0;
+        else
+            nrm[k] = (sum2[k] > floor2 && 2.0 * sum2[k] >= s1) ? std::sqrt(sum2[k]) : 0.0;
+    }
+    const bool ab = nrm[0] > 0.0, ac = nrm[1] > 0.0;
+    if ((!ab || !ac) && r < 2) return BDU_ESPAN;  // no pass on a 2 x 1 or 1 x 1 matrix
+    // eq. (qrlr): the appended unit columns
+    TCHK(launch_track_scale(sides, rows, nrm[0], nrm[1], s));
+    // eq. (equivlrup): one BGU pass on the middle matrix (the r x (r+1) one
+    // as its reversed transpose)
+    const int which = (ab && ac) ? 0 : ((ab || ac) ? 1 : 2);
+    const int64_t pm = which == 2 ? r : r + 1, pn = which == 0 ? r + 1 : r;
+    st = track_mid(t, which, pm, pn);
+    if (st != BDU_OK) return st;
+    bdu_ctx *mh = t->mid[which];
+    TrackMiddle mid{mh->hd.Q, mh->hd.P, mh->hd.d, mh->hd.e, mh->hd.ldq, mh->hd.ldp, (int)pm, (int)pn,
+                    {ab ? 1 : 0, ac ? 1 : 0}, (!ab && ac) ? 1 : 0};
+    TCHK(launch_track_setup(mid, sides, t->d, t->e, r, nrm[0], nrm[1], t->mu, t->mv, s));
+    st = bdu_update_projected(mh, t->mu, t->mv);
     if (st != BDU_OK) {
         t->poisoned = true;
         return st;
     }
     // truncation and eq. (bdlrup)
     const int nxt = 1 - t->cur;
-    TCHK(launch_track_finish(sides, mid, t->d, t->e, t->kdrop, rows, t->r, t->U[nxt], t->V[nxt], s));
+    TCHK(launch_track_finish(sides, mid, t->d, t->e, t->kdrop, rows, r, t->U[nxt], t->V[nxt], s));
     TCHK(hipMemcpyAsync(t->h_k, t->kdrop, sizeof(int), hipMemcpyDeviceToHost, s));
     t->cur = nxt;
+    t->last_norm[0] = nrm[0];
+    t->last_norm[1] = nrm[1];
     t->have_last = true;
 #undef TCHK
     return BDU_OK;
@@ -1772,14 +1843,14 @@ int bdu_track_sync(bdu_track t)
 {
     if (!t) return BDU_EINVAL;
     if (t->poisoned) return BDU_EDEVICE;
-    return hipStreamSynchronize(t->mid->stream) == hipSuccess ? BDU_OK : BDU_EDEVICE;
+    return hipStreamSynchronize(t->mid[0]->stream) == hipSuccess ? BDU_OK : BDU_EDEVICE;
 }
 
 int bdu_track_read(bdu_track t, double *U, double *d, double *e, double *V)
 {
     if (!t) return BDU_EINVAL;
     if (t->poisoned) return BDU_EDEVICE;
-    hipStream_t s = t->mid->stream;
+    hipStream_t s = t->mid[0]->stream;
     if (hipStreamSynchronize(s) != hipSuccess) return BDU_EDEVICE;
     if (U && copy_out(U, t->U[t->cur], sizeof(double) * t->m * t->r, s) != hipSuccess) return BDU_EDEVICE;
     if (V && copy_out(V, t->V[t->cur], sizeof(double) * t->n * t->r, s) != hipSuccess) return BDU_EDEVICE;
@@ -1793,11 +1864,25 @@ int bdu_track_last(bdu_track t, double *delta, double *gamma, int64_t *dropped)
     if (!t) return BDU_EINVAL;
     if (t->poisoned) return BDU_EDEVICE;
     if (!t->have_last) return BDU_EINVAL;
-    if (hipStreamSynchronize(t->mid->stream) != hipSuccess) return BDU_EDEVICE;
-    if (delta) *delta = t->h_info[0];
-    if (gamma) *gamma = t->h_info[1];
+    if (hipStreamSynchronize(t->mid[0]->stream) != hipSuccess) return BDU_EDEVICE;
+    if (delta) *delta = t->last_norm[0];
+    if (gamma) *gamma = t->last_norm[1];
     if (dropped) *dropped = *t->h_k;
     return BDU_OK;
+}
+
+int bdu_track_last_projection(bdu_track t, double *bh, double *ch, double *qb, double *qc)
+{
+    if (!t) return BDU_EINVAL;
+    if (t->poisoned) return BDU_EDEVICE;
+    if (!t->have_last) return BDU_EINVAL;
+    hipStream_t s = t->mid[0]->stream;
+    if (hipStreamSynchronize(s) != hipSuccess) return BDU_EDEVICE;
+    if (bh && copy_out(bh, t->bh, sizeof(double) * t->r, s) != hipSuccess) return BDU_EDEVICE;
+    if (ch && copy_out(ch, t->ch, sizeof(double) * t->r, s) != hipSuccess) return BDU_EDEVICE;
+    if (qb && copy_out(qb, t->bp, sizeof(double) * t->m, s) != hipSuccess) return BDU_EDEVICE;
+    if (qc && copy_out(qc, t->cp, sizeof(double) * t->n, s) != hipSuccess) return BDU_EDEVICE;
+    return hipStreamSynchronize(s) == hipSuccess ? BDU_OK : BDU_EDEVICE;
 }
 
 int bdu_track_destroy(bdu_track t)

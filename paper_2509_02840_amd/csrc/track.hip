@@ -1,9 +1,10 @@
 // track.hip -- gfx950 kernels of the subspace-tracking update (Brust &
-// Saunders, Section 4, eqs. (lrup)-(bdlrup)): projections of b and c onto the
-// tracked bases and their complements, the middle matrix's inputs, the
-// truncation of the updated bidiagonal and the thin products.  The middle
-// (r+1) x (r+1) update itself is an ordinary BGU handle.  FP64; every sum is
-// a sequential fma in a stated order.
+// Saunders, Section 4, eqs. (lrup)-(bdlrup) and the unaugmented case after
+// them): projections of b and c onto the tracked bases and their
+// complements, the middle matrix's inputs, the truncation of the updated
+// bidiagonal and the thin products.  The middle update itself is an
+// ordinary BGU handle.  FP64; every sum is a sequential fma in a stated
+// order.
 #include <hip/hip_runtime.h>
 
 #include "primitives.h"
@@ -56,83 +57,130 @@ __global__ __launch_bounds__(64) void track_combine_kernel(TrackSides s, const d
 }
 
 // xperp_i = x_i - s_i, s_i = sum_j A(i, j) xhat_j (fma, j ascending); one
-// block per chunk of rows, one lane per row; lane 0 then sums the chunk's
-// xperp_i^2 in row order (fma from 0) into npart[side][chunk].
+// block per chunk of rows, one lane per row (x may be xperp itself: each
+// lane reads its entry before writing it); lane 0 then sums the chunk's
+// x_i^2 and xperp_i^2 in row order (fma from 0) into npart[side][chunk].
 // grid (chunks, 2 sides), kTrackChunk lanes.
 __global__ __launch_bounds__(kTrackChunk) void track_residual_kernel(TrackSides s, double *npart, int64_t nchunk)
 {
-    __shared__ double sq[kTrackChunk];
+    __shared__ double sq[kTrackChunk], sx[kTrackChunk];
     const TrackSide &t = s.side[blockIdx.y];
     const int64_t i0 = (int64_t)blockIdx.x * kTrackChunk;
     if (i0 >= t.rows) return;
     const int64_t i = i0 + threadIdx.x;
-    double xp = 0.0;
+    double xp = 0.0, xv = 0.0;
     if (i < t.rows) {
         double acc = 0.0;
         for (int64_t j = 0; j < t.cols; ++j) acc = fma(t.A[i + j * t.lda], t.xhat[j], acc);
-        xp = t.x[i] - acc;
+        xv = t.x[i];
+        xp = xv - acc;
         t.xperp[i] = xp;
     }
     sq[threadIdx.x] = xp;
+    sx[threadIdx.x] = xv;
     __syncthreads();
     if (threadIdx.x == 0) {
         const int cnt = t.rows - i0 < kTrackChunk ? (int)(t.rows - i0) : kTrackChunk;
-        double p = 0.0;
-        for (int q = 0; q < cnt; ++q) p = fma(sq[q], sq[q], p);
-        npart[(int64_t)blockIdx.y * nchunk + blockIdx.x] = p;
+        double p = 0.0, px = 0.0;
+        for (int q = 0; q < cnt; ++q) {
+            px = fma(sx[q], sx[q], px);
+            p = fma(sq[q], sq[q], p);
+        }
+        npart[2 * ((int64_t)blockIdx.y * nchunk + blockIdx.x)] = px;
+        npart[2 * ((int64_t)blockIdx.y * nchunk + blockIdx.x) + 1] = p;
     }
 }
 
-// norm = sqrt(sum over chunks (ascending, from 0) of npart): lane 0 for
-// side 0, lane 1 for side 1.  The norm becomes the last entry of the middle
-// update vector and is copied to norms[side].
-__global__ __launch_bounds__(64) void track_norm_kernel(TrackSides s, const double *npart, int64_t nchunk,
-                                                        double *norms)
+// sums[2 side] = x^T x, sums[2 side + 1] = xperp^T xperp: the chunk
+// partials added in ascending order from 0.  Lanes 0 and 1: the two sides.
+__global__ __launch_bounds__(64) void track_sums_kernel(TrackSides s, const double *npart, int64_t nchunk,
+                                                        double *sums)
 {
     const int side = threadIdx.x;
     if (side > 1) return;
     const TrackSide &t = s.side[side];
     const int64_t nk = (t.rows + kTrackChunk - 1) / kTrackChunk;
-    double total = 0.0;
-    for (int64_t k = 0; k < nk; ++k) total = total + npart[(int64_t)side * nchunk + k];
-    const double nrm = sqrt(total);
-    t.xhat[t.cols] = nrm;
-    norms[side] = nrm;
+    double tx = 0.0, tp = 0.0;
+    for (int64_t k = 0; k < nk; ++k) {
+        tx = tx + npart[2 * ((int64_t)side * nchunk + k)];
+        tp = tp + npart[2 * ((int64_t)side * nchunk + k) + 1];
+    }
+    sums[2 * side] = tx;
+    sums[2 * side + 1] = tp;
 }
 
-// w_i = xperp_i / norm (in place).  grid (ceil(rows / 256), 2 sides).
-__global__ __launch_bounds__(256) void track_scale_kernel(TrackSides s)
+// xhat += add for the sides in mask (bit side).  grid (ceil(cols / 64), 2).
+__global__ __launch_bounds__(64) void track_accumulate_kernel(TrackSides s, const double *add, int64_t r, int mask)
+{
+    const int side = blockIdx.y;
+    if (!((mask >> side) & 1)) return;
+    const int64_t j = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    if (j >= r) return;
+    s.side[side].xhat[j] = s.side[side].xhat[j] + add[side * r + j];
+}
+
+// w_i = xperp_i / norm (in place) for each side with a positive norm.
+// grid (ceil(rows / 256), 2 sides).
+__global__ __launch_bounds__(256) void track_scale_kernel(TrackSides s, double delta, double gamma)
 {
     const TrackSide &t = s.side[blockIdx.y];
+    const double nrm = blockIdx.y == 0 ? delta : gamma;
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= t.rows) return;
-    t.xperp[i] = t.xperp[i] / t.xhat[t.cols];
+    if (!(nrm > 0.0) || i >= t.rows) return;
+    t.xperp[i] = t.xperp[i] / nrm;
 }
 
-// The middle factorization before its update: Q = P = I (R x R, leading
-// dimensions ldq, ldp), d = [d; 0], e = [e; 0].  grid (R), R <= 1024 lanes.
-__global__ void track_reset_kernel(TrackMiddle mid, const double *d, const double *e)
+// The middle factorization before its pass: Q = I (pm x pm, leading
+// dimension ldq), P = I (pn x pn), and
+//   not flipped: d = [d; 0], e = [e; 0] (pn and pn - 1 entries),
+//                u = [b_hat; delta] (pm), v = [c_hat; gamma] (pn);
+//   flipped:     d, e reversed (r, r - 1 entries), u = [J c_hat; gamma],
+//                v = J b_hat (J: reversal of r entries).
+// grid (pm), up to 1024 lanes.
+__global__ void track_setup_kernel(TrackMiddle mid, TrackSides s, const double *d, const double *e, int r,
+                                   double delta, double gamma, double *u, double *v)
 {
     const int col = blockIdx.x;
-    for (int i = threadIdx.x; i < mid.R; i += blockDim.x) {
+    for (int i = threadIdx.x; i < mid.pm; i += blockDim.x) {
         mid.Q[i + (int64_t)col * mid.ldq] = i == col ? 1.0 : 0.0;
-        mid.P[i + (int64_t)col * mid.ldp] = i == col ? 1.0 : 0.0;
+        if (col < mid.pn && i < mid.pn) mid.P[i + (int64_t)col * mid.ldp] = i == col ? 1.0 : 0.0;
     }
-    if (col == 0)
-        for (int i = threadIdx.x; i < mid.R; i += blockDim.x) {
-            mid.d[i] = i < mid.R - 1 ? d[i] : 0.0;
-            if (i < mid.R - 1) mid.e[i] = i < mid.R - 2 ? e[i] : 0.0;
+    if (col != 0) return;
+    const double *bh = s.side[0].xhat, *ch = s.side[1].xhat;
+    for (int i = threadIdx.x; i < mid.pm; i += blockDim.x) {
+        if (!mid.flip) {
+            u[i] = i < r ? bh[i] : delta;
+            if (i < mid.pn) {
+                v[i] = i < r ? ch[i] : gamma;
+                mid.d[i] = i < r ? d[i] : 0.0;
+                if (i + 1 < mid.pn) mid.e[i] = i + 1 < r ? e[i] : 0.0;
+            }
+        } else {
+            u[i] = i < r ? ch[r - 1 - i] : gamma;
+            if (i < r) {
+                v[i] = bh[r - 1 - i];
+                mid.d[i] = d[r - 1 - i];
+                if (i + 1 < r) mid.e[i] = e[r - 2 - i];
+            }
         }
+    }
 }
 
-// Drop the row and column k of the updated R x R bidiagonal with the
-// smallest column norm (d_k^2 + e_{k-1}^2 as fma(d_k, d_k, e_{k-1} e_{k-1});
-// ties drop the highest k): d, e of the tracked factorization become the
-// kept entries, with 0 joining k-1 and k+1.  One lane.
-__global__ void track_truncate_kernel(TrackMiddle mid, double *d, double *e, int *kdrop)
+// The tracked bidiagonal after the pass.  Both sides augmented: drop the
+// row and column k of the (r+1) x (r+1) result with the smallest column
+// norm (d_k^2 + e_{k-1}^2 as fma(d_k, d_k, e_{k-1} e_{k-1}); ties drop the
+// highest k), with 0 joining k-1 and k+1.  Otherwise the r x r result as it
+// is (reversed back when flipped) and k = -1.  One lane.
+__global__ void track_truncate_kernel(TrackMiddle mid, int r, double *d, double *e, int *kdrop)
 {
     if (threadIdx.x != 0) return;
-    const int R = mid.R;
+    if (!(mid.aug[0] && mid.aug[1])) {
+        for (int j = 0; j < r; ++j) d[j] = mid.d[mid.flip ? r - 1 - j : j];
+        for (int j = 0; j + 1 < r; ++j) e[j] = mid.e[mid.flip ? r - 2 - j : j];
+        *kdrop = -1;
+        return;
+    }
+    const int R = r + 1;
     int k = R - 1;
     double best = fma(mid.d[R - 1], mid.d[R - 1], mid.e[R - 2] * mid.e[R - 2]);
     for (int j = R - 2; j >= 0; --j) {
@@ -150,23 +198,34 @@ __global__ void track_truncate_kernel(TrackMiddle mid, double *d, double *e, int
     }
 }
 
-// out(i, j) = sum_{l < r} A(i, l) M(l, kj) + w_i M(r, kj), each term an fma
-// in that order, kj = j for j < k and j + 1 otherwise (M = the middle Q for
-// side 0, P for side 1).  grid (ceil(rows / 256), r, 2 sides).
+// out(i, j) = sum_{l < r} A(i, l) M(rm(l), cm(j)) [+ w_i M(r, cm(j))], each
+// term an fma in that order.  Not flipped: M is the middle Q for side 0 and
+// P for side 1, rm(l) = l, cm(j) = j, or j + 1 from the dropped index k on,
+// and w (the unit complement) only on an augmented side.  Flipped
+// (U2 = U J P3 J, V2 = [V, w] diag(J,1) Q3(:, 1:r) J): M is the middle P
+// for side 0 and Q for side 1, rm(l) = r - 1 - l, cm(j) = r - 1 - j, and w
+// on side 1 only.  grid (ceil(rows / 256), r, 2 sides).
 __global__ __launch_bounds__(256) void track_product_kernel(TrackSides s, TrackMiddle mid, const int *kdrop,
                                                             double *out0, double *out1)
 {
-    const TrackSide &t = s.side[blockIdx.z];
+    const int side = blockIdx.z;
+    const TrackSide &t = s.side[side];
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= t.rows) return;
     const int j = blockIdx.y;
+    const int r = (int)t.cols;
     const int k = *kdrop;
-    const int kj = j < k ? j : j + 1;
-    const double *M = blockIdx.z == 0 ? mid.Q + (int64_t)kj * mid.ldq : mid.P + (int64_t)kj * mid.ldp;
+    const bool useQ = mid.flip ? side == 1 : side == 0;
+    const int cj = mid.flip ? r - 1 - j : (k >= 0 && j >= k ? j + 1 : j);
+    const double *M = useQ ? mid.Q + (int64_t)cj * mid.ldq : mid.P + (int64_t)cj * mid.ldp;
+    const bool with_w = mid.flip ? side == 1 : mid.aug[side] != 0;
     double acc = 0.0;
-    for (int64_t l = 0; l < t.cols; ++l) acc = fma(t.A[i + l * t.lda], M[l], acc);
-    acc = fma(t.xperp[i], M[t.cols], acc);
-    (blockIdx.z == 0 ? out0 : out1)[i + (int64_t)j * t.lda] = acc;
+    if (mid.flip)
+        for (int l = 0; l < r; ++l) acc = fma(t.A[i + (int64_t)l * t.lda], M[r - 1 - l], acc);
+    else
+        for (int l = 0; l < r; ++l) acc = fma(t.A[i + (int64_t)l * t.lda], M[l], acc);
+    if (with_w) acc = fma(t.xperp[i], M[r], acc);
+    (side == 0 ? out0 : out1)[i + (int64_t)j * t.lda] = acc;
 }
 
 hipError_t launch_track_project(const TrackSides &s, int64_t max_rows, int64_t r, double *part, hipStream_t st)
@@ -179,32 +238,41 @@ hipError_t launch_track_project(const TrackSides &s, int64_t max_rows, int64_t r
     return hipGetLastError();
 }
 
-hipError_t launch_track_complement(const TrackSides &s, int64_t max_rows, double *npart, double *norms,
+hipError_t launch_track_complement(const TrackSides &s, int64_t max_rows, double *npart, double *sums,
                                    hipStream_t st)
 {
     const int64_t nchunk = (max_rows + kTrackChunk - 1) / kTrackChunk;
     hipLaunchKernelGGL(track_residual_kernel, dim3((unsigned)nchunk, 2), dim3(kTrackChunk), 0, st, s, npart, nchunk);
-    hipLaunchKernelGGL(track_norm_kernel, dim3(1), dim3(64), 0, st, s, (const double *)npart, nchunk, norms);
+    hipLaunchKernelGGL(track_sums_kernel, dim3(1), dim3(64), 0, st, s, (const double *)npart, nchunk, sums);
     return hipGetLastError();
 }
 
-hipError_t launch_track_scale(const TrackSides &s, int64_t max_rows, hipStream_t st)
+hipError_t launch_track_accumulate(const TrackSides &s, const double *add, int64_t r, int mask, hipStream_t st)
 {
-    hipLaunchKernelGGL(track_scale_kernel, dim3((unsigned)((max_rows + 255) / 256), 2), dim3(256), 0, st, s);
+    hipLaunchKernelGGL(track_accumulate_kernel, dim3((unsigned)((r + 63) / 64), 2), dim3(64), 0, st, s, add, r,
+                       mask);
     return hipGetLastError();
 }
 
-hipError_t launch_track_reset(const TrackMiddle &mid, const double *d, const double *e, hipStream_t st)
+hipError_t launch_track_scale(const TrackSides &s, int64_t max_rows, double delta, double gamma, hipStream_t st)
 {
-    hipLaunchKernelGGL(track_reset_kernel, dim3(mid.R), dim3(mid.R < 1024 ? ((mid.R + 63) / 64) * 64 : 1024), 0, st,
-                       mid, d, e);
+    hipLaunchKernelGGL(track_scale_kernel, dim3((unsigned)((max_rows + 255) / 256), 2), dim3(256), 0, st, s, delta,
+                       gamma);
+    return hipGetLastError();
+}
+
+hipError_t launch_track_setup(const TrackMiddle &mid, const TrackSides &s, const double *d, const double *e,
+                              int64_t r, double delta, double gamma, double *u, double *v, hipStream_t st)
+{
+    hipLaunchKernelGGL(track_setup_kernel, dim3(mid.pm), dim3(mid.pm < 1024 ? ((mid.pm + 63) / 64) * 64 : 1024), 0,
+                       st, mid, s, d, e, (int)r, delta, gamma, u, v);
     return hipGetLastError();
 }
 
 hipError_t launch_track_finish(const TrackSides &s, const TrackMiddle &mid, double *d, double *e, int *kdrop,
                                int64_t max_rows, int64_t r, double *out0, double *out1, hipStream_t st)
 {
-    hipLaunchKernelGGL(track_truncate_kernel, dim3(1), dim3(64), 0, st, mid, d, e, kdrop);
+    hipLaunchKernelGGL(track_truncate_kernel, dim3(1), dim3(64), 0, st, mid, (int)r, d, e, kdrop);
     hipLaunchKernelGGL(track_product_kernel, dim3((unsigned)((max_rows + 255) / 256), (unsigned)r, 2), dim3(256), 0,
                        st, s, mid, kdrop, out0, out1);
     return hipGetLastError();

@@ -162,8 +162,8 @@ def tracking_state(m: int, n: int, r: int, seed: int):
     V (n x r) with orthonormal columns (Q factors of the Householder QR of
     N(0,1) matrices), d ~ U(1, 10) sorted descending (a dominant subspace),
     e ~ U(0, 1).  Returns (U, d, e, V), column-major."""
-    if r < 1 or m < r + 1 or n < r + 1:
-        raise ValueError("need m, n >= r + 1 >= 2")
+    if r < 1 or m < r or n < r:
+        raise ValueError("need m, n >= r >= 1")
     rng = np.random.default_rng(seed)
     U, _ = np.linalg.qr(rng.standard_normal((m, r)))
     V, _ = np.linalg.qr(rng.standard_normal((n, r)))
@@ -177,3 +177,25 @@ def tracking_update(m: int, n: int, seed: int, scale: float = 1.0):
     c ~ N(0,1) / sqrt(n)."""
     rng = np.random.default_rng(seed)
     return (rng.standard_normal(m) * scale / math.sqrt(m), rng.standard_normal(n) / math.sqrt(n))
+
+
+def zero_start_tracking(m: int, n: int, r: int):
+    """The zero start of the paper's streaming experiments (Section 4): A0 = 0,
+    U0 = I_m(:, 1:r), V0 = I_n(:, 1:r), B0 = 0.  Returns (U, d, e, V)."""
+    U = np.asfortranarray(np.eye(m)[:, :r])
+    V = np.asfortranarray(np.eye(n)[:, :r])
+    return U, np.zeros(r), np.zeros(max(r - 1, 0)), V
+
+
+def link_stream(m: int, n: int, steps: int, seed: int, density: float = 0.05):
+    """A link-prediction-shaped update stream (Section 4): at step h, b_h has
+    entries in {0, 1} (each 1 with probability density) and c_h = e_{h mod n}.
+    Returns a list of (b, c)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for h in range(steps):
+        b = (rng.random(m) < density).astype(np.float64)
+        c = np.zeros(n)
+        c[h % n] = 1.0
+        out.append((b, c))
+    return out

@@ -161,7 +161,7 @@ def _staged_protocol_violations(K0, NW, lmax, RC=15, NCS=3):
     at every front f (a front early); the memory wavefront writes columns
     0..6 before the first barrier and 3F+7..3F+9 at front F, stores the
     columns the last wavefront finished at F-1, and writes the coefficients
-    of front F+1 at front F."""
+    of front F+2 at front F, which compute wavefronts read a front early."""
     U = S = K0 + 3
     lam_hi = lmax + 1
     fend = lmax // 3 + K0 + 1
@@ -197,11 +197,24 @@ def _staged_protocol_violations(K0, NW, lmax, RC=15, NCS=3):
                 lam = 3 * (f - K0 + 1) + k
                 if lam >= 0:
                     put(w + 1, lam % RC, F, "w", lam, 0)
-    coef = {0: [(PRO, 0, "w", 0)]}
+    # coefficients: the prologue writes fronts 0 and 1, the memory wavefront
+    # writes front F + 2 at front F; compute wavefront w reads front w S at
+    # its first live front and front F + 1 at every live front F (a front
+    # early, into registers)
+    coef = {}
+    for F0 in range(min(2, nfront)):
+        coef.setdefault(F0 % NCS, []).append((PRO, 0, "w", F0))
     for F in range(nfront):
-        if F + 1 < nfront:
-            coef.setdefault((F + 1) % NCS, []).append((F, 0, "w", F + 1))
-        coef.setdefault(F % NCS, []).append((F, 1, "r", F))
+        if F + 2 < nfront:
+            coef.setdefault((F + 2) % NCS, []).append((F, 0, "w", F + 2))
+    for w in range(NW):
+        live_end = min(w + (flush_end + U) // U, nchunk)
+        if live_end * U <= w * S:
+            continue
+        coef.setdefault((w * S) % NCS, []).append((w * S, 1, "r", w * S))
+        for F in range(w * S, live_end * U):
+            if F + 1 < nfront:
+                coef.setdefault((F + 1) % NCS, []).append((F, 1, "r", F + 1))
 
     def barrier_between(a, b):  # the barrier after some front B, a <= B < b
         return a < b
@@ -253,8 +266,11 @@ def test_tracking_rejects_bad_sizes_without_a_device():
     d = np.ones(3)
     e = np.ones(2)
     V = np.zeros((5, 3), order="F")
-    # r + 1 > m
-    assert L.bdu_track_create(3, 5, 3, U.ctypes.data, d.ctypes.data, e.ctypes.data, V.ctypes.data,
+    # r > m
+    assert L.bdu_track_create(2, 5, 3, U.ctypes.data, d.ctypes.data, e.ctypes.data, V.ctypes.data,
+                              ctypes.byref(h)) == bdu.BDU_EINVAL
+    # r > n
+    assert L.bdu_track_create(4, 2, 3, U.ctypes.data, d.ctypes.data, e.ctypes.data, V.ctypes.data,
                               ctypes.byref(h)) == bdu.BDU_EINVAL
     # r = 0
     assert L.bdu_track_create(4, 5, 0, U.ctypes.data, d.ctypes.data, e.ctypes.data, V.ctypes.data,
