@@ -11,7 +11,7 @@
  * generate the rotations that fold u v^T into Bd and chase the fill back to
  * bidiagonal form, and accumulate them into Q and P (eq. bidiagplus).  A
  * rank-r update is r rank-1 passes in column order, each projecting its
- * column with the current Q and P (Section 3.1).
+ * column with the current Q and P (Section 3.2, eq. (rk1)).
  *
  * Everything is FP64.  The numbers produced are exactly those of the
  * schedule and rounding conventions the library documents: projections are
@@ -189,7 +189,7 @@ int bdu_handle_tiling(bdu_handle h, int *k0, int *nw, int *rpl);
 /* Serving (the served form of the update): resident streams admitted
  * against a device-memory budget, bounded per-stream request queues, and a
  * worker thread that batches continuously at the granularity of rank-1
- * passes (a rank-r request is r passes, Section 3.1).  Each round the worker
+ * passes (a rank-r request is r passes, Section 3.2, eq. (rk1)).  Each round the worker
  * takes the next pass of the oldest pending request of up to max_batch
  * streams (oldest first) and runs them as one batched rank-1 update, so
  * every stream's passes are applied in submission order and each result is
@@ -269,7 +269,7 @@ int bdu_orth_error(bdu_handle h, double *eq, double *ep);
  * the drift measured before the step. */
 int bdu_reorthogonalize(bdu_handle h, double tol, double *eq, double *ep);
 
-/* ---- truncated bidiagonal approximation (Section 2) ------------------- */
+/* ---- truncated bidiagonal approximation (Section 1.3) ----------------- */
 
 /* The best rank-r truncated bidiagonal approximation of the handle's
  * A = Q Bd P^T (eqs. (trBD), (errtrBD)): keep the r columns i of Bd (0-based)

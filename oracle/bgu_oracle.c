@@ -25,7 +25,7 @@
  *    second superdiagonal entry (j,j+2), each followed by a down-right chase;
  *    for m = n this starts the 2n-3 bulge chases the paper counts.
  *  - Rank r is r rank-1 passes, each projecting its column with the current
- *    Q and P (Section 3.1, "repeating the process").
+ *    Q and P (Section 3.2, eq. (rk1), "repeating the process").
  *  - Floating point: explicit fma where written, every other operation
  *    rounded on its own (built with -ffp-contract=off), IEEE sqrt and division.
  */

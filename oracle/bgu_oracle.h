@@ -86,7 +86,7 @@ int orc_bgu_pass_rows(int64_t m, int64_t n, double *Q, int64_t qrows,
                       int flags, orc_rot *trace, int64_t trace_cap,
                       int64_t *counts);
 
-/* Rank-r update A + B C^T (eq. main) as r rank-1 passes (Section 3.1): for
+/* Rank-r update A + B C^T (eq. main) as r rank-1 passes (Section 3.2, eq. (rk1)): for
  * column i = 1..r, u = Q^T B(:,i), v = P^T C(:,i) with the current Q, P,
  * then one pass.  B is m x r (ldb), C is n x r (ldc). */
 int orc_bgu_update(int64_t m, int64_t n, double *Q, int64_t ldq, double *d,

@@ -344,7 +344,7 @@ def reorth_step(X):
     return X - (X @ orth_gram(X)) / 2.0
 
 
-# ---- truncated bidiagonal approximation (Section 2, eqs. (trBD), (errtrBD)) --
+# ---- truncated bidiagonal approximation (Section 1.3, eqs. (trBD), (errtrBD)) --
 
 def truncated_bd(Q, d, e, P, r: int):
     """Best rank-r truncated bidiagonal approximation of A = Q Bd P^T: keep

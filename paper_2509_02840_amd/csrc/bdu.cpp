@@ -1437,7 +1437,7 @@ int bdu_reorthogonalize(bdu_handle h, double tol, double *eq, double *ep)
 
 }  // extern "C"
 
-// ---- truncated bidiagonal approximation (Section 2) -----------------------------
+// ---- truncated bidiagonal approximation (Section 1.3) ---------------------------
 
 extern "C" int bdu_truncated_bd(bdu_handle h, int64_t r, int64_t *idx, double *err2, double *Qr, double *Pr)
 {

@@ -1,6 +1,6 @@
 // primitives.h -- device-side pieces shared by the generation and
 // application kernels: address-space casts, the rotation generator and the
-// rotation (Section 2, the Givens rotation equations).
+// rotation (Section 3.4, eqs. (giv), (giv1)).
 //
 // Rounding: every operation is rounded on its own (-ffp-contract=off);
 // fma only where written; sqrt and division are IEEE.

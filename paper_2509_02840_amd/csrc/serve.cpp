@@ -2,7 +2,7 @@
 // a device-memory budget, bounded per-stream queues and continuous batching.
 //
 // One worker thread owns the GPU work.  A rank-r request is r rank-1 passes
-// (Section 3.1), and rounds batch passes, not requests: each round takes,
+// (Section 3.2, eq. (rk1)), and rounds batch passes, not requests: each round takes,
 // from every stream with pending work (up to max_batch streams, oldest
 // request first), the next pass of the stream's oldest request and runs them
 // together as one batched rank-1 update (bdu_update_batched).  A stream's

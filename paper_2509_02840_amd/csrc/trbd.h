@@ -1,5 +1,5 @@
 // trbd.h -- truncated bidiagonal approximation of a handle's factorization
-// (Section 2, eqs. (trBD), (errtrBD)).
+// (Section 1.3, eqs. (trBD), (errtrBD)).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>

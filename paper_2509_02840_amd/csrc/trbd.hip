@@ -1,5 +1,5 @@
 // trbd.hip -- gfx950 kernels of the truncated bidiagonal approximation
-// (Section 2, eqs. (trBD), (errtrBD)): A = Q Bd P^T is approximated by the r
+// (Section 1.3, eqs. (trBD), (errtrBD)): A = Q Bd P^T is approximated by the r
 // columns i of Bd with the largest t_i = d_i^2 + e_{i-1}^2 (e_0 = 0), as
 // A_r = Qr Pr^T with Qr(:, j) = d_i q_i + e_{i-1} q_{i-1}, Pr(:, j) = p_i;
 // the squared error is the sum of the dropped t_i.  Every product and sum is

@@ -1,4 +1,4 @@
-"""Truncated bidiagonal approximation (Section 2, eqs. (trBD), (errtrBD)) on
+"""Truncated bidiagonal approximation (Section 1.3, eqs. (trBD), (errtrBD)) on
 the GPU, bit for bit against the oracle."""
 import numpy as np
 import pytest

@@ -1,4 +1,4 @@
-"""Pins of the oracle's truncated bidiagonal approximation (Section 2,
+"""Pins of the oracle's truncated bidiagonal approximation (Section 1.3,
 eqs. (trBD) and (errtrBD)) against dense products and the SVD."""
 import itertools
 
