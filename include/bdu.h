@@ -46,7 +46,7 @@ enum {
     BDU_EDEVICE = -3,    /* a HIP call failed; the handle is poisoned */
     BDU_ENONFINITE = -4, /* a NaN or infinite input was rejected (bdu_set_finite_check) */
     BDU_EBUSY = -5,      /* serving queue full */
-    BDU_ESPAN = -6       /* tracking: b or c lies in the span of the tracked basis */
+    BDU_ESPAN = -6       /* tracking: r = 1 with b or c in the span of the tracked basis */
 };
 
 /* Create a handle from A = Q Bd P^T (eq. bidiag).  Requires m >= n >= 2.

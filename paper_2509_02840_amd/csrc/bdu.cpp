@@ -378,12 +378,13 @@ int panels_of(const bdu_ctx *h)
     return (int)((h->m + ph - 1) / ph + (h->n + ph - 1) / ph);
 }
 
-int pass_single(bdu_ctx *h, int pass, bool project)
+int pass_single(bdu_ctx *h, int pass, bool project, const double *xb = nullptr, const double *xc = nullptr)
 {
     hipError_t e = hipSuccess;
     hipStream_t st = h->stream;
     if (project)
-        e = timed(ST_PROJECT, st, [&] { return launch_project(h->d_self, 1, tiles_of(h), Gate{nullptr, pass}, st); });
+        e = timed(ST_PROJECT, st,
+                  [&] { return launch_project(h->d_self, 1, tiles_of(h), Gate{nullptr, pass, 0, xb, xc}, st); });
     const int64_t lds = gen_lds_bytes(h->n, h->plan->N);
     const int L = h->plan->L, np = panels_of(h), k0 = h->plan->K0, nw = h->plan->NW;
     if (e == hipSuccess && h->side && h->plan->nseg > 0 && h->seg[0]) {
@@ -655,7 +656,7 @@ const char *bdu_strerror(int status)
     case BDU_EDEVICE: return "device error (handle poisoned)";
     case BDU_ENONFINITE: return "non-finite input";
     case BDU_EBUSY: return "queue full";
-    case BDU_ESPAN: return "update vector in the span of the tracked basis";
+    case BDU_ESPAN: return "rank-1 tracker with an update vector in the span of its basis";
     default: return "unknown status";
     }
 }

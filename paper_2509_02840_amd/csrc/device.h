@@ -45,6 +45,9 @@ struct Gate {
     const int32_t *ranks;
     int32_t pass;
     int32_t part;
+    // staged update columns of a single-handle launch when not null (m x r
+    // and n x r, column-major); otherwise the handle's own staging bst, cst
+    const double *xb, *xc;
 };
 
 // Applier blocks [*bbeg, *bend) of a part, and whether it applies the spike.

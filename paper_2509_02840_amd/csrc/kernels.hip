@@ -54,10 +54,12 @@ __global__ __launch_bounds__(64) void project_kernel(HandleDev *const *hs, Gate 
     GLOBAL double *out;
     int rows, ld;
     if (tile < qt) {
-        A = gptr(h->Q); x = gptr(h->bst) + (int64_t)pass * m; out = gptr(h->u); rows = m; ld = h->ldq;
+        A = gptr(h->Q); x = gptr(gate.xb ? gate.xb : h->bst) + (int64_t)pass * m; out = gptr(h->u); rows = m;
+        ld = h->ldq;
     } else {
         tile -= qt;
-        A = gptr(h->P); x = gptr(h->cst) + (int64_t)pass * n; out = gptr(h->v); rows = n; ld = h->ldp;
+        A = gptr(h->P); x = gptr(gate.xc ? gate.xc : h->cst) + (int64_t)pass * n; out = gptr(h->v); rows = n;
+        ld = h->ldp;
     }
     const int cols = rows;
     __shared__ double tileA[64 * 65];
