@@ -46,7 +46,8 @@ enum {
     BDU_EDEVICE = -3,    /* a HIP call failed; the handle is poisoned */
     BDU_ENONFINITE = -4, /* a NaN or infinite input was rejected (bdu_set_finite_check) */
     BDU_EBUSY = -5,      /* serving queue full */
-    BDU_ESPAN = -6       /* tracking: r = 1 with b or c in the span of the tracked basis */
+    BDU_ESPAN = -6,      /* tracking: r = 1 with b or c in the span of the tracked basis */
+    BDU_ESCRATCH = -7    /* bdu_update_noalloc: r (m + n) exceeds bdu_noalloc_capacity() */
 };
 
 /* Create a handle from A = Q Bd P^T (eq. bidiag).  Requires m >= n >= 2.
@@ -62,6 +63,22 @@ int bdu_create(int64_t m, int64_t n, const double *Q, const double *d,
  * call returns, device inputs must stay valid until the stream reaches the
  * update (bdu_sync). */
 int bdu_update(bdu_handle h, const double *B, const double *C, int r);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * update as bdu_update, with the same results bit for bit, but B and C are
+ * staged in a fixed device array of bdu_noalloc_capacity() doubles
+ * (8 MiB) that the library holds on each device until the process ends,
+ * instead of the handle's staging buffers, which bdu_update grows with
+ * hipMalloc when r exceeds their capacity.  No allocation or free is made.
+ * Requires r (m + n) <= bdu_noalloc_capacity(); BDU_ESCRATCH otherwise,
+ * with nothing changed.  Every call on one device shares that device's
+ * array, which keeps the last call's contents: calls that overlap on one
+ * device (different streams, no synchronization between them) race and
+ * must be serialized by the caller.  Call with the handle's device
+ * current.  Other errors as bdu_update. */
+int bdu_update_noalloc(bdu_handle h, const double *B, const double *C, int r);
+int64_t bdu_noalloc_capacity(void);
 
 /* Same as bdu_update on each handle in turn (results are bit-identical to
  * that loop), but every stage of every handle is issued as one launch over

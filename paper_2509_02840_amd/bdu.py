@@ -22,6 +22,7 @@ BDU_EDEVICE = -3
 BDU_ENONFINITE = -4
 BDU_EBUSY = -5
 BDU_ESPAN = -6
+BDU_ESCRATCH = -7
 
 
 class BduError(RuntimeError):
@@ -46,6 +47,10 @@ def lib():
         L.bdu_update_batched.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                          ctypes.POINTER(i32), i32]
         L.bdu_update_projected.argtypes = [vp, vp, vp]
+        L.bdu_update_noalloc.argtypes = [vp, vp, vp, i32]
+        L.bdu_update_noalloc.restype = i32
+        L.bdu_noalloc_capacity.argtypes = []
+        L.bdu_noalloc_capacity.restype = i64
         L.bdu_project.argtypes = [vp, vp, vp, vp, vp]
         L.bdu_read.argtypes = [vp, vp, vp, vp, vp]
         L.bdu_last_rotations.argtypes = [vp, vp, vp, vp, vp, i64]
@@ -310,6 +315,12 @@ class Handle:
     def update(self, B, C) -> None:
         pb, pc, r = _pair(B, C, self.m, self.n)
         _check(lib().bdu_update(self._h, pb, pc, r), "bdu_update")
+
+    def update_noalloc(self, B, C) -> None:
+        """bdu_update_noalloc: the same update, staged in the library's fixed
+        device scratch (no allocation)."""
+        pb, pc, r = _pair(B, C, self.m, self.n)
+        _check(lib().bdu_update_noalloc(self._h, pb, pc, r), "bdu_update_noalloc")
 
     def update_projected(self, u, v) -> None:
         _check(lib().bdu_update_projected(self._h, _arg(u, (self.m,), "u"), _arg(v, (self.n,), "v")),

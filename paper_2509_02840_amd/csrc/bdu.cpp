@@ -657,6 +657,7 @@ const char *bdu_strerror(int status)
     case BDU_ENONFINITE: return "non-finite input";
     case BDU_EBUSY: return "queue full";
     case BDU_ESPAN: return "rank-1 tracker with an update vector in the span of its basis";
+    case BDU_ESCRATCH: return "update larger than the no-allocation scratch (bdu_noalloc_capacity)";
     default: return "unknown status";
     }
 }
@@ -885,6 +886,68 @@ int bdu_update(bdu_handle h, const double *B, const double *C, int r)
     if (st != BDU_OK) return st;
     for (int p = 0; p < r; ++p) {
         st = pass_single(h, p, true);
+        if (st != BDU_OK) return st;
+    }
+    return BDU_OK;
+}
+
+// ---- update without allocation -----------------------------------------------
+//
+// bdu_update_noalloc stages B and C in a fixed device array instead of the
+// handle's staging buffers, which bdu_update grows with hipMalloc when r
+// exceeds their capacity.  In host code `scratch` names a host-side stand-in
+// of the array; its device address is looked up once per device with
+// hipGetSymbolAddress, and only that address is ever given to the runtime
+// or a kernel.
+
+}  // extern "C"
+
+namespace {
+
+constexpr int64_t kScratchDoubles = (int64_t)1 << 20;  // 8 MiB per device
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+std::mutex g_scratch_mu;
+std::map<int, double *> g_scratch_ptr;  // device ordinal -> address of scratch
+
+// The current device's copy of scratch (looked up on the first call there).
+int scratch_ptr(double **out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return BDU_EDEVICE;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it == g_scratch_ptr.end()) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return BDU_EDEVICE;
+        it = g_scratch_ptr.emplace(dev, (double *)p).first;
+    }
+    *out = it->second;
+    return BDU_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t bdu_noalloc_capacity(void) { return kScratchDoubles; }
+
+int bdu_update_noalloc(bdu_handle h, const double *B, const double *C, int r)
+{
+    if (!h || !B || !C || r < 1) return BDU_EINVAL;
+    if (h->poisoned) return BDU_EDEVICE;
+    if ((int64_t)r * (h->m + h->n) > kScratchDoubles) return BDU_ESCRATCH;
+    double *xs = nullptr;
+    int st = scratch_ptr(&xs);
+    if (st != BDU_OK) return st;
+    HIPCHK(h, wait_dep(h));
+    double *xb = xs, *xc = xs + h->m * r;
+    HIPCHK(h, copy_in(xb, B, sizeof(double) * h->m * r, h->stream));
+    HIPCHK(h, copy_in(xc, C, sizeof(double) * h->n * r, h->stream));
+    st = check_finite(h, {{xb, h->m * r}, {xc, h->n * r}}, h->stream);
+    if (st != BDU_OK) return st;
+    for (int p = 0; p < r; ++p) {
+        st = pass_single(h, p, true, xb, xc);
         if (st != BDU_OK) return st;
     }
     return BDU_OK;
