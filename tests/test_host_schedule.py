@@ -280,7 +280,7 @@ def test_tracking_rejects_bad_sizes_without_a_device():
                               ctypes.byref(h)) == bdu.BDU_EINVAL
     assert L.bdu_track_update(None, None, None) == bdu.BDU_EINVAL
     assert L.bdu_track_last(None, None, None, None) == bdu.BDU_EINVAL
-    assert L.bdu_strerror(bdu.BDU_ESPAN) == b"update vector in the span of the tracked basis"
+    assert L.bdu_strerror(bdu.BDU_ESPAN) == b"rank-1 tracker with an update vector in the span of its basis"
 
 
 def test_orthogonality_calls_reject_a_null_handle():
