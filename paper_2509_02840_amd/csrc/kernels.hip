@@ -379,23 +379,22 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(K0 * R 
 // ---- staged application ---------------------------------------------------------
 //
 // A workgroup of NW compute wavefronts and one memory wavefront (index NW).
-// The compute wavefronts run the register-window sweep above with LDS
-// traffic only: wavefront w takes its new columns from ring w and hands its
-// finished columns to ring w + 1; the coefficients of each front come from a
-// coefficient ring in LDS.  The memory wavefront feeds ring 0 and the
-// coefficient ring from global memory, DL fronts ahead, and writes the
-// columns arriving in ring NW back to Q or P.  Compute wavefronts therefore
-// issue no global or scalar memory operation in their loop, and none of their
-// waits depends on a global-memory latency.
+// The compute wavefronts run the register-window sweep above with their
+// column traffic through LDS only: wavefront w takes its new columns from
+// ring w and hands its finished columns to ring w + 1.  The memory wavefront
+// feeds ring 0 from global memory, DL fronts ahead, and writes the columns
+// arriving in ring NW back to Q or P, so no compute wavefront issues a
+// global load or store.
 //
-// Coefficient delivery.  A (c, s) pair is uniform across the rows.  Read
-// with one broadcast LDS load per rotation it would move 1 KB through the
-// LDS data path (64 lanes x 16 bytes) for 16 bytes of data, which at one
-// rotation per 16 FP64 lane-cycles is more than the LDS can deliver.  So a
-// compute wavefront reads the pairs of its next front once, lane l holding
-// pair l mod 16 (each row of 16 lanes holds the same copy), and broadcasts
-// pair p to all lanes with a 64-bit DPP move (row_newbcast:p), which costs
-// one VALU instruction per 8 bytes and no LDS bandwidth.
+// Coefficient delivery.  A (c, s) pair is uniform across the rows, so the
+// compute wavefronts hold it in scalar registers, loaded from the rotation
+// stream by scalar loads (sweep_compute_sc), and a rotation is four FP64
+// instructions with scalar operands.  A broadcast LDS read per rotation
+// would move 1 KB through the LDS data path for 16 bytes of data (the LDS
+// then bounds the kernel), and a row broadcast by DPP moves costs two more
+// vector instructions per rotation.  The memory wavefront still streams
+// each front's coefficients into an LDS ring a few fronts ahead, which
+// keeps them in the L2 cache for the compute wavefronts' scalar loads.
 template <int K0, int NW, int R>
 struct Staged {
     static constexpr int U = K0 + 3, WSZ = 3 * U, S = U, K = K0 * NW;
@@ -405,59 +404,44 @@ struct Staged {
     static constexpr int LDS_DOUBLES = COEF + 3 * K * 2;      // 3 fronts of K pairs
     static constexpr int DL = U / 3;                          // memory prefetch depth, U % DL == 0
     static constexpr int NCI = (K + 63) / 64;                 // coefficient loads per front
-    static constexpr int NCR = (K0 + 15) / 16;                // coefficient registers per compute lane
     static_assert(U % 3 == 0 && U % DL == 0 && (3 * U) % RC == 0, "static ring slots");
 };
 
-// Value of v in lane 16 * (lane / 16) + P (row_newbcast:P, a 64-bit DPP move).
-template <int P>
-__device__ __forceinline__ double row_bcast(double v)
+// Rotations at positions [P, P1) of a front in front_order, pair p's
+// coefficients in (c[p], s[p]).
+template <int K0, int R, int MODE, int K, int WSZ, int P, int P1>
+__device__ __forceinline__ void front_part(const double (&c)[K0], const double (&s)[K0], double (&buf)[R][WSZ],
+                                           int phi)
 {
-    static_assert(P >= 0 && P < 16, "row lane");
-    long x = __builtin_bit_cast(long, v);
-    long y = __builtin_amdgcn_mov_dpp(x, 0x150 + P, 0xf, 0xf, true);
-    return __builtin_bit_cast(double, y);
-}
-
-// Pairs [16 j, 16 j + 16) of a compute wavefront's K0 pairs of one front,
-// lane l holding pair 16 j + (l mod 16) (clamped to the last pair).
-template <int K0>
-__device__ __forceinline__ double2 coef_lane(const double2 *front, int j, int lane)
-{
-    const int q = 16 * j + (lane & 15);
-    return front[q < K0 ? q : K0 - 1];
-}
-
-template <int P, int K0, int NCR>
-__device__ __forceinline__ void coef_bcast(const double2 (&cv)[NCR], double &c, double &s)
-{
-    c = row_bcast<P % 16>(cv[P / 16].x);
-    s = row_bcast<P % 16>(cv[P / 16].y);
-}
-
-template <int K0, int NCR, int R, int MODE, int K, int WSZ, int P = 0>
-__device__ __forceinline__ void front_rotations(const double2 (&cv)[NCR], double (&buf)[R][WSZ], int phi)
-{
-    if constexpr (P < K0) {
+    if constexpr (P < P1) {
         constexpr FrontOrder ord = front_order(MODE, K, K0);
         constexpr bool DESC = MODE < 2;
         constexpr int t = ord.t[P];
         const int l0 = 3 * (phi - t) + rho_of(MODE, K, t);
         const int sx = pmod(l0 + (DESC ? 1 : 0), WSZ);
         const int sy = pmod(l0 + (DESC ? 0 : 1), WSZ);
-        double c, sn;
-        coef_bcast<P, K0, NCR>(cv, c, sn);
 #pragma unroll
-        for (int r = 0; r < R; ++r) rot(c, sn, buf[r][sx], buf[r][sy]);
-        front_rotations<K0, NCR, R, MODE, K, WSZ, P + 1>(cv, buf, phi);
+        for (int r = 0; r < R; ++r) rot(c[P], s[P], buf[r][sx], buf[r][sy]);
+        front_part<K0, R, MODE, K, WSZ, P + 1, P1>(c, s, buf, phi);
     }
 }
 
+// Compute wavefronts with their coefficients in scalar registers (scalar
+// loads from the rotation stream): pair p of front F sits at
+// cs[2 (F K + w K0 + p)].  The first half of a front's pairs is loaded in
+// the middle of the previous front (once the first half of its rotations
+// has freed those registers), the second half at the start of the front
+// itself, so every scalar load has about half a front of work before its
+// value is needed, and the wait at the front's barrier (whose LDS writes
+// share the counter with scalar loads) finds the loads of the middle of
+// the front landed.
 template <int K0, int NW, int R, int MODE>
-__device__ __forceinline__ void sweep_compute(const BlockDesc bd, double *lds, int w, int lane)
+__device__ __forceinline__ void sweep_compute_sc(const CONSTANT double *__restrict__ cs, const BlockDesc bd,
+                                                 double *lds, int w, int lane)
 {
     using T = Staged<K0, NW, R>;
-    constexpr int U = T::U, WSZ = T::WSZ, S = T::S, K = T::K, RC = T::RC, NCR = T::NCR;
+    constexpr int U = T::U, WSZ = T::WSZ, S = T::S, K = T::K, RC = T::RC;
+    constexpr int H = K0 / 2;
     const int lmax = bd.lmax;
     if (lmax < 0) return;
     const int nfront = bd.nfront;
@@ -469,7 +453,6 @@ __device__ __forceinline__ void sweep_compute(const BlockDesc bd, double *lds, i
         for (int i = 0; i < WSZ; ++i) buf[r][i] = 0.0;
     const double *rin = lds + w * T::RING + lane;
     double *rout = lds + (w + 1) * T::RING + lane;
-    const double2 *coef = (const double2 *)(lds + T::COEF) + w * K0;
     const int flush_end = lam_hi / 3 + K0 - 1;
     const int nchunk = nfront / U;
     int live_end = w + (flush_end + U) / U;
@@ -477,19 +460,27 @@ __device__ __forceinline__ void sweep_compute(const BlockDesc bd, double *lds, i
     auto idle = [&](int chunks) {
         for (int c = 0; c < chunks * U; ++c) __syncthreads();
     };
+    double c[K0], sn[K0];
+    // pairs [p0, p1) of front F
+    auto load = [&](int F, int p0, int p1) {
+        const CONSTANT double *q = cs + 2 * ((int64_t)F * K + w * K0);
+#pragma unroll
+        for (int p = 0; p < K0; ++p)
+            if (p >= p0 && p < p1) {
+                c[p] = q[2 * p];
+                sn[p] = q[2 * p + 1];
+            }
+    };
     __syncthreads();  // the memory wavefront's prologue is in LDS
     idle(w);
-    // front F's pairs sit in slot F mod 3 of the coefficient ring (the
-    // memory wavefront writes them during front F - 2); the first live
-    // front w S is a multiple of 3
-    double2 cv[NCR];
-#pragma unroll
-    for (int j = 0; j < NCR; ++j) cv[j] = coef_lane<K0>(coef, j, lane);
+    load(w * S, 0, H);
     for (int F0 = w * S; F0 < live_end * U; F0 += U) {
 #pragma unroll
         for (int phi = 0; phi < U; ++phi) {
             const int F = F0 + phi;
             const int f = F - w * S;
+            load(F, H, K0);
+            __builtin_amdgcn_sched_barrier(0);
             if (phi == 0 && f == 0) {
 #pragma unroll
                 for (int k = 0; k <= 3; ++k)
@@ -504,21 +495,22 @@ __device__ __forceinline__ void sweep_compute(const BlockDesc bd, double *lds, i
 #pragma unroll
                 for (int r = 0; r < R; ++r)
                     buf[r][pmod(3 * phi + k, WSZ)] = rin[(pmod(3 * phi + k, RC) * R + r) * 64];
-            // the next front's pairs, read a front early (written during
-            // front F - 1, overwritten during front F + 2)
-            double2 cn[NCR];
-#pragma unroll
-            for (int j = 0; j < NCR; ++j) cn[j] = coef_lane<K0>(coef + ((phi + 1) % 3) * K, j, lane);
             // this wavefront's K0 rotations at front F, in front_order (their
-            // coefficients are stored in that order)
-            front_rotations<K0, NCR, R, MODE, K, WSZ>(cv, buf, phi);
-#pragma unroll
-            for (int j = 0; j < NCR; ++j) cv[j] = cn[j];
+            // coefficients are stored in that order); the first ones (chain
+            // K0 - 1) finish the columns that leave the window
+            front_part<K0, R, MODE, K, WSZ, 0, H>(c, sn, buf, phi);
 #pragma unroll
             for (int k = 0; k < 3; ++k)
 #pragma unroll
                 for (int r = 0; r < R; ++r)
                     rout[(pmod(3 * (phi - K0 + 1) + k, RC) * R + r) * 64] = buf[r][pmod(3 * (phi - K0 + 1) + k, WSZ)];
+            // wait here (not after the next loads) for this front's second
+            // half: a wait for one scalar load waits for all in flight
+            asm volatile("" ::"s"(c[H]));
+            __builtin_amdgcn_sched_barrier(0);
+            load(F + 1, 0, H);
+            __builtin_amdgcn_sched_barrier(0);
+            front_part<K0, R, MODE, K, WSZ, H, K0>(c, sn, buf, phi);
             __syncthreads();
 #pragma unroll
             for (int r = 0; r < R; ++r)
@@ -680,11 +672,11 @@ void apply_staged_kernel(HandleDev *const *hs, Gate gate)
             }
         } else {
             if (b < nb1) {
-                if (onQ) sweep_compute<K0, NW, R, 0>(bd, lds, w, lane);
-                else sweep_compute<K0, NW, R, 1>(bd, lds, w, lane);
+                if (onQ) sweep_compute_sc<K0, NW, R, 0>(cb, bd, lds, w, lane);
+                else sweep_compute_sc<K0, NW, R, 1>(cb, bd, lds, w, lane);
             } else {
-                if (onQ) sweep_compute<K0, NW, R, 2>(bd, lds, w, lane);
-                else sweep_compute<K0, NW, R, 3>(bd, lds, w, lane);
+                if (onQ) sweep_compute_sc<K0, NW, R, 2>(cb, bd, lds, w, lane);
+                else sweep_compute_sc<K0, NW, R, 3>(cb, bd, lds, w, lane);
             }
         }
         __syncthreads();
