@@ -151,17 +151,17 @@ def test_plan_queries_in_auto_tiling_mode(tmp_path):
         bdu.set_tiling(*saved)
 
 
-def _staged_protocol_violations(K0, NW, lmax, RC=15, NCS=3):
-    """Replay the staged applier's LDS hand-overs front by front (a barrier
-    after every front) and return every read that does not see its value's
-    write across a barrier, or that is not separated by a barrier from the
-    slot's next write.  Ring j feeds compute wavefront j (ring 0 from the
-    memory wavefront, ring NW to it); the coefficient ring has NCS fronts.
-    Compute wavefront w reads columns 0..3 at its first front and 3f+4..3f+6
-    at every front f (a front early); the memory wavefront writes columns
-    0..6 before the first barrier and 3F+7..3F+9 at front F, stores the
-    columns the last wavefront finished at F-1, and writes the coefficients
-    of front F+2 at front F, which compute wavefronts read a front early."""
+def _staged_protocol_violations(K0, NW, lmax, RC=15):
+    """Replay the staged applier's LDS column hand-overs front by front (a
+    barrier after every front) and return every read that does not see its
+    value's write across a barrier, or that is not separated by a barrier
+    from the slot's next write.  Ring j feeds compute wavefront j (ring 0
+    from the memory wavefront, ring NW to it).  Compute wavefront w reads
+    columns 0..3 at its first front and 3f+4..3f+6 at every front f (a front
+    early); the memory wavefront writes columns 0..6 before the first barrier
+    and 3F+7..3F+9 at front F, and stores the columns the last wavefront
+    finished at F-1.  (The coefficients reach the compute wavefronts by
+    scalar loads, outside LDS.)"""
     U = S = K0 + 3
     lam_hi = lmax + 1
     fend = lmax // 3 + K0 + 1
@@ -197,30 +197,11 @@ def _staged_protocol_violations(K0, NW, lmax, RC=15, NCS=3):
                 lam = 3 * (f - K0 + 1) + k
                 if lam >= 0:
                     put(w + 1, lam % RC, F, "w", lam, 0)
-    # coefficients: the prologue writes fronts 0 and 1, the memory wavefront
-    # writes front F + 2 at front F; compute wavefront w reads front w S at
-    # its first live front and front F + 1 at every live front F (a front
-    # early, into registers)
-    coef = {}
-    for F0 in range(min(2, nfront)):
-        coef.setdefault(F0 % NCS, []).append((PRO, 0, "w", F0))
-    for F in range(nfront):
-        if F + 2 < nfront:
-            coef.setdefault((F + 2) % NCS, []).append((F, 0, "w", F + 2))
-    for w in range(NW):
-        live_end = min(w + (flush_end + U) // U, nchunk)
-        if live_end * U <= w * S:
-            continue
-        coef.setdefault((w * S) % NCS, []).append((w * S, 1, "r", w * S))
-        for F in range(w * S, live_end * U):
-            if F + 1 < nfront:
-                coef.setdefault((F + 1) % NCS, []).append((F, 1, "r", F + 1))
-
     def barrier_between(a, b):  # the barrier after some front B, a <= B < b
         return a < b
 
     bad = []
-    for key, ev in list(events.items()) + [(("coef", s_), e) for s_, e in coef.items()]:
+    for key, ev in events.items():
         ev.sort(key=lambda x: (x[0], x[1]))
         writes = [e for e in ev if e[2] == "w"]
         for F, _, kind, value in ev:
@@ -228,7 +209,7 @@ def _staged_protocol_violations(K0, NW, lmax, RC=15, NCS=3):
                 continue
             mine = [wr for wr in writes if wr[3] == value]
             if not mine:
-                if key[0] == "coef" or value <= lam_hi:
+                if value <= lam_hi:
                     bad.append((key, F, value, "never written"))
                 continue
             Fw = mine[-1][0]
@@ -248,9 +229,8 @@ def test_staged_lds_protocol_is_race_free(K0, NW, RC, lmax):
 
 def test_staged_protocol_checker_sees_a_race():
     """A ring of 9 columns (three fronts) would be rewritten in the front of
-    its last read; a coefficient ring of one front likewise."""
+    its last read."""
     assert _staged_protocol_violations(12, 7, 100, RC=9) != []
-    assert _staged_protocol_violations(12, 7, 100, NCS=1) != []
 
 
 def test_finite_check_switch_validates_its_argument():
