@@ -199,3 +199,65 @@ def link_stream(m: int, n: int, steps: int, seed: int, density: float = 0.05):
         c[h % n] = 1.0
         out.append((b, c))
     return out
+
+
+def bidiagonal_factors(A: np.ndarray, seed: int = 0):
+    """A starting factorization A = Q [B; 0] P^T of a tall matrix (m >= n):
+    Householder QR A = Q1 [R; 0] (LAPACK, through numpy), then Golub-Kahan
+    bidiagonalization of R from p1 = e1 (Section 2's recurrences
+    R P = W B, R^T W = P B^T) with two passes of full reorthogonalization
+    against all earlier vectors, and Q = Q1 diag(W, I).  A breakdown (a zero
+    d_k or e_k) continues from a random unit vector orthogonal to the earlier
+    ones, with that entry of B exactly 0.  Input construction only: it
+    shares nothing with the update method.  Returns (Q, d, e, P)."""
+    A = np.asarray(A, dtype=np.float64)
+    m, n = A.shape
+    if m < n or n < 2:
+        raise ValueError("need m >= n >= 2")
+    rng = np.random.default_rng(seed)
+    Q1, R = np.linalg.qr(A, mode="complete")
+    R = np.ascontiguousarray(R[:n])
+    scale = max(np.linalg.norm(R), 1.0)
+    W = np.zeros((n, n))
+    P = np.zeros((n, n))
+    d = np.zeros(n)
+    e = np.zeros(n - 1)
+
+    def orth(x, basis):
+        for _ in range(2):
+            x = x - basis @ (basis.T @ x)
+        return x
+
+    def fresh(basis):
+        while True:
+            x = orth(rng.standard_normal(basis.shape[0]), basis)
+            nx = np.linalg.norm(x)
+            if nx > 1e-8:
+                return x / nx
+
+    p = np.zeros(n)
+    p[0] = 1.0
+    for k in range(n):
+        P[:, k] = p
+        w = R @ p - (e[k - 1] * W[:, k - 1] if k > 0 else 0.0)
+        w = orth(w, W[:, :k])
+        nw = np.linalg.norm(w)
+        if nw <= 1e-13 * scale:
+            d[k] = 0.0
+            W[:, k] = fresh(W[:, :k])
+        else:
+            d[k] = nw
+            W[:, k] = w / nw
+        if k + 1 < n:
+            p = R.T @ W[:, k] - d[k] * P[:, k]
+            p = orth(p, P[:, :k + 1])
+            npn = np.linalg.norm(p)
+            if npn <= 1e-13 * scale:
+                e[k] = 0.0
+                p = fresh(P[:, :k + 1])
+            else:
+                e[k] = npn
+                p = p / npn
+    Q = Q1.copy(order="F")
+    Q[:, :n] = Q1[:, :n] @ W
+    return Q, d, e, np.asfortranarray(P)
