@@ -111,19 +111,88 @@ def applier_flops(bdu, m: int, n: int) -> float:
     return 6.0 * (m * st["left"] + n * st["right"])
 
 
-def cpu_baseline(n: int, seed: int) -> dict:
-    """The oracle, as it stands, on one rank-1 update of one n x n stream."""
-    from oracle import oracle as O
-    from paper_2509_02840_amd import workloads as W
+def host_cpu() -> dict:
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0))}
 
-    f = W.factorization(n, n, seed)
-    (B, C), = W.gaussian_updates(n, n, 1, seed + 1)
-    st = O.State(f.Q, f.d, f.e, f.P)
-    t0 = time.perf_counter()
-    O.bgu_update(st, B, C)
-    dt = time.perf_counter() - t0
-    return {"value": 1.0 / dt, "unit": "rank-1 updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"one rank-1 update of one {n}x{n} stream, single thread ({dt:.1f} s)"}
+
+def cpu_threads() -> int:
+    """Threads for the all-cores leg: the CPUs this process may run on,
+    capped by OMP_NUM_THREADS where it is set (a share of a shared host)."""
+    usable = len(os.sched_getaffinity(0))
+    cap = os.environ.get("OMP_NUM_THREADS", "")
+    return max(1, min(usable, int(cap))) if cap.isdigit() and int(cap) > 0 else usable
+
+
+def oracle_rows_split_seconds(O, Q, d, e, P, b, c, threads: int) -> float:
+    """One rank-1 update by the oracle, as it stands, split over threads:
+    the projections by columns of Q and P (every entry is the oracle's own
+    sequential sum), the pass by rows of Q and P (each thread regenerates
+    the same rotations and applies them to its rows; the oracle's C entry
+    points release the interpreter lock).  The row groups are gathered
+    before the clock starts."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    m, n = Q.shape[0], P.shape[0]
+    gq = [g for g in np.array_split(np.arange(m), threads) if len(g)]
+    gp = [g for g in np.array_split(np.arange(n), threads) if len(g)]
+    Qg = [np.asfortranarray(Q[g]) for g in gq]
+    Pg = [np.asfortranarray(P[g]) for g in gp] + [np.zeros((0, n), order="F")] * (len(gq) - len(gp))
+    cq = [(g[0], g[-1] + 1) for g in gq]
+    cp = [(g[0], g[-1] + 1) for g in gp]
+    with ThreadPoolExecutor(threads) as pool:
+        t0 = time.perf_counter()
+        u = np.concatenate(list(pool.map(lambda s: O.project(Q[:, s[0]:s[1]], b), cq)))
+        v = np.concatenate(list(pool.map(lambda s: O.project(P[:, s[0]:s[1]], c), cp)))
+        list(pool.map(lambda k: O.bgu_pass_rows(m, n, Qg[k], d, e, Pg[k], u, v), range(len(gq))))
+        return time.perf_counter() - t0
+
+
+def cpu_baseline(Q, d, e, P, b, c, what: str, single_sample: int = 1) -> dict:
+    """The oracle, as it stands, on one rank-1 update of one stream, in two
+    modes: all host threads with the rows split (the reported value) and a
+    single thread.  With single_sample = k > 1 the single thread runs the
+    pass on the first 1/k of the rows of Q and P and is extrapolated:
+    projection + generation (a pass on no rows) + k x (the sample's rows)."""
+    from oracle import oracle as O
+
+    m, n = Q.shape[0], P.shape[0]
+    T = cpu_threads()
+    all_s = oracle_rows_split_seconds(O, Q, d, e, P, b, c, T)
+    if single_sample <= 1:
+        st = O.State(Q, d, e, P)
+        t0 = time.perf_counter()
+        O.bgu_update(st, b, c)
+        single = time.perf_counter() - t0
+        how = f"the whole update, measured ({single:.1f} s)"
+    else:
+        k = single_sample
+        Qs, Ps = np.asfortranarray(Q[: m // k]), np.asfortranarray(P[: n // k])
+        none = np.zeros((0, m), order="F"), np.zeros((0, n), order="F")
+        t0 = time.perf_counter()
+        u, v = O.project(Q, b), O.project(P, c)
+        t1 = time.perf_counter()
+        O.bgu_pass_rows(m, n, none[0], d, e, none[1], u, v)
+        t2 = time.perf_counter()
+        O.bgu_pass_rows(m, n, Qs, d, e, Ps, u, v)
+        t3 = time.perf_counter()
+        gen = t2 - t1
+        single = (t1 - t0) + gen + k * ((t3 - t2) - gen)
+        how = (f"extrapolated from a pass on 1/{k} of the rows of Q and P ({t3 - t2:.1f} s; "
+               f"projection {t1 - t0:.2f} s, generation {gen:.2f} s)")
+    return {"value": 1.0 / all_s, "unit": "rank-1 updates/s", "cores": T, "kind": "oracle",
+            "sample": f"one rank-1 update of {what}, rows of Q and P split over {T} threads ({all_s:.1f} s)",
+            "single_thread": {"value": 1.0 / single, "unit": "rank-1 updates/s", "cores": 1,
+                              "sample": f"one rank-1 update of {what}, one thread: {how}"},
+            "host": host_cpu()}
 
 
 def copy_probe(torch) -> int:
@@ -353,6 +422,105 @@ def track(torch, bdu, args) -> int:
     return 0
 
 
+def recsys(torch, bdu, args) -> int:
+    """The recommendation-shaped stream (users x items, Section 4's rating
+    experiments on synthetic data): integer ratings 1..5 at 1% density with
+    Zipf(1.1) item popularity; the starting factorization A = Q Bd P^T from
+    the ratings (Householder QR, then Golub-Kahan on R; host, untimed, its
+    time reported).  Then calls of rank r = 1, 4, 8 in turn, each replacing
+    r users' rows (b_k = e_i, c_k = new row - old row, 20 new ratings), with
+    the row-mean adjustment (b = -A e / n, c = e) as every 50th call.  The
+    calls are drawn, and the dense rating matrix followed, on the host
+    beforehand; B and C are resident on the device before the timed region.
+    One bdu_update per call, each waited for.  value = rank-1 passes per
+    second over the timed calls of all three ranks."""
+    from paper_2509_02840_amd import workloads as W
+
+    m, n = args.recsys_users, args.recsys_items
+    t0 = time.perf_counter()
+    A = W.ratings(m, n, seed=args.seed)
+    Q, d, e, P = W.bidiagonal_factors(A, seed=args.seed + 1)
+    init_s = time.perf_counter() - t0
+    rng = np.random.default_rng(args.seed + 2)
+    dev = torch.device("cuda:0")
+    ranks = [1, 4, 8]
+    calls = []  # (rank label, timed, B, C) with B, C on the device
+    first = None
+    k_all = 0
+    for r in ranks:
+        for k in range(args.warmup + args.recsys_steps):
+            k_all += 1
+            if k_all % 50 == 0:
+                B = (-(A @ np.ones(n)) / n)[:, None]
+                C = np.ones((n, 1))
+                A += B @ C.T
+                label = "mean"
+            else:
+                who = rng.choice(m, r, replace=False)
+                B = np.zeros((m, r))
+                C = np.zeros((n, r))
+                for j, i in enumerate(who):
+                    B[i, j] = 1.0
+                    C[:, j] = W.rating_row(rng, n, nnz=20) - A[i]
+                    A[i] += C[:, j]
+                label = r
+            if first is None:
+                first = (B[:, 0].copy(), C[:, 0].copy())
+            col = lambda X: torch.from_numpy(np.ascontiguousarray(X.T)).to(dev).T  # column-major
+            calls.append((label, k >= args.warmup, col(B), col(C)))
+    h = bdu.Handle(Q, d, e, P)
+    torch.cuda.synchronize()
+    for label, timed, B, C in calls:
+        if not timed:
+            h.update(B, C)
+    h.sync()
+    bdu.timing_enable(True)
+    lat = {r: [] for r in ranks + ["mean"]}
+    passes = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for label, timed, B, C in calls:
+        if not timed:
+            continue
+        ta = time.perf_counter()
+        h.update(B, C)
+        h.sync()
+        lat[label].append(time.perf_counter() - ta)
+        passes += B.shape[1]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stages = bdu.timing_read()
+    bdu.timing_enable(False)
+    h.close()
+    apply_ms, apply_launches = stages["apply"]
+    avg_apply_s = apply_ms / 1e3 / max(apply_launches, 1)
+    flops_per_launch = passes * applier_flops(bdu, m, n) / max(apply_launches, 1)
+    achieved = flops_per_launch / avg_apply_s / 1e12
+    pct = lambda xs, q: 1e3 * float(np.percentile(xs, q)) if xs else None
+    line = {
+        "metric": "FP64 rank-1 updates/sec + p50/p99 latency, recommendation stream",
+        "value": passes / dt, "unit": "rank-1 updates/s", "n_gpus": 1, "steps": len(calls) - args.warmup * 3,
+        "warmup": args.warmup, "ms_per_step": 1e3 * dt / passes, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{m} users x {n} items ratings 1..5 at 1% density (Zipf 1.1 items); calls "
+                               f"replacing r users' rows, r = 1, 4, 8 ({args.recsys_steps} timed calls each), "
+                               "row-mean adjustment every 50th call",
+                   "m": m, "n": n, "ranks": ranks, "initial_factorization_s": init_s},
+        "per_rank": {str(r): {"calls": len(lat[r]), "p50_ms": pct(lat[r], 50), "p99_ms": pct(lat[r], 99),
+                              "passes_per_s": (len(lat[r]) * (1 if r == "mean" else r)) / max(sum(lat[r]), 1e-30)}
+                     for r in lat},
+        "stage_ms_per_pass": {k: v[0] / passes for k, v in stages.items()},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "flops_per_launch": flops_per_launch, "avg_launch_ms": avg_apply_s * 1e3},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(Q, d, e, P, first[0], first[1], f"the {m} x {n} rating stream",
+                                            single_sample=8)
+    print(json.dumps(line))
+    return 0
+
+
 def orth(torch, bdu, args) -> int:
     """Orthogonality monitor and correction at m = n = args.n: drift
     measurement (X^T X - I on the FP64 matrix cores) and one Newton-Schulz
@@ -511,6 +679,11 @@ def main() -> int:
     ap.add_argument("--track-n", type=int, default=2000)
     ap.add_argument("--track-r", type=int, default=64)
     ap.add_argument("--track-steps", type=int, default=200)
+    ap.add_argument("--recsys", action="store_true",
+                    help="instead: the recommendation-shaped stream (prints its own JSON line)")
+    ap.add_argument("--recsys-users", type=int, default=10000)
+    ap.add_argument("--recsys-items", type=int, default=2000)
+    ap.add_argument("--recsys-steps", type=int, default=100)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy three times (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -529,6 +702,8 @@ def main() -> int:
     torch.cuda.set_device(0)
     if args.track:
         return track(torch, bdu, args)
+    if args.recsys:
+        return recsys(torch, bdu, args)
     if args.orth:
         return orth(torch, bdu, args)
     if args.bhu:
@@ -677,7 +852,11 @@ def main() -> int:
                      "avg_launch_ms": avg_apply_s * 1e3},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(n, args.seed)
+        from paper_2509_02840_amd import workloads as W
+
+        f = W.factorization(n, n, args.seed)
+        (B, C), = W.gaussian_updates(n, n, 1, args.seed + 1)
+        out["cpu_baseline"] = cpu_baseline(f.Q, f.d, f.e, f.P, B[:, 0], C[:, 0], f"one {n}x{n} stream")
     print(json.dumps(out))
     return 0
 

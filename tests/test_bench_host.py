@@ -49,3 +49,23 @@ def test_traffic_is_reported_only_for_measured_sources():
         assert bench.measured_traffic(t["n"], t["streams"], til) is None
     finally:
         t["sha256"] = saved
+
+
+@pytest.mark.parametrize("sample", [1, 4])
+def test_cpu_baseline_reports_both_modes(sample):
+    from paper_2509_02840_amd import workloads as W
+
+    f = W.factorization(96, 64, 11)
+    (B, C), = W.gaussian_updates(96, 64, 1, 12)
+    out = bench.cpu_baseline(f.Q, f.d, f.e, f.P, B[:, 0], C[:, 0], "a 96x64 stream", single_sample=sample)
+    assert out["kind"] == "oracle" and out["value"] > 0 and out["cores"] == bench.cpu_threads()
+    assert out["single_thread"]["cores"] == 1 and out["single_thread"]["value"] > 0
+    assert out["host"]["logical_cpus"] >= 1
+    assert ("extrapolated" in out["single_thread"]["sample"]) == (sample > 1)
+
+
+def test_cpu_threads_follow_the_thread_cap(monkeypatch):
+    monkeypatch.setenv("OMP_NUM_THREADS", "1")
+    assert bench.cpu_threads() == 1
+    monkeypatch.setenv("OMP_NUM_THREADS", "")
+    assert bench.cpu_threads() == len(os.sched_getaffinity(0))

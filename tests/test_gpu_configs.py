@@ -1,7 +1,7 @@
 """The workload configurations at their own sizes, against the oracle.
 
   * one stream, m = 4000, n = 2000, 200 rank-1 updates: every update in
-    lockstep (the GPU's projections u, v feed the oracle's pass on 8 tracked
+    lockstep (the GPU's projections u, v feed the oracle's pass on 64 tracked
     rows of Q and P; d and e are compared bit for bit after every update,
     the tracked rows at checkpoints), then the dense invariants and the
     singular values of Bd against a dense SVD of A+;
@@ -16,6 +16,8 @@
   * served mix with n = 512 ... 8192: every stream served equals the same
     updates on a lone handle.
 """
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 import pytest
 
@@ -49,18 +51,35 @@ def _de(h):
 
 
 class _Lockstep:
-    """The oracle's continuation of a GPU handle on a few tracked rows."""
+    """The oracle's continuation of a GPU handle on a few tracked rows.
 
-    def __init__(self, f, qr, pr):
+    The rows are split into groups that the oracle passes on concurrent
+    threads (its C entry points release the interpreter lock); each group
+    regenerates the same rotations, so every group's d, e must agree."""
+
+    def __init__(self, f, qr, pr, groups=1):
         self.m, self.n = f.Q.shape[0], f.P.shape[0]
         self.qr, self.pr = qr, pr
+        self.gq = np.array_split(np.arange(len(qr)), groups)
+        self.gp = np.array_split(np.arange(len(pr)), groups)
         self.Qr, self.Pr = f.Q[qr].copy(), f.P[pr].copy()
         self.d, self.e = f.d.copy(), f.e.copy()
+        self.pool = ThreadPoolExecutor(groups) if groups > 1 else None
+
+    def step(self, oracle, u, v):
+        one = lambda g: oracle.bgu_pass_rows(self.m, self.n, self.Qr[self.gq[g]], self.d, self.e,
+                                             self.Pr[self.gp[g]], u, v)
+        outs = list(self.pool.map(one, range(len(self.gq)))) if self.pool else [one(0)]
+        for g, (Qg, dg, eg, Pg) in enumerate(outs):
+            _eq(f"oracle group {g} d", dg, outs[0][1])
+            _eq(f"oracle group {g} e", eg, outs[0][2])
+            self.Qr[self.gq[g]] = Qg
+            self.Pr[self.gp[g]] = Pg
+        self.d, self.e = outs[0][1], outs[0][2]
 
     def pass_(self, oracle, h, b, c, tag):
         u, v = h.project(b, c)
-        self.Qr, self.d, self.e, self.Pr = oracle.bgu_pass_rows(self.m, self.n, self.Qr, self.d, self.e,
-                                                               self.Pr, u, v)
+        self.step(oracle, u, v)
         h.update(b, c)
         d, e = _de(h)
         _eq(f"{tag} d", d, self.d)
@@ -72,6 +91,10 @@ class _Lockstep:
         _eq(f"{tag} P rows", P[self.pr], self.Pr)
         return Q, d, e, P
 
+    def close(self):
+        if self.pool:
+            self.pool.shutdown()
+
 
 # ---- one stream, 4000 x 2000, 200 updates --------------------------------------------
 
@@ -79,11 +102,12 @@ class _Lockstep:
 def one_stream(bdu):
     f, ups = W.one_stream()
     rng = np.random.default_rng(74)
-    qr = np.sort(rng.choice(f.m, 8, replace=False))
-    pr = np.sort(rng.choice(f.n, 8, replace=False))
+    qr = np.sort(rng.choice(f.m, 64, replace=False))
+    pr = np.sort(rng.choice(f.n, 64, replace=False))
     h = bdu.Handle(f.Q, f.d, f.e, f.P)
-    st = {"f": f, "ups": ups, "h": h, "ls": _Lockstep(f, qr, pr), "done": 0, "A": f.dense()}
+    st = {"f": f, "ups": ups, "h": h, "ls": _Lockstep(f, qr, pr, groups=8), "done": 0, "A": f.dense()}
     yield st
+    st["ls"].close()
     h.close()
 
 
@@ -130,11 +154,11 @@ def test_rating_stream_full_size(bdu, oracle):
     f = W.Factorization(Q0, d0, e0, P0)
     del Q0
     rng = np.random.default_rng(4002)
-    qr = np.sort(rng.choice(users, 8, replace=False))
-    pr = np.sort(rng.choice(items, 8, replace=False))
+    qr = np.sort(rng.choice(users, 32, replace=False))
+    pr = np.sort(rng.choice(items, 32, replace=False))
     h1 = bdu.Handle(f.Q, f.d, f.e, f.P)   # rank-1 passes, in lockstep with the oracle
     hr = bdu.Handle(f.Q, f.d, f.e, f.P)   # the same calls as rank-r updates
-    ls = _Lockstep(f, qr, pr)
+    ls = _Lockstep(f, qr, pr, groups=4)
     calls = [1] * 8 + [4] * 3 + ["mean"] + [8] * 2
     passes = 0
     try:
@@ -165,6 +189,7 @@ def test_rating_stream_full_size(bdu, oracle):
         assert np.linalg.norm(rows - A[qr]) <= 1e-12 * np.linalg.norm(A)
         assert passes == 8 + 12 + 1 + 16
     finally:
+        ls.close()
         h1.close()
         hr.close()
 
@@ -219,8 +244,7 @@ def test_mixed_size_batch_sampled_streams(bdu, oracle):
                 for nm, x, y in zip("QdeP", hs[i].read(), (ref.Q, ref.d, ref.e, ref.P)):
                     _eq(f"step {step} stream {i} (n = {hs[i].n}) {nm}", x, y)
             for i, ls in lock.items():
-                u, v = proj[i]
-                ls.Qr, ls.d, ls.e, ls.Pr = oracle.bgu_pass_rows(ls.m, ls.n, ls.Qr, ls.d, ls.e, ls.Pr, u, v)
+                ls.step(oracle, *proj[i])
                 d, e = _de(hs[i])
                 _eq(f"step {step} stream {i} (n = {hs[i].n}) d", d, ls.d)
                 _eq(f"step {step} stream {i} (n = {hs[i].n}) e", e, ls.e)
