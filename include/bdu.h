@@ -390,6 +390,32 @@ int bdu_track_last(bdu_track t, double *delta, double *gamma, int64_t *dropped);
  * and gamma). */
 int bdu_track_last_projection(bdu_track t, double *bh, double *ch, double *qb, double *qc);
 
+/* Orthogonality of the tracked factors (Section 4.2: the products of the
+ * thin factors with the middle factors lose orthogonality slowly, and the
+ * paper checks for that periodically and reorthogonalizes a few times).
+ * eu / ev (either may be NULL) receive ||U^T U - I||_F and ||V^T V - I||_F,
+ * computed on the FP64 matrix cores as bdu_orth_error does for Q and P.
+ * Synchronizes the tracker's stream.  Scratch of about
+ * 16 max(m, n) r + 8 r^2 bytes is allocated on first use and kept. */
+int bdu_track_orth_error(bdu_track t, double *eu, double *ev);
+
+/* Measure as above and, on each side whose drift exceeds tol (every side
+ * if tol <= 0), take one Newton-Schulz step X <- X - X (X^T X - I) / 2
+ * (the step of bdu_reorthogonalize).  eu / ev receive the drift measured
+ * before the step. */
+int bdu_track_reorthogonalize(bdu_track t, double tol, double *eu, double *ev);
+
+/* The periodic check: after every period-th successful bdu_track_update
+ * (counted from this call), bdu_track_reorthogonalize(t, tol, ...) runs on
+ * the tracker's stream and the update then synchronizes.  period = 0 turns
+ * the check off (the default).  BDU_EINVAL for period < 0 or a NaN tol. */
+int bdu_track_set_drift_check(bdu_track t, int64_t period, double tol);
+
+/* Checks run so far, sides corrected so far, and the drift of U and V
+ * measured by the last check (before its correction).  Any pointer may be
+ * NULL. */
+int bdu_track_drift_stats(bdu_track t, int64_t *checks, int64_t *corrections, double *eu, double *ev);
+
 int bdu_track_destroy(bdu_track t);
 
 /* ---- schedule inspection (host only, no device needed) ---------------- */

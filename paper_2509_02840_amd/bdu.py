@@ -87,6 +87,11 @@ def lib():
         L.bdu_track_last.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(i64)]
         L.bdu_track_last_projection.argtypes = [vp, vp, vp, vp, vp]
+        dbl = ctypes.POINTER(ctypes.c_double)
+        L.bdu_track_orth_error.argtypes = [vp, dbl, dbl]
+        L.bdu_track_reorthogonalize.argtypes = [vp, ctypes.c_double, dbl, dbl]
+        L.bdu_track_set_drift_check.argtypes = [vp, i64, ctypes.c_double]
+        L.bdu_track_drift_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), dbl, dbl]
         L.bdu_track_destroy.argtypes = [vp]
         L.bdu_tune_save.argtypes = [ctypes.c_char_p]
         L.bdu_tune_load.argtypes = [ctypes.c_char_p]
@@ -593,6 +598,29 @@ class Tracker:
         _check(lib().bdu_track_read(self._h, U.ctypes.data, d.ctypes.data, e.ctypes.data, V.ctypes.data),
                "bdu_track_read")
         return U, d, e[: self.r - 1], V
+
+    def orth_error(self):
+        """(||U^T U - I||_F, ||V^T V - I||_F)."""
+        eu, ev = ctypes.c_double(), ctypes.c_double()
+        _check(lib().bdu_track_orth_error(self._h, ctypes.byref(eu), ctypes.byref(ev)), "bdu_track_orth_error")
+        return eu.value, ev.value
+
+    def reorthogonalize(self, tol: float = 0.0):
+        """One Newton-Schulz step on each side whose drift exceeds tol; the drift before it."""
+        eu, ev = ctypes.c_double(), ctypes.c_double()
+        _check(lib().bdu_track_reorthogonalize(self._h, tol, ctypes.byref(eu), ctypes.byref(ev)),
+               "bdu_track_reorthogonalize")
+        return eu.value, ev.value
+
+    def set_drift_check(self, period: int, tol: float) -> None:
+        _check(lib().bdu_track_set_drift_check(self._h, period, tol), "bdu_track_set_drift_check")
+
+    def drift_stats(self) -> dict:
+        c, k = ctypes.c_int64(), ctypes.c_int64()
+        eu, ev = ctypes.c_double(), ctypes.c_double()
+        _check(lib().bdu_track_drift_stats(self._h, ctypes.byref(c), ctypes.byref(k), ctypes.byref(eu),
+                                           ctypes.byref(ev)), "bdu_track_drift_stats")
+        return {"checks": c.value, "corrections": k.value, "eu": eu.value, "ev": ev.value}
 
     def last(self):
         """(delta, gamma, removed index) of the last update."""

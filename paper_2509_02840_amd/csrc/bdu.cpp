@@ -1676,6 +1676,12 @@ struct bdu_track_ctx {
     int *h_k = nullptr;                   // pinned: removed index
     double last_norm[2] = {0.0, 0.0};     // delta, gamma of the last update
     bool have_last = false;
+    // drift monitor of U and V (scratch allocated on first use): X padded
+    // to ld rows, its Newton-Schulz image, E = X^T X - I, the norm's partials
+    double *oX = nullptr, *oY = nullptr, *oE = nullptr, *oPart = nullptr, *oOut = nullptr;
+    int64_t oLd = 0, oLde = 0;
+    int64_t check_period = 0, since_check = 0, checks = 0, corrections = 0;
+    double check_tol = 0.0, drift[2] = {0.0, 0.0};
     bool poisoned = false;
     std::vector<void *> allocs;
     std::vector<void *> pinned;
@@ -1732,6 +1738,62 @@ int track_mid(bdu_track_ctx *t, int which, int64_t rows, int64_t cols)
         }
     }
     t->mid[which] = h;
+    return BDU_OK;
+}
+
+// Drift ||X^T X - I||_F of the tracked U and V (Section 4.2: the products
+// of the thin factors with the middle factors lose orthogonality slowly and
+// are reorthogonalized now and then), and with fix one Newton-Schulz step
+// X <- X - X E / 2 on each side whose drift exceeds tol (every side if
+// tol <= 0).  The orthogonality kernels take X with a leading dimension that
+// is a multiple of 128 and zero rows past the matrix, so each side is staged
+// in a padded copy.  Synchronizes the tracker's stream.
+int track_orth(bdu_track_ctx *t, bool fix, double tol, double *out)
+{
+    hipStream_t s = t->mid[0]->stream;
+    const int64_t r = t->r;
+    if (!t->oX) {
+        const int64_t ld = (std::max(t->m, t->n) + 127) / 128 * 128, lde = (r + 63) / 64 * 64;
+        hipError_t e = talloc(t, &t->oX, ld * r);
+        if (e == hipSuccess) e = talloc(t, &t->oY, ld * r);
+        if (e == hipSuccess) e = talloc(t, &t->oE, lde * lde);
+        if (e == hipSuccess) e = talloc(t, &t->oPart, lde);
+        if (e == hipSuccess) e = talloc(t, &t->oOut, 2);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            t->oX = nullptr;  // the pieces already taken are freed with the tracker
+            return e == hipErrorOutOfMemory ? BDU_ENOMEM : BDU_EDEVICE;
+        }
+        t->oLd = ld;
+        t->oLde = lde;
+    }
+    const int64_t ld = t->oLd, lde = t->oLde;
+    const size_t row = sizeof(double);
+    for (int k = 0; k < 2; ++k) {
+        double *X = k == 0 ? t->U[t->cur] : t->V[t->cur];
+        const int64_t rows = k == 0 ? t->m : t->n;
+        double e = 0.0;
+        if (hipMemsetAsync(t->oX, 0, row * ld * r, s) != hipSuccess ||
+            hipMemcpy2DAsync(t->oX, row * ld, X, row * rows, row * rows, r, hipMemcpyDeviceToDevice, s) !=
+                hipSuccess ||
+            launch_orth_gram(t->oX, ld, r, t->oE, lde, s) != hipSuccess ||
+            launch_orth_norm(t->oE, r, lde, t->oPart, t->oOut, s) != hipSuccess ||
+            hipMemcpyAsync(&e, t->oOut, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            t->poisoned = true;
+            return BDU_EDEVICE;
+        }
+        out[k] = e;
+        if (fix && (tol <= 0.0 || e > tol)) {
+            if (launch_orth_update(t->oX, ld, r, t->oE, lde, t->oY, s) != hipSuccess ||
+                hipMemcpy2DAsync(X, row * rows, t->oY, row * ld, row * rows, r, hipMemcpyDeviceToDevice, s) !=
+                    hipSuccess) {
+                t->poisoned = true;
+                return BDU_EDEVICE;
+            }
+            ++t->corrections;
+        }
+    }
     return BDU_OK;
 }
 
@@ -1900,6 +1962,11 @@ int bdu_track_update(bdu_track t, const double *b, const double *c)
     t->last_norm[1] = nrm[1];
     t->have_last = true;
 #undef TCHK
+    if (t->check_period > 0 && ++t->since_check >= t->check_period) {
+        t->since_check = 0;
+        ++t->checks;
+        return track_orth(t, true, t->check_tol, t->drift);
+    }
     return BDU_OK;
 }
 
@@ -1947,6 +2014,49 @@ int bdu_track_last_projection(bdu_track t, double *bh, double *ch, double *qb, d
     if (qb && copy_out(qb, t->bp, sizeof(double) * t->m, s) != hipSuccess) return BDU_EDEVICE;
     if (qc && copy_out(qc, t->cp, sizeof(double) * t->n, s) != hipSuccess) return BDU_EDEVICE;
     return hipStreamSynchronize(s) == hipSuccess ? BDU_OK : BDU_EDEVICE;
+}
+
+int bdu_track_orth_error(bdu_track t, double *eu, double *ev)
+{
+    if (!t) return BDU_EINVAL;
+    if (t->poisoned) return BDU_EDEVICE;
+    double out[2];
+    const int st = track_orth(t, false, 0.0, out);
+    if (st != BDU_OK) return st;
+    if (eu) *eu = out[0];
+    if (ev) *ev = out[1];
+    return BDU_OK;
+}
+
+int bdu_track_reorthogonalize(bdu_track t, double tol, double *eu, double *ev)
+{
+    if (!t || !(tol == tol)) return BDU_EINVAL;
+    if (t->poisoned) return BDU_EDEVICE;
+    double out[2];
+    const int st = track_orth(t, true, tol, out);
+    if (st != BDU_OK) return st;
+    if (eu) *eu = out[0];
+    if (ev) *ev = out[1];
+    return BDU_OK;
+}
+
+int bdu_track_set_drift_check(bdu_track t, int64_t period, double tol)
+{
+    if (!t || period < 0 || !(tol == tol)) return BDU_EINVAL;
+    t->check_period = period;
+    t->check_tol = tol;
+    t->since_check = 0;
+    return BDU_OK;
+}
+
+int bdu_track_drift_stats(bdu_track t, int64_t *checks, int64_t *corrections, double *eu, double *ev)
+{
+    if (!t) return BDU_EINVAL;
+    if (checks) *checks = t->checks;
+    if (corrections) *corrections = t->corrections;
+    if (eu) *eu = t->drift[0];
+    if (ev) *ev = t->drift[1];
+    return BDU_OK;
 }
 
 int bdu_track_destroy(bdu_track t)

@@ -260,6 +260,10 @@ def test_tracking_rejects_bad_sizes_without_a_device():
                               ctypes.byref(h)) == bdu.BDU_EINVAL
     assert L.bdu_track_update(None, None, None) == bdu.BDU_EINVAL
     assert L.bdu_track_last(None, None, None, None) == bdu.BDU_EINVAL
+    assert L.bdu_track_orth_error(None, None, None) == bdu.BDU_EINVAL
+    assert L.bdu_track_reorthogonalize(None, 0.0, None, None) == bdu.BDU_EINVAL
+    assert L.bdu_track_set_drift_check(None, 5, 1e-12) == bdu.BDU_EINVAL
+    assert L.bdu_track_drift_stats(None, None, None, None, None) == bdu.BDU_EINVAL
     assert L.bdu_strerror(bdu.BDU_ESPAN) == b"rank-1 tracker with an update vector in the span of its basis"
 
 
