@@ -295,10 +295,16 @@ def hetero(torch, bdu, args) -> int:
 
 def serve(torch, bdu, args) -> int:
     """Served load: R resident square streams, n uniform over {512, ..., 8192};
-    requests arrive as a Poisson process at the given rate, uniform over the
-    streams, rank 1/2/4/8 with probability 0.6/0.2/0.1/0.1, Gaussian b, c.
-    Reports accepted rank-1-equivalent updates/s and the latency of completed
-    requests; requests that find their stream's queue full are rejected."""
+    requests arrive as a Poisson process, uniform over the streams, rank
+    1/2/4/8 with probability 0.6/0.2/0.1/0.1, Gaussian b, c.  Requests that
+    find their stream's queue full are rejected.  Two runs on the same
+    resident streams: one at the given rate (saturating at the default), then
+    a search for the highest sustainable rate, starting at 0.9 x the accepted
+    request rate of the first run and stepping down by 0.85: a rate is
+    sustainable when at most 1 % of its arrivals are rejected and its p99
+    latency is not growing (the second half of the window, drain included,
+    within 1.25 x the first half's p99 + 50 ms).  Each run reports accepted rank-1-equivalent updates/s (arrival window
+    and drain) and the latency of its completed requests."""
     rng = np.random.default_rng(args.seed)
     gen = torch.Generator(device="cuda:0")
     gen.manual_seed(args.seed)
@@ -318,6 +324,7 @@ def serve(torch, bdu, args) -> int:
         del Q, P
     torch.cuda.empty_cache()
     live = [(sid, n) for sid, n in zip(sids, sizes) if sid is not None]
+    admission = srv.stats()
     # pre-drawn update vectors per size and rank, in host memory as a client
     # would send them (the server copies its inputs)
     ranks = [1, 2, 4, 8]
@@ -325,44 +332,86 @@ def serve(torch, bdu, args) -> int:
                      np.asfortranarray(rng.standard_normal((n, r)) / math.sqrt(n)))
             for n in set(n for _, n in live) for r in ranks}
     torch.cuda.synchronize()
-    submitted = busy = accepted_r1 = 0
-    t0 = time.perf_counter()
-    next_t = t0
-    while True:
-        now = time.perf_counter()
-        if now - t0 >= args.serve:
-            break
-        if now < next_t:
-            time.sleep(min(next_t - now, 0.01))
-            continue
-        next_t += rng.exponential(1.0 / args.serve_rate)
-        sid, n = live[rng.integers(len(live))]
-        r = int(rng.choice(ranks, p=[0.6, 0.2, 0.1, 0.1]))
-        B, C = pool[(n, r)]
-        try:
-            srv.submit(sid, B, C, detach=True)
-            submitted += 1
-            accepted_r1 += r
-        except bdu.BduError as err:
-            if err.status != bdu.BDU_EBUSY:
-                raise
-            busy += 1
-    t_arrivals = time.perf_counter() - t0
-    srv.drain()
-    t_all = time.perf_counter() - t0
-    st = srv.stats()
+
+    def run(rate: float, seconds: float, halves: bool) -> dict:
+        """Poisson arrivals at `rate` for `seconds`, then a drain.  With
+        halves, the latency statistics are read at half time and again after
+        the drain, so the two halves' p99 can be compared."""
+        srv.reset_stats()
+        submitted = busy = accepted_r1 = 0
+        first_half = None
+        t0 = time.perf_counter()
+        next_t = t0
+        while True:
+            now = time.perf_counter()
+            if now - t0 >= seconds:
+                break
+            if halves and first_half is None and now - t0 >= seconds / 2:
+                first_half = srv.stats()
+                srv.reset_stats()
+            if now < next_t:
+                time.sleep(min(next_t - now, 0.01))
+                continue
+            next_t += rng.exponential(1.0 / rate)
+            sid, n = live[rng.integers(len(live))]
+            r = int(rng.choice(ranks, p=[0.6, 0.2, 0.1, 0.1]))
+            B, C = pool[(n, r)]
+            try:
+                srv.submit(sid, B, C, detach=True)
+                submitted += 1
+                accepted_r1 += r
+            except bdu.BduError as err:
+                if err.status != bdu.BDU_EBUSY:
+                    raise
+                busy += 1
+        t_arrivals = time.perf_counter() - t0
+        srv.drain()
+        t_all = time.perf_counter() - t0
+        st = srv.stats()
+        out = {"rate": rate, "value": accepted_r1 / t_all, "requests_per_s": submitted / t_all,
+               "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"], "max_ms": st["max_ms"],
+               "requests_accepted": submitted, "requests_rejected_busy": busy, "rounds": st["rounds"],
+               "mean_round_size": st["batched_passes"] / max(st["rounds"], 1),
+               "arrival_window_s": t_arrivals, "drain_s": t_all - t_arrivals}
+        if halves and first_half is not None:
+            out["first_half_p99_ms"] = first_half["p99_ms"]
+            out["first_half_p50_ms"] = first_half["p50_ms"]
+            out["rounds"] += first_half["rounds"]
+        return out
+
+    first = run(args.serve_rate, args.serve, False)
+    tried = []
+    sustain = None
+    if args.serve_search:
+        # stable: at most 1 % of arrivals rejected, and the second half's
+        # p99 (through the drain) within 1.25 x the first half's + 50 ms
+        rate = 0.9 * first["requests_per_s"]
+        for _ in range(args.serve_search):
+            x = run(rate, args.serve, True)
+            tried.append({k: x.get(k) for k in ("rate", "requests_accepted", "requests_rejected_busy", "drain_s",
+                                                 "first_half_p99_ms", "p50_ms", "p99_ms")})
+            offered = x["requests_accepted"] + x["requests_rejected_busy"]
+            if ("first_half_p99_ms" in x and x["requests_rejected_busy"] <= 0.01 * max(offered, 1)
+                    and x["p99_ms"] <= 1.25 * x["first_half_p99_ms"] + 50.0):
+                sustain = x
+                break
+            rate *= 0.85
     srv.close()
-    print(json.dumps({
+    line = {
         "metric": "FP64 served rank-1-equivalent updates/sec, p50/p99 latency of completed requests",
-        "value": accepted_r1 / t_all, "unit": "rank-1 updates/s", "dtype": "f64", "data": "synthetic",
-        "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"], "max_ms": st["max_ms"],
+        "value": first["value"], "unit": "rank-1 updates/s", "dtype": "f64", "data": "synthetic",
+        "p50_ms": first["p50_ms"], "p99_ms": first["p99_ms"], "mean_ms": first["mean_ms"], "max_ms": first["max_ms"],
         "config": {"workload": f"{R} resident square streams, n uniform over {{{args.serve_sizes}}}, Poisson arrivals "
                                f"{args.serve_rate}/s for {args.serve} s, ranks 1/2/4/8 w.p. .6/.2/.1/.1",
-                   "streams_admitted": len(live), "streams_rejected_memory": st["rejected_memory"],
-                   "budget_gb": args.serve_budget_gb, "queue_cap": args.serve_queue},
-        "requests_accepted": submitted, "requests_rejected_busy": busy, "rounds": st["rounds"],
-        "mean_round_size": st["batched_passes"] / max(st["rounds"], 1),
-        "arrival_window_s": t_arrivals, "drain_included_s": t_all}))
+                   "streams_admitted": len(live), "streams_rejected_memory": admission["rejected_memory"],
+                   "budget_gb": args.serve_budget_gb, "queue_cap": args.serve_queue,
+                   "size_classes": "n <= 1024, <= 2048, <= 4096, larger"},
+        "requests_accepted": first["requests_accepted"], "requests_rejected_busy": first["requests_rejected_busy"],
+        "rounds": first["rounds"], "mean_round_size": first["mean_round_size"],
+        "arrival_window_s": first["arrival_window_s"], "drain_included_s": first["arrival_window_s"] + first["drain_s"],
+        "sustainable": sustain, "sustainable_search": tried,
+    }
+    print(json.dumps(line))
     return 0
 
 
@@ -667,6 +716,8 @@ def main() -> int:
     ap.add_argument("--serve-rate", type=float, default=20000.0)
     ap.add_argument("--serve-queue", type=int, default=4)
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
+    ap.add_argument("--serve-search", type=int, default=6,
+                    help="after the --serve run, at most this many lower rates tried for the sustainable one")
     ap.add_argument("--orth", action="store_true",
                     help="time the orthogonality monitor and correction at m = n = --n")
     ap.add_argument("--orth-steps", type=int, default=10)

@@ -98,12 +98,22 @@ int bdu_update_batched(const bdu_handle *hs, const double *const *Bs,
  * Results are bit-identical to bdu_update on each handle.  From the second
  * step on, a step's launches are captured once in a HIP graph and replayed
  * (not while stage timing is on).  The call returns once host inputs are
- * consumed; bdu_batch_sync waits for the batch stream.  Later calls on a
- * member handle are ordered after the batch's last step.  The handles must
+ * consumed; bdu_batch_sync waits for the batch stream.  The batch stream
+ * does not synchronize implicitly with the null stream (so that capturing
+ * its graph never conflicts with null-stream work of other threads): each
+ * step is ordered after the work queued on the null stream and on every
+ * member's stream before the call, by events.  Later calls on a member
+ * handle are ordered after the batch's last step.  The handles must
  * outlive the batch, and must not be destroyed or used by another thread
  * while a step is being queued.  bdu_batch_info fills out[5] = {handles,
  * max_rank, launch groups, graph captured (0/1), steps queued}. */
 int bdu_batch_create(const bdu_handle *hs, int count, int max_rank, bdu_batch *out);
+/* As bdu_batch_create, with flags: BDU_BATCH_EAGER launches every step
+ * eagerly (no graph capture) on the first handle's stream instead of a
+ * stream of the batch's own; for callers that queue steps from several
+ * threads while other threads also use the device. */
+#define BDU_BATCH_EAGER 1
+int bdu_batch_create_flags(const bdu_handle *hs, int count, int max_rank, int flags, bdu_batch *out);
 int bdu_batch_update(bdu_batch b, const double *const *Bs, const double *const *Cs,
                      const int *rs);
 int bdu_batch_sync(bdu_batch b);
@@ -204,17 +214,28 @@ int bdu_tune_load(const char *path);
 int bdu_handle_tiling(bdu_handle h, int *k0, int *nw, int *rpl);
 
 /* Serving (the served form of the update): resident streams admitted
- * against a device-memory budget, bounded per-stream request queues, and a
- * worker thread that batches continuously at the granularity of rank-1
- * passes (a rank-r request is r passes, Section 3.2, eq. (rk1)).  Each round the worker
- * takes the next pass of the oldest pending request of up to max_batch
- * streams (oldest first) and runs them as one batched rank-1 update, so
- * every stream's passes are applied in submission order and each result is
- * bit-identical to the stream's own sequence of bdu_update calls.  A round
- * lasts one pass, so short requests are not held back by long ones.
+ * against a device-memory budget, bounded per-stream request queues, and
+ * continuous batching at the granularity of rank-1 passes (a rank-r request
+ * is r passes, Section 3.2, eq. (rk1)).  Streams are grouped in size
+ * classes by n; each class has its own worker thread and HIP stream, so the
+ * classes' rounds run concurrently and small streams do not wait for the
+ * rounds of large ones.  Each round a class's worker takes the next pass of
+ * the oldest pending request of up to max_batch of its streams (oldest
+ * first) and runs them as one batched rank-1 step, so every stream's passes
+ * are applied in submission order and each result is bit-identical to the
+ * stream's own sequence of bdu_update calls.  A round lasts one pass, so
+ * short requests are not held back by long ones.  A class keeps one batch
+ * over all its streams (rank 0 for those without work in a round, launched
+ * eagerly), rebuilt only when a stream of the class opens or closes: rounds
+ * allocate no device memory.
  *
  * bdu_server_create: budget_bytes of device memory for resident streams
- *   (each costs bdu_footprint_bytes(m, n)), queue_cap requests per stream.
+ *   (each costs bdu_footprint_bytes(m, n)), queue_cap requests per stream,
+ *   size classes n <= 1024, <= 2048, <= 4096 and larger.
+ * bdu_server_create_classes: the same with the classes' ascending upper
+ *   bounds of n given (nbounds of them, 0..15, each >= 2; one more class
+ *   takes every larger n).
+ * bdu_server_class_of: the class (0-based) a stream of n columns joins.
  * bdu_server_open: admit a stream (arguments as bdu_create); BDU_ENOMEM when
  *   the budget would be exceeded (counted, the server is unchanged).
  * bdu_server_submit: queue A_s <- A_s + B C^T (B m x r, C n x r, host or
@@ -225,18 +246,25 @@ int bdu_handle_tiling(bdu_handle h, int *k0, int *nw, int *rpl);
  * bdu_server_wait: block until the request is done; its latency (submit to
  *   completion) in ms.  bdu_server_poll: 1 done, 0 pending.
  * bdu_server_drain: wait until no request is queued or running.
- * bdu_server_pause: 1 stops the worker from starting rounds, 0 resumes.
+ * bdu_server_pause: 1 stops the workers from starting rounds, 0 resumes.
  * bdu_server_read / bdu_server_close: wait until the stream has no queued or
  *   running request, then read (as bdu_read) / destroy it and return its
- *   budget.  Both fail (BDU_EINVAL) on a paused server with queued requests.
+ *   budget (requests submitted to a stream while it closes fail with
+ *   BDU_EINVAL).  Both fail (BDU_EINVAL) on a paused server with queued
+ *   requests.
  * bdu_server_stats: counts[9] = {completed, rejected busy, rejected for
  *   memory, rounds, passes run in rounds, open streams, budget bytes in
  *   use, requests pending, failed}; latency[4] = {p50, p99, mean, max} in ms
- *   over completed requests.
- * bdu_server_destroy: runs what is queued (unless paused), stops the worker
- *   and destroys every stream; no call on the server may be in progress. */
+ *   over completed requests.  bdu_server_reset_stats zeroes the counters
+ *   and the latency record (streams and queues stay).
+ * bdu_server_destroy: runs what is queued (unless paused), stops the
+ *   workers and destroys every stream; no call on the server may be in
+ *   progress. */
 typedef struct bdu_server_ctx *bdu_server;
 int bdu_server_create(int64_t budget_bytes, int queue_cap, int max_batch, bdu_server *out);
+int bdu_server_create_classes(int64_t budget_bytes, int queue_cap, int max_batch, const int64_t *bounds,
+                              int nbounds, bdu_server *out);
+int bdu_server_class_of(bdu_server s, int64_t n);
 int bdu_server_open(bdu_server s, int64_t m, int64_t n, const double *Q, const double *d,
                     const double *e, const double *P, int *stream_id);
 int bdu_server_submit(bdu_server s, int stream_id, const double *B, const double *C, int r,
@@ -248,6 +276,7 @@ int bdu_server_pause(bdu_server s, int paused);
 int bdu_server_read(bdu_server s, int stream_id, double *Q, double *d, double *e, double *P);
 int bdu_server_close(bdu_server s, int stream_id);
 int bdu_server_stats(bdu_server s, int64_t *counts, double *latency);
+int bdu_server_reset_stats(bdu_server s);
 int bdu_server_destroy(bdu_server s);
 
 /* Stage timing.  bdu_timing_enable(1) clears the log and brackets every

@@ -97,6 +97,9 @@ def lib():
         L.bdu_tune_load.argtypes = [ctypes.c_char_p]
         L.bdu_handle_tiling.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.bdu_server_create.argtypes = [i64, i32, i32, ctypes.POINTER(vp)]
+        L.bdu_server_create_classes.argtypes = [i64, i32, i32, ctypes.POINTER(i64), i32, ctypes.POINTER(vp)]
+        L.bdu_server_class_of.argtypes = [vp, i64]
+        L.bdu_server_reset_stats.argtypes = [vp]
         L.bdu_server_open.argtypes = [vp, i64, i64, vp, vp, vp, vp, ctypes.POINTER(i32)]
         L.bdu_server_submit.argtypes = [vp, i32, vp, vp, i32, ctypes.POINTER(i64)]
         L.bdu_server_wait.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_double)]
@@ -108,6 +111,7 @@ def lib():
         L.bdu_server_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
         L.bdu_server_destroy.argtypes = [vp]
         L.bdu_batch_create.argtypes = [ctypes.POINTER(vp), i32, i32, ctypes.POINTER(vp)]
+        L.bdu_batch_create_flags.argtypes = [ctypes.POINTER(vp), i32, i32, i32, ctypes.POINTER(vp)]
         L.bdu_batch_update.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i32)]
         L.bdu_batch_sync.argtypes = [vp]
         L.bdu_batch_info.argtypes = [vp, ctypes.POINTER(i64)]
@@ -432,12 +436,15 @@ def update_batched(handles, Bs, Cs) -> None:
 class Batch:
     """bdu_batch: a fixed set of distinct handles updated together, step after step."""
 
-    def __init__(self, handles, max_rank: int = 1):
+    def __init__(self, handles, max_rank: int = 1, eager: bool = False):
+        """eager: launch every step eagerly on the first handle's stream (no
+        graph capture; BDU_BATCH_EAGER)."""
         n = len(handles)
         self.handles = list(handles)  # the batch keeps them alive
         hp = (ctypes.c_void_p * n)(*[h.ptr.value for h in handles])
         b = ctypes.c_void_p()
-        _check(lib().bdu_batch_create(hp, n, max_rank, ctypes.byref(b)), "bdu_batch_create")
+        _check(lib().bdu_batch_create_flags(hp, n, max_rank, 1 if eager else 0, ctypes.byref(b)),
+               "bdu_batch_create_flags")
         self._b = b
 
     def update(self, Bs, Cs, ranks=None) -> None:
@@ -485,9 +492,16 @@ class Server:
     STAT_KEYS = ["completed", "rejected_busy", "rejected_memory", "rounds", "batched_passes",
                  "streams", "bytes_in_use", "pending", "failed"]
 
-    def __init__(self, budget_bytes: int, queue_cap: int = 8, max_batch: int = 256):
+    def __init__(self, budget_bytes: int, queue_cap: int = 8, max_batch: int = 256, classes=None):
+        """classes: ascending upper bounds of n of the size classes (None: the
+        library's default 1024, 2048, 4096; [] for a single class)."""
         s = ctypes.c_void_p()
-        _check(lib().bdu_server_create(budget_bytes, queue_cap, max_batch, ctypes.byref(s)), "bdu_server_create")
+        if classes is None:
+            _check(lib().bdu_server_create(budget_bytes, queue_cap, max_batch, ctypes.byref(s)), "bdu_server_create")
+        else:
+            b = (ctypes.c_int64 * max(len(classes), 1))(*classes)
+            _check(lib().bdu_server_create_classes(budget_bytes, queue_cap, max_batch, b, len(classes),
+                                                   ctypes.byref(s)), "bdu_server_create_classes")
         self._s = s
         self.shapes = {}
 
@@ -535,6 +549,12 @@ class Server:
         _check(lib().bdu_server_read(self._s, sid, Q.ctypes.data, d.ctypes.data, e.ctypes.data, P.ctypes.data),
                "bdu_server_read")
         return Q, d, e[: n - 1], P
+
+    def reset_stats(self) -> None:
+        _check(lib().bdu_server_reset_stats(self._s), "bdu_server_reset_stats")
+
+    def class_of(self, n: int) -> int:
+        return _check(lib().bdu_server_class_of(self._s, n), "bdu_server_class_of")
 
     def close_stream(self, sid: int) -> None:
         _check(lib().bdu_server_close(self._s, sid), "bdu_server_close")

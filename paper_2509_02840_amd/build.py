@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libbdu.so")
 
-SOURCES = ["kernels.hip", "gen.hip", "track.hip", "orth.hip", "trbd.hip", "bhu.hip", "bdu.cpp", "plan.cpp", "serve.cpp"]
+SOURCES = ["kernels.hip", "gen.hip", "track.hip", "orth.hip", "trbd.hip", "bhu.hip", "bdu.cpp", "plan.cpp", "serve.cpp", "serve_core.cpp"]
 
 # -ffp-contract=off: only the fma calls written in the source fuse.
 # -packed-fp32-ops off: no packed FP32 instructions are generated.

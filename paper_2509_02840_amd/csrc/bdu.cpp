@@ -499,6 +499,7 @@ struct bdu_batch_ctx {
     int32_t *d_ranks = nullptr;
     int32_t *h_ranks = nullptr;  // pinned staging of the ranks
     hipEvent_t ranks_copied = nullptr, done = nullptr;
+    hipEvent_t null_ready = nullptr;  // own stream: the null stream's work before a step
     // split passes: phase 1 applied on `side` while phase 2 is generated
     hipStream_t side = nullptr;
     hipEvent_t sp1 = nullptr, sp2 = nullptr, sp3 = nullptr;
@@ -519,6 +520,7 @@ void batch_free(bdu_batch b)
     if (b->h_ranks) (void)hipHostFree(b->h_ranks);
     if (b->ranks_copied) (void)hipEventDestroy(b->ranks_copied);
     if (b->done) (void)hipEventDestroy(b->done);
+    if (b->null_ready) (void)hipEventDestroy(b->null_ready);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
     if (b->sp1) (void)hipEventDestroy(b->sp1);
     if (b->sp2) (void)hipEventDestroy(b->sp2);
@@ -547,8 +549,12 @@ int batch_build(const bdu_handle *hs, int count, int maxr, bool graph, bdu_batch
     b->use_graph = graph;
     hipError_t e = hipSuccess;
     if (graph) {
-        e = hipStreamCreate(&b->stream);
+        // non-blocking: a graph is captured on it, and capture on a stream
+        // that synchronizes implicitly with the null stream would fail the
+        // null-stream work of any other thread meanwhile
+        e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
         b->own_stream = e == hipSuccess;
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->null_ready, hipEventDisableTiming);
     } else {
         b->stream = hs[0]->stream;
     }
@@ -1062,6 +1068,13 @@ int bdu_batch_create(const bdu_handle *hs, int count, int max_rank, bdu_batch *o
     return batch_build(hs, count, max_rank, true, out);
 }
 
+int bdu_batch_create_flags(const bdu_handle *hs, int count, int max_rank, int flags, bdu_batch *out)
+{
+    if (!out || (flags & ~BDU_BATCH_EAGER)) return BDU_EINVAL;
+    *out = nullptr;
+    return batch_build(hs, count, max_rank, !(flags & BDU_BATCH_EAGER), out);
+}
+
 int bdu_batch_update(bdu_batch b, const double *const *Bs, const double *const *Cs, const int *rs)
 {
     if (!b || !rs) return BDU_EINVAL;
@@ -1078,6 +1091,11 @@ int bdu_batch_update(bdu_batch b, const double *const *Bs, const double *const *
         for (bdu_ctx *h : b->hs) h->poisoned = true;
         return BDU_EDEVICE;
     };
+    // the batch's own stream is ordered after the null stream's earlier
+    // work explicitly (it does not synchronize with it implicitly)
+    if (b->own_stream &&
+        (hipEventRecord(b->null_ready, nullptr) != hipSuccess || hipStreamWaitEvent(st, b->null_ready, 0) != hipSuccess))
+        return fail();
     // inputs, in stream order after each handle's own work
     for (int i = 0; i < count; ++i) {
         bdu_ctx *h = b->hs[i];

@@ -56,11 +56,12 @@ def _check(hs, refs, what):
             _eq(f"{what}, stream {i} {nm}", x, y)
 
 
-def test_batch_steps_replayed_graph_match_oracle(bdu, oracle):
+@pytest.mark.parametrize("eager", [False, True])
+def test_batch_steps_replayed_graph_match_oracle(bdu, oracle, eager):
     hs, refs = _streams(bdu, oracle, 300)
     other = bdu.Handle(*(lambda f: (f.Q, f.d, f.e, f.P))(W.factorization(80, 80, 399)))
     (ob, oc), = W.gaussian_updates(80, 80, 1, 398)
-    batch = bdu.Batch(hs, max_rank=3)
+    batch = bdu.Batch(hs, max_rank=3, eager=eager)
     rng = np.random.default_rng(301)
     try:
         for step in range(6):
@@ -83,7 +84,7 @@ def test_batch_steps_replayed_graph_match_oracle(bdu, oracle):
             info = batch.info()
             assert info["steps"] == step + 1
             assert info["groups"] == 6  # (12,7,1) (12,4,2) (6,2,1) (12,8,1) (6,4,2) (12,1,1)
-            assert info["graph"] == (1 if step >= 1 else 0)
+            assert info["graph"] == (1 if step >= 1 and not eager else 0)
     finally:
         batch.close()
         other.close()

@@ -165,3 +165,75 @@ def test_rounds_batch_passes_so_short_requests_finish_first(bdu, oracle):
                 _eq(f"stream {sid} {nm}", x, y)
     finally:
         srv.close()
+
+
+@pytest.mark.parametrize("classes,rounds", [([], 8), ([100], 9)])
+def test_size_classes_run_their_own_rounds(bdu, oracle, classes, rounds):
+    """A rank-8 request on a large stream and a rank-1 request on a small
+    one: with one class the small pass rides in the first of the large
+    stream's eight rounds; with the two streams in different classes it
+    runs in a round of its own, concurrently, and waits for none of them.
+    Results are bit-identical either way."""
+    srv = bdu.Server(budget_bytes=1 << 34, queue_cap=4, max_batch=16, classes=classes)
+    try:
+        fa, fb = W.factorization(300, 280, 570), W.factorization(64, 50, 571)
+        assert srv.class_of(280) == len(classes) and srv.class_of(50) == 0
+        a = srv.open(fa.Q, fa.d, fa.e, fa.P)
+        b = srv.open(fb.Q, fb.d, fb.e, fb.P)
+        (Ba, Ca), = W.gaussian_updates(300, 280, 1, 572, r=8)
+        (Bb, Cb), = W.gaussian_updates(64, 50, 1, 573, r=1)
+        srv.pause(True)
+        ta = srv.submit(a, Ba, Ca)
+        tb = srv.submit(b, Bb, Cb)
+        srv.pause(False)
+        srv.wait(ta)
+        srv.wait(tb)
+        st = srv.stats()
+        assert st["rounds"] == rounds and st["batched_passes"] == 9 and st["completed"] == 2
+        ra, rb = oracle.State(fa.Q, fa.d, fa.e, fa.P), oracle.State(fb.Q, fb.d, fb.e, fb.P)
+        oracle.bgu_update(ra, Ba, Ca)
+        oracle.bgu_update(rb, Bb, Cb)
+        for sid, ref in ((a, ra), (b, rb)):
+            for nm, x, y in zip("QdeP", srv.read(sid), (ref.Q, ref.d, ref.e, ref.P)):
+                _eq(f"stream {sid} {nm}", x, y)
+    finally:
+        srv.close()
+
+
+def test_streams_open_and_close_while_other_classes_run(bdu, oracle):
+    """Membership changes rebuild a class's batch between its rounds; the
+    other classes keep serving, and every stream ends equal to the oracle."""
+    srv = bdu.Server(budget_bytes=1 << 34, queue_cap=8, max_batch=16, classes=[64, 128])
+    try:
+        shapes = [(60, 40), (100, 90), (200, 150), (50, 50)]
+        fs = [W.factorization(m, n, 580 + i) for i, (m, n) in enumerate(shapes)]
+        refs = [oracle.State(f.Q, f.d, f.e, f.P) for f in fs]
+        sids = [srv.open(f.Q, f.d, f.e, f.P) for f in fs[:3]]
+        tickets = []
+        for k in range(4):
+            for i in range(3):
+                m, n = shapes[i]
+                (B, C), = W.gaussian_updates(m, n, 1, 590 + 10 * k + i, r=1 + (k + i) % 2)
+                tickets.append(srv.submit(sids[i], B, C))
+                oracle.bgu_update(refs[i], B, C)
+            if k == 1:  # a fourth stream joins class 0 mid-load
+                sids.append(srv.open(fs[3].Q, fs[3].d, fs[3].e, fs[3].P))
+            if k >= 1:
+                m, n = shapes[3]
+                (B, C), = W.gaussian_updates(m, n, 1, 700 + k)
+                tickets.append(srv.submit(sids[3], B, C))
+                oracle.bgu_update(refs[3], B, C)
+        for t in tickets:
+            srv.wait(t)
+        for i, sid in enumerate(sids):
+            for nm, x, y in zip("QdeP", srv.read(sid), (refs[i].Q, refs[i].d, refs[i].e, refs[i].P)):
+                _eq(f"stream {i} {nm}", x, y)
+        srv.close_stream(sids[0])  # class 0 rebuilt without it; stream 3 still served
+        (B, C), = W.gaussian_updates(50, 50, 1, 710)
+        srv.wait(srv.submit(sids[3], B, C))
+        oracle.bgu_update(refs[3], B, C)
+        for nm, x, y in zip("QdeP", srv.read(sids[3]), (refs[3].Q, refs[3].d, refs[3].e, refs[3].P)):
+            _eq(f"stream 3 after close {nm}", x, y)
+        assert srv.stats()["failed"] == 0
+    finally:
+        srv.close()
