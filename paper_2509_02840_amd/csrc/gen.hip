@@ -260,6 +260,10 @@ __global__ __launch_bounds__(kGenThreads) void gen_kernel(HandleDev *const *hs, 
             ky1 = h->carry[4 * tid + 3];
         }
     }
+    // wait for the carries here: a load still in flight at the tick loop
+    // would make the loop wait on the vector memory counter in every tick,
+    // and that counter also counts the coefficient stores
+    asm volatile("" ::"v"(kx0), "v"(kx1), "v"(ky0), "v"(ky1));
     // One rotation with its window, for one phase (the phase is uniform
     // across a wavefront except where phase 2 starts, so a wavefront
     // normally runs one of the two bodies).
