@@ -36,18 +36,17 @@ METRIC = "FP64 rank-1 updates/sec + p50/p99 latency, batched vs plain, n=2048"
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CUs x 128 FP64 flop/clk x 2.4 GHz
 
 # HBM bytes of one applier launch (the average over a pass's launches, one
-# per segment of the pass) for the tilings the batched autotuner picks, from
+# per segment of the pass) for the tiling the batched autotuner picks, from
 # rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of this script
-# (profiles/apply_staged_kernel_n2048_s64_traffic.md,
-# profiles/apply_staged_kernel_12_15_1_n2048_s64_traffic.md),
-# each scaled by what the counter reads for a plain 1 GiB device copy
-# (bench.py --copy-probe).  Valid only for the sources with this digest and
-# the workload named; otherwise the traffic is reported as null.
+# (profiles/apply_staged_kernel_n2048_s64_traffic.md), each scaled by what
+# the counter reads for a plain 1 GiB device copy (bench.py --copy-probe).
+# Valid only for the sources with this digest and the workload named;
+# otherwise the traffic is reported as null.
 TRAFFIC_SOURCES = ["paper_2509_02840_amd/csrc/kernels.hip", "paper_2509_02840_amd/csrc/primitives.h",
                    "paper_2509_02840_amd/csrc/schedule.h", "paper_2509_02840_amd/csrc/device.h",
                    "paper_2509_02840_amd/csrc/plan.cpp", "paper_2509_02840_amd/csrc/bdu.cpp"]
-MEASURED_TRAFFIC = {"sha256": "36916e1a829e2805b21a3e9afd6f4dbf98d1a4e82dffad009ff6c903630ff2c1", "n": 2048, "streams": 64,
-                    "bytes": {(12, 7, 1): 54794952701.0, (12, 15, 1): 27048479386.2}}
+MEASURED_TRAFFIC = {"sha256": "e2785d62dc0601f0e1103538ee68e6ea9efa197aecfabf20f8b5d7e19142d85f", "n": 2048, "streams": 64,
+                    "bytes": {(12, 7, 1): 55457642734.6}}
 
 
 def sources_digest() -> str:
