@@ -204,28 +204,77 @@ __global__ void track_truncate_kernel(TrackMiddle mid, int r, double *d, double 
 // and w (the unit complement) only on an augmented side.  Flipped
 // (U2 = U J P3 J, V2 = [V, w] diag(J,1) Q3(:, 1:r) J): M is the middle P
 // for side 0 and Q for side 1, rm(l) = r - 1 - l, cm(j) = r - 1 - j, and w
-// on side 1 only.  grid (ceil(rows / 256), r, 2 sides).
+// on side 1 only.
+//
+// Register-tiled outer products: a thread accumulates kProdRows rows (256
+// apart) by kProdCols columns of out, l running in order over the whole
+// sum, so every entry is still the sequential fma chain above.  The block's
+// kProdCols columns of M are staged in LDS kProdChunk rows of l at a time
+// and read as broadcasts; A streams once per block of kProdCols columns.
+// grid (ceil(rows / (256 kProdRows)), ceil(r / kProdCols), 2 sides).
+constexpr int kProdRows = 2, kProdCols = 32, kProdChunk = 64;
+
 __global__ __launch_bounds__(256) void track_product_kernel(TrackSides s, TrackMiddle mid, const int *kdrop,
                                                             double *out0, double *out1)
 {
+    __shared__ double Ms[kProdChunk][kProdCols];
     const int side = blockIdx.z;
     const TrackSide &t = s.side[side];
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= t.rows) return;
-    const int j = blockIdx.y;
+    const int64_t rows = t.rows;
+    const int64_t i0 = (int64_t)blockIdx.x * (256 * kProdRows) + threadIdx.x;
+    if ((int64_t)blockIdx.x * (256 * kProdRows) >= rows) return;  // the other side has more rows
     const int r = (int)t.cols;
+    const int j0 = blockIdx.y * kProdCols;
     const int k = *kdrop;
     const bool useQ = mid.flip ? side == 1 : side == 0;
-    const int cj = mid.flip ? r - 1 - j : (k >= 0 && j >= k ? j + 1 : j);
-    const double *M = useQ ? mid.Q + (int64_t)cj * mid.ldq : mid.P + (int64_t)cj * mid.ldp;
+    const double *Mb = useQ ? mid.Q : mid.P;
+    const int64_t ldm = useQ ? mid.ldq : mid.ldp;
     const bool with_w = mid.flip ? side == 1 : mid.aug[side] != 0;
-    double acc = 0.0;
-    if (mid.flip)
-        for (int l = 0; l < r; ++l) acc = fma(t.A[i + (int64_t)l * t.lda], M[r - 1 - l], acc);
-    else
-        for (int l = 0; l < r; ++l) acc = fma(t.A[i + (int64_t)l * t.lda], M[l], acc);
-    if (with_w) acc = fma(t.xperp[i], M[r], acc);
-    (side == 0 ? out0 : out1)[i + (int64_t)j * t.lda] = acc;
+    auto colof = [&](int j) { return mid.flip ? r - 1 - j : (k >= 0 && j >= k ? j + 1 : j); };
+    double acc[kProdRows][kProdCols];
+#pragma unroll
+    for (int q = 0; q < kProdRows; ++q)
+#pragma unroll
+        for (int c = 0; c < kProdCols; ++c) acc[q][c] = 0.0;
+    for (int l0 = 0; l0 < r; l0 += kProdChunk) {
+        __syncthreads();
+        for (int x = threadIdx.x; x < kProdChunk * kProdCols; x += 256) {
+            const int ll = x % kProdChunk, c = x / kProdChunk, l = l0 + ll, j = j0 + c;
+            Ms[ll][c] = (l < r && j < r) ? Mb[(mid.flip ? r - 1 - l : l) + (int64_t)colof(j) * ldm] : 0.0;
+        }
+        __syncthreads();
+        const int lend = r - l0 < kProdChunk ? r - l0 : kProdChunk;
+        for (int ll = 0; ll < lend; ++ll) {
+            const int64_t col = (int64_t)(l0 + ll) * t.lda;
+            double a[kProdRows];
+#pragma unroll
+            for (int q = 0; q < kProdRows; ++q) {
+                const int64_t i = i0 + 256 * q;
+                a[q] = i < rows ? t.A[i + col] : 0.0;
+            }
+#pragma unroll
+            for (int c = 0; c < kProdCols; ++c) {
+                const double m = Ms[ll][c];
+#pragma unroll
+                for (int q = 0; q < kProdRows; ++q) acc[q][c] = fma(a[q], m, acc[q][c]);
+            }
+        }
+    }
+    double *out = side == 0 ? out0 : out1;
+#pragma unroll
+    for (int c = 0; c < kProdCols; ++c) {
+        const int j = j0 + c;
+        if (j >= r) break;
+        const double mw = with_w ? Mb[r + (int64_t)colof(j) * ldm] : 0.0;
+#pragma unroll
+        for (int q = 0; q < kProdRows; ++q) {
+            const int64_t i = i0 + 256 * q;
+            if (i >= rows) continue;
+            double v = acc[q][c];
+            if (with_w) v = fma(t.xperp[i], mw, v);
+            out[i + (int64_t)j * t.lda] = v;
+        }
+    }
 }
 
 hipError_t launch_track_project(const TrackSides &s, int64_t max_rows, int64_t r, double *part, hipStream_t st)
@@ -273,8 +322,9 @@ hipError_t launch_track_finish(const TrackSides &s, const TrackMiddle &mid, doub
                                int64_t max_rows, int64_t r, double *out0, double *out1, hipStream_t st)
 {
     hipLaunchKernelGGL(track_truncate_kernel, dim3(1), dim3(64), 0, st, mid, (int)r, d, e, kdrop);
-    hipLaunchKernelGGL(track_product_kernel, dim3((unsigned)((max_rows + 255) / 256), (unsigned)r, 2), dim3(256), 0,
-                       st, s, mid, kdrop, out0, out1);
+    hipLaunchKernelGGL(track_product_kernel, dim3((unsigned)((max_rows + 256 * kProdRows - 1) / (256 * kProdRows)),
+                                                   (unsigned)((r + kProdCols - 1) / kProdCols), 2),
+                       dim3(256), 0, st, s, mid, kdrop, out0, out1);
     return hipGetLastError();
 }
 
