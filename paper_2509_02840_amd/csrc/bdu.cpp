@@ -345,18 +345,35 @@ hipError_t run_split_stages(HandleDev *const *hs, int count, bool any_spike, int
 // The stages of a pass in nseg segments (every listed handle's plan has
 // that many): segment k's application on sd once its generation is done,
 // the next segment's generation beside it; st waits for the application.
+// With fold_seg > 0 (and the events spk_in, spk_out) the spike runs on sd
+// beside the first segments' generation: phase 1 does not touch u beyond
+// row N - 1, so only the segment holding the fold, which reads u_N (the
+// spike's survivor), waits for it; the generator reloads u_N at the start
+// of every later segment.  Segment 0's application, which applies the
+// spike's rotations, follows it on sd.
 hipError_t run_segment_stages(HandleDev *const *hs, int count, bool any_spike, int64_t lds_bytes, bool in_lds,
                               int gen_threads, int max_panels, int k0, int nw, int rpl, Gate gate, int nseg,
-                              hipStream_t st, hipStream_t sd, const hipEvent_t *ev, hipEvent_t done)
+                              hipStream_t st, hipStream_t sd, const hipEvent_t *ev, hipEvent_t done,
+                              int fold_seg = 0, hipEvent_t spk_in = nullptr, hipEvent_t spk_out = nullptr)
 {
     hipError_t e = hipSuccess;
     Gate g0 = gate;
     g0.part = 3;
-    if (any_spike) e = timed(ST_SPIKE, st, [&] { return launch_spike(hs, count, g0, st); });
+    const bool beside = any_spike && fold_seg > 0 && spk_in && spk_out;
+    if (beside) {
+        e = hipEventRecord(spk_in, st);  // the projections are done
+        if (e == hipSuccess) e = hipStreamWaitEvent(sd, spk_in, 0);
+        if (e == hipSuccess) e = timed(ST_SPIKE, sd, [&] { return launch_spike(hs, count, g0, sd); });
+        if (e == hipSuccess) e = hipEventRecord(spk_out, sd);
+    } else if (any_spike) {
+        e = timed(ST_SPIKE, st, [&] { return launch_spike(hs, count, g0, st); });
+    }
     for (int k = 0; k < nseg && e == hipSuccess; ++k) {
         Gate gk = gate;
         gk.part = 3 + k;
-        e = timed(ST_GEN, st, [&] { return launch_gen(hs, count, lds_bytes, in_lds, gen_threads, gk, st); });
+        if (beside && k == fold_seg) e = hipStreamWaitEvent(st, spk_out, 0);
+        if (e == hipSuccess)
+            e = timed(ST_GEN, st, [&] { return launch_gen(hs, count, lds_bytes, in_lds, gen_threads, gk, st); });
         if (e == hipSuccess) e = hipEventRecord(ev[k], st);
     }
     for (int k = 0; k < nseg && e == hipSuccess; ++k) {
@@ -388,8 +405,11 @@ int pass_single(bdu_ctx *h, int pass, bool project, const double *xb = nullptr, 
     const int64_t lds = gen_lds_bytes(h->n, h->plan->N);
     const int L = h->plan->L, np = panels_of(h), k0 = h->plan->K0, nw = h->plan->NW;
     if (e == hipSuccess && h->side && h->plan->nseg > 0 && h->seg[0]) {
+        // sp1 and sp2 (the split pass's events) order the spike beside the
+        // generation
         e = run_segment_stages(h->d_self, 1, h->m > h->n, lds, h->lds_gen, L, np, k0, nw, h->rpl,
-                               Gate{nullptr, pass, 0}, h->plan->nseg, st, h->side, h->seg, h->sp3);
+                               Gate{nullptr, pass, 0}, h->plan->nseg, st, h->side, h->seg, h->sp3,
+                               h->plan->fold_seg, h->sp1, h->sp2);
     } else if (e == hipSuccess && h->side) {
         e = run_split_stages(h->d_self, 1, h->m > h->n, lds, h->lds_gen, L, np, k0, nw, h->rpl, Gate{nullptr, pass, 0},
                              st, h->side, h->sp1, h->sp2, h->sp3);

@@ -186,6 +186,11 @@ __global__ __launch_bounds__(kGenThreads) void gen_kernel(HandleDev *const *hs, 
     if (t_begin > 0) {
         if (IN_LDS)
             for (int k = tid; k < total; k += nt) S[k] = h->band[k];
+        // u_N, the spike's survivor, is read only by the fold: a pass may
+        // start generating before the spike has finished (the first segment
+        // then read u_N early) and let only the fold's segment wait for it,
+        // so every later segment takes u_N afresh
+        if (N > n && tid == 0) S[UO + N + 3] = h->u[N - 1];
         __syncthreads();
     } else {
         for (int k = tid; k < total; k += nt) S[k] = 0.0;

@@ -216,6 +216,9 @@ std::unique_ptr<Plan> build_plan(int64_t m, int64_t n, int K0, int NW, int gen_t
             prev_t = t;
         }
         if (P->nseg == 0 || P->bcut[P->nseg - 1] != nbt || P->tcut[P->nseg - 1] != P->ticks) P->nseg = 0;
+        for (const GenChain &g : ch)
+            if (g.type == CH_FOLD)
+                while (P->fold_seg + 1 < P->nseg && g.tau0 >= P->tcut[P->fold_seg]) ++P->fold_seg;
     }
     return P;
 }

@@ -19,6 +19,7 @@ struct Plan {
     int64_t split = 0;              // tick where phase 1 ends with nothing in flight (0: no split)
     int nseg = 0;                   // phase-2 segments (HandleDev::tcut, bcut)
     int32_t tcut[kMaxSeg] = {}, bcut[kMaxSeg] = {};
+    int fold_seg = 0;               // the segment whose ticks include the fold
     int64_t nleft = 0, nright = 0;  // rotations of phases 1 and 2 per side
     int64_t nspike = 0;             // spike rotations (m > n)
     std::vector<BlockDesc> blocks[2];  // per side: phase-1 blocks, then phase-2 blocks
