@@ -237,3 +237,69 @@ def test_streams_open_and_close_while_other_classes_run(bdu, oracle):
         assert srv.stats()["failed"] == 0
     finally:
         srv.close()
+
+
+def test_concurrent_clients_across_classes(bdu):
+    """Three client threads submit to streams of three size classes while the
+    main thread opens, updates, reads and closes streams of a fourth; every
+    stream ends equal to the same updates on a lone handle."""
+    import threading
+
+    srv = bdu.Server(budget_bytes=1 << 34, queue_cap=3, max_batch=16, classes=[64, 128, 256])
+    shapes = [(50, 40), (60, 60), (120, 100), (110, 90), (250, 200), (240, 240)]
+    fs = [W.factorization(m, n, 810 + i) for i, (m, n) in enumerate(shapes)]
+    sids = [srv.open(f.Q, f.d, f.e, f.P) for f in fs]
+    alone = [bdu.Handle(f.Q, f.d, f.e, f.P) for f in fs]
+    plans = {i: [W.gaussian_updates(m, n, 1, 820 + 10 * i + k, r=1 + (k % 3))[0] for k in range(8)]
+             for i, (m, n) in enumerate(shapes)}
+    errors = []
+
+    def client(idx):
+        try:
+            tickets = []
+            for k in range(8):
+                for i in idx:
+                    B, C = plans[i][k]
+                    while True:
+                        try:
+                            tickets.append(srv.submit(sids[i], B, C))
+                            break
+                        except bdu.BduError as err:
+                            if err.status != bdu.BDU_EBUSY:
+                                raise
+            for t in tickets:
+                srv.wait(t)
+        except Exception as exc:  # reported by the main thread
+            errors.append(exc)
+
+    threads = [threading.Thread(target=client, args=([0, 1],)), threading.Thread(target=client, args=([2, 3],)),
+               threading.Thread(target=client, args=([4, 5],))]
+    try:
+        for t in threads:
+            t.start()
+        for k in range(4):  # meanwhile: a stream of the largest class opens, updates, reads and closes
+            f = W.factorization(300, 280, 850 + k)
+            sid = srv.open(f.Q, f.d, f.e, f.P)
+            lone = bdu.Handle(f.Q, f.d, f.e, f.P)
+            (B, C), = W.gaussian_updates(300, 280, 1, 860 + k, r=2)
+            srv.wait(srv.submit(sid, B, C))
+            lone.update(B, C)
+            for nm, x, y in zip("QdeP", srv.read(sid), lone.read()):
+                _eq(f"transient stream {k} {nm}", x, y)
+            srv.close_stream(sid)
+            lone.close()
+        for t in threads:
+            t.join(timeout=240)
+        assert not errors, errors
+        for i, updates in plans.items():
+            for B, C in updates:
+                alone[i].update(B, C)
+        for i, sid in enumerate(sids):
+            for nm, x, y in zip("QdeP", srv.read(sid), alone[i].read()):
+                _eq(f"stream {i} (n = {shapes[i][1]}) {nm}", x, y)
+        st = srv.stats()
+        assert st["failed"] == 0 and st["completed"] == 6 * 8 + 4
+    finally:
+        srv.close()
+        for h in alone:
+            h.close()
