@@ -376,6 +376,8 @@ def serve(torch, bdu, args) -> int:
             out["first_half_p99_ms"] = first_half["p99_ms"]
             out["first_half_p50_ms"] = first_half["p50_ms"]
             out["rounds"] += first_half["rounds"]
+        print(f"serve: rate {rate:.3g}/s accepted {submitted} rejected {busy} p50 {st['p50_ms']:.1f} ms "
+              f"p99 {st['p99_ms']:.1f} ms drain {t_all - t_arrivals:.2f} s", file=sys.stderr, flush=True)
         return out
 
     first = run(args.serve_rate, args.serve, False)
