@@ -296,9 +296,11 @@ def serve(torch, bdu, args) -> int:
     """Served load: R resident square streams, n uniform over {512, ..., 8192};
     requests arrive as a Poisson process, uniform over the streams, rank
     1/2/4/8 with probability 0.6/0.2/0.1/0.1, Gaussian b, c.  Requests that
-    find their stream's queue full are rejected.  Two runs on the same
-    resident streams: one at the given rate (saturating at the default), then
-    a search for the highest sustainable rate, starting at 0.9 x the accepted
+    find their stream's queue full are rejected.  Two runs: one at the given
+    rate (saturating at the default) during which new streams arrive as a
+    Poisson process (2/s by default) and are admitted while the device-memory
+    budget allows (else refused and counted), then, on the streams resident
+    by then, a search for the highest sustainable rate, starting at 0.9 x the accepted
     request rate of the first run and stepping down by 0.85: a rate is
     sustainable when at most 1 % of its arrivals are rejected and its p99
     latency is not growing (the second half of the window, drain included,
@@ -327,24 +329,41 @@ def serve(torch, bdu, args) -> int:
     # pre-drawn update vectors per size and rank, in host memory as a client
     # would send them (the server copies its inputs)
     ranks = [1, 2, 4, 8]
+    size_set = sorted(set(int(v) for v in args.serve_sizes.split(",")))
     pool = {(n, r): (np.asfortranarray(rng.standard_normal((n, r)) / math.sqrt(n)),
                      np.asfortranarray(rng.standard_normal((n, r)) / math.sqrt(n)))
-            for n in set(n for _, n in live) for r in ranks}
+            for n in size_set for r in ranks}
     torch.cuda.synchronize()
 
-    def run(rate: float, seconds: float, halves: bool) -> dict:
-        """Poisson arrivals at `rate` for `seconds`, then a drain.  With
-        halves, the latency statistics are read at half time and again after
-        the drain, so the two halves' p99 can be compared."""
+    def run(rate: float, seconds: float, halves: bool, stream_rate: float = 0.0) -> dict:
+        """Poisson arrivals at `rate` for `seconds`, then a drain; new
+        streams (n uniform over the sizes) arrive at `stream_rate` and are
+        admitted while the budget allows.  With halves, the latency
+        statistics are read at half time and again after the drain, so the
+        two halves' p99 can be compared."""
         srv.reset_stats()
-        submitted = busy = accepted_r1 = 0
+        submitted = busy = accepted_r1 = opened = refused = 0
         first_half = None
         t0 = time.perf_counter()
         next_t = t0
+        next_s = t0 + rng.exponential(1.0 / stream_rate) if stream_rate > 0 else float("inf")
         while True:
             now = time.perf_counter()
             if now - t0 >= seconds:
                 break
+            if now >= next_s:
+                n = int(rng.choice(size_set))
+                Q, d, e, P = random_stream(torch, gen, n)
+                try:
+                    live.append((srv.open(Q, d, e, P), n))
+                    opened += 1
+                except bdu.BduError as err:
+                    if err.status != bdu.BDU_ENOMEM:
+                        raise
+                    refused += 1
+                del Q, P
+                next_s += rng.exponential(1.0 / stream_rate)
+                continue
             if halves and first_half is None and now - t0 >= seconds / 2:
                 first_half = srv.stats()
                 srv.reset_stats()
@@ -371,7 +390,9 @@ def serve(torch, bdu, args) -> int:
                "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"], "max_ms": st["max_ms"],
                "requests_accepted": submitted, "requests_rejected_busy": busy, "rounds": st["rounds"],
                "mean_round_size": st["batched_passes"] / max(st["rounds"], 1),
-               "arrival_window_s": t_arrivals, "drain_s": t_all - t_arrivals}
+               "arrival_window_s": t_arrivals, "drain_s": t_all - t_arrivals,
+               "streams_opened": opened, "streams_rejected_memory": refused, "streams_resident": st["streams"],
+               "budget_bytes_in_use": st["bytes_in_use"]}
         if halves and first_half is not None:
             out["first_half_p99_ms"] = first_half["p99_ms"]
             out["first_half_p50_ms"] = first_half["p50_ms"]
@@ -380,7 +401,7 @@ def serve(torch, bdu, args) -> int:
               f"p99 {st['p99_ms']:.1f} ms drain {t_all - t_arrivals:.2f} s", file=sys.stderr, flush=True)
         return out
 
-    first = run(args.serve_rate, args.serve, False)
+    first = run(args.serve_rate, args.serve, False, args.serve_stream_rate)
     tried = []
     sustain = None
     if args.serve_search:
@@ -402,12 +423,16 @@ def serve(torch, bdu, args) -> int:
         "metric": "FP64 served rank-1-equivalent updates/sec, p50/p99 latency of completed requests",
         "value": first["value"], "unit": "rank-1 updates/s", "dtype": "f64", "data": "synthetic",
         "p50_ms": first["p50_ms"], "p99_ms": first["p99_ms"], "mean_ms": first["mean_ms"], "max_ms": first["max_ms"],
-        "config": {"workload": f"{R} resident square streams, n uniform over {{{args.serve_sizes}}}, Poisson arrivals "
-                               f"{args.serve_rate}/s for {args.serve} s, ranks 1/2/4/8 w.p. .6/.2/.1/.1",
+        "config": {"workload": f"{R} resident square streams, n uniform over {{{args.serve_sizes}}}, new streams "
+                               f"Poisson({args.serve_stream_rate}/s) admitted under the budget, update arrivals "
+                               f"Poisson {args.serve_rate}/s for {args.serve} s, ranks 1/2/4/8 w.p. .6/.2/.1/.1",
                    "streams_admitted": len(live), "streams_rejected_memory": admission["rejected_memory"],
                    "budget_gb": args.serve_budget_gb, "queue_cap": args.serve_queue,
                    "size_classes": "n <= 1024, <= 2048, <= 4096, larger"},
         "requests_accepted": first["requests_accepted"], "requests_rejected_busy": first["requests_rejected_busy"],
+        "streams_opened_during_run": first["streams_opened"],
+        "streams_rejected_memory_during_run": first["streams_rejected_memory"],
+        "streams_resident_at_end": first["streams_resident"], "budget_bytes_in_use_at_end": first["budget_bytes_in_use"],
         "rounds": first["rounds"], "mean_round_size": first["mean_round_size"],
         "arrival_window_s": first["arrival_window_s"], "drain_included_s": first["arrival_window_s"] + first["drain_s"],
         "sustainable": sustain, "sustainable_search": tried,
@@ -717,6 +742,8 @@ def main() -> int:
     ap.add_argument("--serve-rate", type=float, default=20000.0)
     ap.add_argument("--serve-queue", type=int, default=4)
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
+    ap.add_argument("--serve-stream-rate", type=float, default=2.0,
+                    help="new streams per second (Poisson) during the --serve run, admitted under the budget")
     ap.add_argument("--serve-search", type=int, default=6,
                     help="after the --serve run, at most this many lower rates tried for the sustainable one")
     ap.add_argument("--orth", action="store_true",
