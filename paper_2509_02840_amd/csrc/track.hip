@@ -170,30 +170,61 @@ __global__ void track_setup_kernel(TrackMiddle mid, TrackSides s, const double *
 // row and column k of the (r+1) x (r+1) result with the smallest column
 // norm (d_k^2 + e_{k-1}^2 as fma(d_k, d_k, e_{k-1} e_{k-1}); ties drop the
 // highest k), with 0 joining k-1 and k+1.  Otherwise the r x r result as it
-// is (reversed back when flipped) and k = -1.  One lane.
-__global__ void track_truncate_kernel(TrackMiddle mid, int r, double *d, double *e, int *kdrop)
+// is (reversed back when flipped) and k = -1.  One block of 256 lanes.
+__global__ __launch_bounds__(256) void track_truncate_kernel(TrackMiddle mid, int r, double *d, double *e,
+                                                             int *kdrop)
 {
-    if (threadIdx.x != 0) return;
+    const int t = threadIdx.x;
     if (!(mid.aug[0] && mid.aug[1])) {
-        for (int j = 0; j < r; ++j) d[j] = mid.d[mid.flip ? r - 1 - j : j];
-        for (int j = 0; j + 1 < r; ++j) e[j] = mid.e[mid.flip ? r - 2 - j : j];
-        *kdrop = -1;
+        for (int j = t; j < r; j += 256) d[j] = mid.d[mid.flip ? r - 1 - j : j];
+        for (int j = t; j + 1 < r; j += 256) e[j] = mid.e[mid.flip ? r - 2 - j : j];
+        if (t == 0) *kdrop = -1;
         return;
     }
+    // The column of least norm, as a scan from j = R - 1 down that keeps the
+    // first strictly smaller value would find it: the smallest value, the
+    // highest index among equal ones, NaN norms never chosen, and R - 1 when
+    // its own norm is NaN (nothing compares below a NaN).  Each lane scans a
+    // strided share, then a tree over the lanes with the same rule.
+    __shared__ double bv[256];
+    __shared__ int bk[256];
     const int R = r + 1;
-    int k = R - 1;
-    double best = fma(mid.d[R - 1], mid.d[R - 1], mid.e[R - 2] * mid.e[R - 2]);
-    for (int j = R - 2; j >= 0; --j) {
-        const double nj = j == 0 ? mid.d[0] * mid.d[0] : fma(mid.d[j], mid.d[j], mid.e[j - 1] * mid.e[j - 1]);
-        if (nj < best) {
+    auto norm = [&](int j) {
+        return j == 0 ? mid.d[0] * mid.d[0] : fma(mid.d[j], mid.d[j], mid.e[j - 1] * mid.e[j - 1]);
+    };
+    double best = 0.0;
+    int k = -1;
+    for (int j = t; j < R; j += 256) {
+        const double nj = norm(j);
+        if (nj == nj && (k < 0 || nj < best || (nj == best && j > k))) {
             best = nj;
             k = j;
         }
     }
-    *kdrop = k;
-    for (int j = 0; j < R - 1; ++j) d[j] = mid.d[j < k ? j : j + 1];
-    for (int j = 0; j + 1 < R - 1; ++j) {
-        const int a = j < k ? j : j + 1, b = j + 1 < k ? j + 1 : j + 2;
+    bv[t] = best;
+    bk[t] = k;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) {
+            const double ov = bv[t + w];
+            const int ok = bk[t + w];
+            if (ok >= 0 && (bk[t] < 0 || ov < bv[t] || (ov == bv[t] && ok > bk[t]))) {
+                bv[t] = ov;
+                bk[t] = ok;
+            }
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        const double top = norm(R - 1);
+        bk[0] = (top != top || bk[0] < 0) ? R - 1 : bk[0];
+        *kdrop = bk[0];
+    }
+    __syncthreads();
+    const int kd = bk[0];
+    for (int j = t; j < R - 1; j += 256) d[j] = mid.d[j < kd ? j : j + 1];
+    for (int j = t; j + 1 < R - 1; j += 256) {
+        const int a = j < kd ? j : j + 1, b = j + 1 < kd ? j + 1 : j + 2;
         e[j] = b == a + 1 ? mid.e[a] : 0.0;
     }
 }
@@ -321,7 +352,7 @@ hipError_t launch_track_setup(const TrackMiddle &mid, const TrackSides &s, const
 hipError_t launch_track_finish(const TrackSides &s, const TrackMiddle &mid, double *d, double *e, int *kdrop,
                                int64_t max_rows, int64_t r, double *out0, double *out1, hipStream_t st)
 {
-    hipLaunchKernelGGL(track_truncate_kernel, dim3(1), dim3(64), 0, st, mid, (int)r, d, e, kdrop);
+    hipLaunchKernelGGL(track_truncate_kernel, dim3(1), dim3(256), 0, st, mid, (int)r, d, e, kdrop);
     hipLaunchKernelGGL(track_product_kernel, dim3((unsigned)((max_rows + 256 * kProdRows - 1) / (256 * kProdRows)),
                                                    (unsigned)((r + kProdCols - 1) / kProdCols), 2),
                        dim3(256), 0, st, s, mid, kdrop, out0, out1);
