@@ -67,6 +67,11 @@ Plan *get_plan(int64_t m, int64_t n, int k0, int nw, bool upload, hipError_t *er
         size_t cb = sizeof(GenChain) * p->chains.size();
         hipError_t e = hipMalloc(&p->d_chains, cb);
         if (e == hipSuccess) e = hipMemcpy(p->d_chains, p->chains.data(), cb, hipMemcpyHostToDevice);
+        if (e == hipSuccess && !p->starts.empty()) {
+            size_t sb = sizeof(GenStart) * p->starts.size();
+            e = hipMalloc(&p->d_starts, sb);
+            if (e == hipSuccess) e = hipMemcpy(p->d_starts, p->starts.data(), sb, hipMemcpyHostToDevice);
+        }
         for (int s = 0; s < 2 && e == hipSuccess; ++s) {
             size_t bb = sizeof(BlockDesc) * p->blocks[s].size();
             e = hipMalloc(&p->d_blocks[s], bb);
@@ -814,6 +819,7 @@ int create_impl(int64_t m, int64_t n, const double *Q, const double *d, const do
     }
     h->rcap = 1;
     hd.chains = plan->d_chains;
+    hd.starts = plan->d_starts;
     hd.blkL = plan->d_blocks[0];
     hd.blkR = plan->d_blocks[1];
     hd.ticks = plan->ticks;

@@ -19,13 +19,17 @@ namespace bdu {
 // Band storage: band_row (device.h).  Entries outside the band read as zero
 // and are never written: the schedule keeps them zero.
 
-// Chain descriptor held in registers (GenChain fields).
+// Chain descriptor held in registers (GenChain fields, and for the in-LDS
+// kernel the chain's GenStart record).
 struct ChainReg {
     int type, param, len, tau0;
     int64_t slot0, slot1;
+    uint32_t so[11];
+    int sides;
 };
 
-__device__ __forceinline__ ChainReg load_chain(const GenChain *chains, int idx)
+template <bool IN_LDS>
+__device__ __forceinline__ ChainReg load_chain(const GenChain *chains, const GenStart *starts, int idx)
 {
     const GLOBAL int *p = (const GLOBAL int *)gptr(chains) + 8 * idx;
     const GLOBAL int64_t *q = (const GLOBAL int64_t *)(p + 4);
@@ -36,6 +40,16 @@ __device__ __forceinline__ ChainReg load_chain(const GenChain *chains, int idx)
     c.tau0 = p[3];
     c.slot0 = q[0];
     c.slot1 = q[1];
+    if constexpr (IN_LDS) {
+        const GLOBAL uint32_t *r = (const GLOBAL uint32_t *)gptr(starts) + 12 * idx;
+#pragma unroll
+        for (int k = 0; k < 11; ++k) c.so[k] = r[k];
+        c.sides = (int)r[11];
+    } else {
+#pragma unroll
+        for (int k = 0; k < 11; ++k) c.so[k] = 0;
+        c.sides = 0;
+    }
     return c;
 }
 
@@ -43,9 +57,15 @@ __device__ __forceinline__ ChainReg load_chain(const GenChain *chains, int idx)
 // vector memory counter also counts the coefficient stores, so a wait for a
 // load left in flight across the tick loop would wait for the previous
 // tick's store in every tick.
+template <bool IN_LDS>
 __device__ __forceinline__ void settle(const ChainReg &c)
 {
     asm volatile("" ::"v"(c.type), "v"(c.param), "v"(c.len), "v"(c.tau0), "v"(c.slot0), "v"(c.slot1));
+    if constexpr (IN_LDS) {
+#pragma unroll
+        for (int k = 0; k < 11; ++k) asm volatile("" ::"v"(c.so[k]));
+        asm volatile("" ::"v"(c.sides));
+    }
 }
 
 // Ticks between refills of a thread's prefetched chain descriptor.
@@ -56,28 +76,11 @@ __device__ __forceinline__ int band_cell(int r, int c)
     return band_row(r) + (c - r) + 2;
 }
 
-// Rotation s of chain g, decoded into band pointers.
-//
-// In phase 1 both chain types are the up-left chase pattern L(ii)
-// [(ii,ii+3) onto (ii+1,ii+3)], R(ii-1) [(ii+1,ii-1) onto (ii+1,ii)],
-// ii = i0 - 3*(ss>>1), whose first rotation eliminates an entry of v (P1A) or
-// u (P1B) instead.  In phase 2 both are the down-right pattern R(ii+2)
-// [(ii,ii+3) into (ii,ii+2)], L(ii+3) [(ii+4,ii+2) into (ii+3,ii+2)],
-// ii = i0 + 3*(ss>>1), whose first rotation acts one column (P2A) or one row
-// (P2B) further on.  A left rotation on rows (i, i+1) rotates the band pairs
-// w_j in columns i-1+j, a right rotation on columns (j', j'+1) those in rows
-// j'-2+j (j = 0..4, the only pairs the schedule can make nonzero), plus the
-// matching u or v pair.
-//
-// Consecutive rotations of a chain share two window pairs: in phase 1 pairs
-// w_0, w_1 of one rotation are w_3, w_4 of the next, in phase 2 the reverse.
-// The window is kept in the order (w_3, w_4, w_2, w_0, w_1) in phase 1 and
-// (w_0, ..., w_4) in phase 2, so slots 0 and 1 are the pairs shared with the
-// previous rotation and slots 3 and 4 those shared with the next, and the
-// next rotation's slots 0, 1 hold (x_3, y_3), (x_4, y_4) of this one's, in
-// both phases and both directions.  The pair a rotation is generated from
-// is slot 1 in phase 1 and slot 0 in phase 2, except at a chain's first
-// rotation: the u or v pair in phase 1, slot 1 in phase 2.
+// Rotation s of chain g as band pointers (the offsets of rot_offsets):
+// the pair a rotation is generated from is slot 1 in phase 1 and slot 0 in
+// phase 2, except at a chain's first rotation: the u or v pair in phase 1,
+// slot 1 in phase 2.  The next rotation's slots 0, 1 hold (x_3, y_3),
+// (x_4, y_4) of this one's, in both phases and both directions.
 //
 // Rotations s and s + 2 of a chain have the same pattern three rows and
 // columns further on: every band pointer moves by kBandStep3 doubles, the u
@@ -93,33 +96,15 @@ template <typename BP>
 __device__ __forceinline__ RotAddr<BP> decode(BP S, const ChainReg &g, int s, int K, int UO, int VO,
                                               GLOBAL double *csL, GLOBAL double *csR)
 {
-    const bool ph1 = g.type <= CH_P1B;
-    const bool first = ph1 ? (g.type == CH_P1A) : (g.type == CH_P2A);
-    const int ss = s + (first ? 1 : 0);
-    const int odd = ss & 1;
-    const int i0 = ph1 ? (first ? g.param + 1 : g.param) : (first ? g.param - 3 : g.param - 1);
-    const int ii = ph1 ? i0 - 3 * (ss >> 1) : i0 + 3 * (ss >> 1);
-    const int side = ph1 ? odd : 1 - odd;
-    const int i = ph1 ? (odd ? ii - 1 : ii) : (odd ? ii + 3 : ii + 2);
+    const RotOff o = rot_offsets(g.type, g.param, s, UO, VO);
     RotAddr<BP> d;
-    d.vb = S + (side == 0 ? UO : VO) + i + 3;
-    // left: rows i, i+1 at columns i-1..i+3; right: rows i-2..i+2 at
-    // columns i, i+1 (adjacent doubles)
-    const int b2 = band_row(i), b3 = band_row(i + 1);
-    const int rb[5] = {band_row(i - 2) + 4, band_row(i - 1) + 3, b2 + 2, b3 + 1, band_row(i + 2)};
-    int wx[5], wy[5];
-#pragma unroll
-    for (int j = 0; j < 5; ++j) {
-        wx[j] = side == 0 ? b2 + j + 1 : rb[j];
-        wy[j] = side == 0 ? b3 + j : rb[j] + 1;
-    }
-    constexpr int ord1[5] = {3, 4, 2, 0, 1};
+    d.vb = S + o.vb;
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-        d.x[k] = S + (ph1 ? wx[ord1[k]] : wx[k]);
-        d.y[k] = S + (ph1 ? wy[ord1[k]] : wy[k]);
+        d.x[k] = S + o.x[k];
+        d.y[k] = S + o.y[k];
     }
-    d.cs = (side == 0 ? csL + 2 * g.slot0 : csR + 2 * g.slot1) + (int64_t)(s >> 1) * 2 * K;
+    d.cs = (o.side == 0 ? csL + 2 * g.slot0 : csR + 2 * g.slot1) + (int64_t)(s >> 1) * 2 * K;
     return d;
 }
 
@@ -213,34 +198,52 @@ __global__ __launch_bounds__(kGenThreads) void gen_kernel(HandleDev *const *hs, 
     // every kRefill ticks, or (when a chain ends before a refill) at the
     // switch, so the tick body itself never waits on vector memory.
     int ci = tid;
-    ChainReg g = {0, 0, 0, 0, 0, 0}, gn = {0, 0, 0, 0, 0, 0};
+    ChainReg g = {}, gn = {};
     bool next = false;
-    if (ci < nch) g = load_chain(h->chains, ci);
-    settle(g);
+    if (ci < nch) g = load_chain<IN_LDS>(h->chains, h->starts, ci);
+    settle<IN_LDS>(g);
     // part 2: skip the chains that finished before it (none is in flight at
     // the split)
     while (ci < nch && g.tau0 + g.len <= t_begin) {
         ci += nt;
         if (ci < nch) {
-            g = load_chain(h->chains, ci);
-            settle(g);
+            g = load_chain<IN_LDS>(h->chains, h->starts, ci);
+            settle<IN_LDS>(g);
         }
     }
     if (ci + nt < nch) {
-        gn = load_chain(h->chains, ci + nt);
+        gn = load_chain<IN_LDS>(h->chains, h->starts, ci + nt);
         next = true;
     }
-    settle(gn);
+    settle<IN_LDS>(gn);
 
     RotAddr<BP> ae, ao;
     bool m1 = false, fold = false;
     int db = 0, du = 0;
     int tend = -1;
     auto start = [&]() {
-        const RotAddr<BP> a0 = decode(SB, g, 0, K, UO, VO, csL, csR), a1 = decode(SB, g, 1, K, UO, VO, csL, csR);
-        const bool odd0 = g.tau0 & 1;
-        ae = odd0 ? a1 : a0;
-        ao = odd0 ? a0 : a1;
+        if constexpr (IN_LDS) {
+            // both address sets as the host decoded them, already in even-
+            // and odd-tick order
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                ae.x[k] = SB + (g.so[k] & 0xffffu);
+                ao.x[k] = SB + (g.so[k] >> 16);
+                ae.y[k] = SB + (g.so[5 + k] & 0xffffu);
+                ao.y[k] = SB + (g.so[5 + k] >> 16);
+            }
+            ae.vb = SB + (g.so[10] & 0xffffu);
+            ao.vb = SB + (g.so[10] >> 16);
+            GLOBAL double *cl = csL + 2 * g.slot0, *cr = csR + 2 * g.slot1;
+            ae.cs = (g.sides & 1) ? cr : cl;
+            ao.cs = (g.sides & 2) ? cr : cl;
+        } else {
+            const RotAddr<BP> a0 = decode(SB, g, 0, K, UO, VO, csL, csR),
+                              a1 = decode(SB, g, 1, K, UO, VO, csL, csR);
+            const bool odd0 = g.tau0 & 1;
+            ae = odd0 ? a1 : a0;
+            ao = odd0 ? a0 : a1;
+        }
         m1 = g.type <= CH_P1B;
         fold = g.type == CH_FOLD;
         db = m1 ? -kBandStep3 : kBandStep3;
@@ -356,8 +359,8 @@ __global__ __launch_bounds__(kGenThreads) void gen_kernel(HandleDev *const *hs, 
                     g = gn;
                     next = false;
                 } else if (ci < nch) {
-                    g = load_chain(h->chains, ci);
-                    settle(g);
+                    g = load_chain<IN_LDS>(h->chains, h->starts, ci);
+                    settle<IN_LDS>(g);
                 }
                 if (ci < nch) start();
             } else {
@@ -365,8 +368,8 @@ __global__ __launch_bounds__(kGenThreads) void gen_kernel(HandleDev *const *hs, 
             }
         }
         if (((t + 1) & (kRefill - 1)) == 0 && !next && ci + nt < nch) {
-            gn = load_chain(h->chains, ci + nt);
-            settle(gn);
+            gn = load_chain<IN_LDS>(h->chains, h->starts, ci + nt);
+            settle<IN_LDS>(gn);
             next = true;
         }
         __syncthreads();

@@ -185,6 +185,31 @@ std::unique_ptr<Plan> build_plan(int64_t m, int64_t n, int K0, int NW, int gen_t
             g.slot[r.side] = bd.off + (int64_t)(lam0 / 3 + tl + w * S) * K + w * K0 + pos;
         }
     }
+    // the first two rotations of each chain, decoded for the in-LDS
+    // generation kernel (in the order of its even- and odd-tick sets)
+    {
+        const int uo = (int)band_doubles(N), vo = uo + (N + 8);
+        if ((int64_t)vo + nn + 8 <= 65536) {
+            P->starts.resize(ch.size());
+            for (size_t c = 0; c < ch.size(); ++c) {
+                const GenChain &g = ch[c];
+                GenStart &st = P->starts[c];
+                for (uint32_t &o : st.off) o = 0;
+                st.sides = 0;
+                if (g.type == CH_FOLD) continue;
+                const int se = (g.tau0 & 1) ? 1 : 0;
+                for (int set = 0; set < 2; ++set) {
+                    const int s = set == 0 ? se : 1 - se;
+                    if (s >= g.len) continue;
+                    const RotOff o = rot_offsets(g.type, g.param, s, uo, vo);
+                    const int v[11] = {o.x[0], o.x[1], o.x[2], o.x[3], o.x[4], o.y[0], o.y[1], o.y[2], o.y[3], o.y[4],
+                                       o.vb};
+                    for (int k = 0; k < 11; ++k) st.off[k] |= (uint32_t)v[k] << (16 * set);
+                    st.sides |= o.side << set;
+                }
+            }
+        }
+    }
     // ---- segments of a pass ---------------------------------------------
     // Applier block b (phase-1 blocks, then phase-2 blocks) holds the chains
     // of in-phase index [bK, bK + K) of its phase on both sides; blocks

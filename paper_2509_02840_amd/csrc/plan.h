@@ -15,6 +15,8 @@ struct Plan {
     int K0 = 0, NW = 0, K = 0, S = 0;
     int L = 0;                      // generation threads
     std::vector<GenChain> chains;   // non-empty chains in schedule order (with the fold)
+    std::vector<GenStart> starts;   // their first two rotations decoded (empty when the band
+                                    // offsets exceed 16 bits, i.e. the band cannot be in LDS)
     int64_t ticks = 0;              // generation ticks
     int64_t split = 0;              // tick where phase 1 ends with nothing in flight (0: no split)
     int nseg = 0;                   // phase-2 segments (HandleDev::tcut, bcut)
@@ -28,6 +30,7 @@ struct Plan {
 
     // device copies (owned by the plan cache, freed at unload)
     GenChain *d_chains = nullptr;
+    GenStart *d_starts = nullptr;
     BlockDesc *d_blocks[2] = {nullptr, nullptr};
 };
 
