@@ -392,18 +392,19 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(K0 * R 
 // instructions with scalar operands.  A broadcast LDS read per rotation
 // would move 1 KB through the LDS data path for 16 bytes of data (the LDS
 // then bounds the kernel), and a row broadcast by DPP moves costs two more
-// vector instructions per rotation.  The memory wavefront still streams
-// each front's coefficients into an LDS ring a few fronts ahead, which
-// keeps them in the L2 cache for the compute wavefronts' scalar loads.
+// vector instructions per rotation.  The memory wavefront touches every
+// 128-byte line of a front's coefficients a few fronts ahead (one load per
+// line, its value unused), which brings them into the L2 cache for the
+// compute wavefronts' scalar loads; without it the scalar loads miss to
+// HBM and the applier runs at half the speed.
 template <int K0, int NW, int R>
 struct Staged {
     static constexpr int U = K0 + 3, WSZ = 3 * U, S = U, K = K0 * NW;
     static constexpr int RC = ring_cols(K0);
     static constexpr int RING = RC * 64 * R;                  // doubles per ring
-    static constexpr int COEF = (NW + 1) * RING;              // offset of the coefficient ring
-    static constexpr int LDS_DOUBLES = COEF + 3 * K * 2;      // 3 fronts of K pairs
+    static constexpr int LDS_DOUBLES = (NW + 1) * RING;       // rings 0 .. NW
     static constexpr int DL = U / 3;                          // memory prefetch depth, U % DL == 0
-    static constexpr int NCI = (K + 63) / 64;                 // coefficient loads per front
+    static constexpr int NPF = (2 * K + 15) / 16 + 1;         // 128-byte lines of a front's pairs, at most
     static_assert(U % 3 == 0 && U % DL == 0 && (3 * U) % RC == 0, "static ring slots");
 };
 
@@ -432,9 +433,13 @@ __device__ __forceinline__ void front_part(const double (&c)[K0], const double (
 // the middle of the previous front (once the first half of its rotations
 // has freed those registers), the second half at the start of the front
 // itself, so every scalar load has about half a front of work before its
-// value is needed, and the wait at the front's barrier (whose LDS writes
-// share the counter with scalar loads) finds the loads of the middle of
-// the front landed.
+// value is needed.  Scalar loads share their completion counter with LDS
+// accesses and complete out of order, so every wait for one is a wait for
+// all: the front's LDS accesses are all issued before the mid-front wait,
+// and the barrier that ends the front waits for nothing more (a
+// __syncthreads would also wait for the next front's first-half loads just
+// issued; they are waited for after the barrier, before the second half's
+// loads go out).
 template <int K0, int NW, int R, int MODE>
 __device__ __forceinline__ void sweep_compute_sc(const CONSTANT double *__restrict__ cs, const BlockDesc bd,
                                                  double *lds, int w, int lane)
@@ -479,6 +484,10 @@ __device__ __forceinline__ void sweep_compute_sc(const CONSTANT double *__restri
         for (int phi = 0; phi < U; ++phi) {
             const int F = F0 + phi;
             const int f = F - w * S;
+            // the first half's pairs (loaded during the previous front) have
+            // landed before the second half's loads are issued
+            asm volatile("" ::"s"(c[0]));
+            __builtin_amdgcn_sched_barrier(0);
             load(F, H, K0);
             __builtin_amdgcn_sched_barrier(0);
             if (phi == 0 && f == 0) {
@@ -506,12 +515,15 @@ __device__ __forceinline__ void sweep_compute_sc(const CONSTANT double *__restri
                     rout[(pmod(3 * (phi - K0 + 1) + k, RC) * R + r) * 64] = buf[r][pmod(3 * (phi - K0 + 1) + k, WSZ)];
             // wait here (not after the next loads) for this front's second
             // half: a wait for one scalar load waits for all in flight
+            // every LDS access of this front (the column reads and writes
+            // above) is complete after this wait
             asm volatile("" ::"s"(c[H]));
+            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
             __builtin_amdgcn_sched_barrier(0);
             load(F + 1, 0, H);
             __builtin_amdgcn_sched_barrier(0);
             front_part<K0, R, MODE, K, WSZ, H, K0>(c, sn, buf, phi);
-            __syncthreads();
+            asm volatile("s_barrier" ::: "memory");
 #pragma unroll
             for (int r = 0; r < R; ++r)
 #pragma unroll
@@ -526,7 +538,7 @@ __device__ __forceinline__ void sweep_memory(GLOBAL double *__restrict__ X, int 
                                              const CONSTANT double *cs, const BlockDesc bd, double *lds, int lane)
 {
     using T = Staged<K0, NW, R>;
-    constexpr int U = T::U, S = T::S, K = T::K, RC = T::RC, DL = T::DL, NCI = T::NCI;
+    constexpr int U = T::U, S = T::S, K = T::K, RC = T::RC, DL = T::DL, NPF = T::NPF;
     constexpr bool DESC = MODE < 2;
     constexpr int DIR = DESC ? -1 : 1;
     const int lmax = bd.lmax;
@@ -538,7 +550,6 @@ __device__ __forceinline__ void sweep_memory(GLOBAL double *__restrict__ X, int 
     const int col0 = base - 1;
     double *rw = lds + lane;                               // ring 0
     const double *rr = lds + NW * T::RING + lane;          // ring NW
-    double *coef = lds + T::COEF;  // pairs (c, s)
     const GLOBAL double *cg = (const GLOBAL double *)(uintptr_t)cs;
     auto colptr = [&](int lam) -> const GLOBAL double * {
         int c = col0 + DIR * lam;
@@ -547,10 +558,13 @@ __device__ __forceinline__ void sweep_memory(GLOBAL double *__restrict__ X, int 
     };
     // FIFO entry for front Fl (written to LDS during front Fl): the columns
     // 3 Fl + 7 .. 3 Fl + 9 that wavefront 0 reads at front Fl + 1 (for its
-    // front Fl + 2), and the coefficients of front Fl + 2 (the compute
-    // wavefronts read them during front Fl + 1).
+    // front Fl + 2), and one word of each 128-byte line of the coefficients
+    // of front Fl + 2 (lanes below NPF), loaded only to bring those lines
+    // into the L2 cache before the compute wavefronts' scalar loads.
     double colf[DL][3][R];
-    double cof[DL][NCI][2];
+    double pf[DL];
+#pragma unroll
+    for (int j = 0; j < DL; ++j) pf[j] = 0.0;
     auto load_entry = [&](int slot, int Fl) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
@@ -560,32 +574,18 @@ __device__ __forceinline__ void sweep_memory(GLOBAL double *__restrict__ X, int 
         }
         int Fc = Fl + 2 < nfront ? Fl + 2 : nfront - 1;
         const GLOBAL double *cp = cg + 2 * (int64_t)Fc * K;
-#pragma unroll
-        for (int i = 0; i < NCI; ++i) {
-            const int q = lane + 64 * i < K ? lane + 64 * i : K - 1;
-            cof[slot][i][0] = cp[2 * q];
-            cof[slot][i][1] = cp[2 * q + 1];
-        }
+        // words 0, 16, 32, ... and the last of the front's 2K: one in every
+        // 128-byte line the front's pairs touch
+        const int q = 16 * lane < 2 * K ? 16 * lane : 2 * K - 1;
+        if (lane < NPF) pf[slot] = cp[q];
     };
-    // prologue: columns 0..6 and the coefficients of fronts 0 and 1 (slots
-    // 0 and 1), then the FIFO
+    // prologue: columns 0..6, then the FIFO
     {
 #pragma unroll
         for (int k = 0; k <= 6; ++k) {
             const GLOBAL double *cp = colptr(k);
 #pragma unroll
             for (int r = 0; r < R; ++r) rw[(k * R + r) * 64] = cp[row0 + 64 * r];
-        }
-#pragma unroll
-        for (int f = 0; f < 2; ++f) {
-            const int Fc = f < nfront ? f : nfront - 1;
-#pragma unroll
-            for (int i = 0; i < NCI; ++i)
-                if (lane + 64 * i < K) {
-                    const int q = f * K + lane + 64 * i;
-                    coef[2 * q] = cg[2 * ((int64_t)Fc * K + lane + 64 * i)];
-                    coef[2 * q + 1] = cg[2 * ((int64_t)Fc * K + lane + 64 * i) + 1];
-                }
         }
     }
 #pragma unroll
@@ -596,18 +596,13 @@ __device__ __forceinline__ void sweep_memory(GLOBAL double *__restrict__ X, int 
         for (int phi = 0; phi < U; ++phi) {
             const int F = F0 + phi;
             const int slot = phi % DL;
-            // columns wavefront 0 reads at front F + 1, coefficients of front F + 2
+            // columns wavefront 0 reads at front F + 1; the prefetch word of
+            // this slot is consumed (waited for) before the slot is reused
 #pragma unroll
             for (int k = 0; k < 3; ++k)
 #pragma unroll
                 for (int r = 0; r < R; ++r) rw[(pmod(3 * phi + 7 + k, RC) * R + r) * 64] = colf[slot][k][r];
-#pragma unroll
-            for (int i = 0; i < NCI; ++i)
-                if (lane + 64 * i < K) {
-                    double *d = coef + 2 * (((phi + 2) % 3) * K + lane + 64 * i);
-                    d[0] = cof[slot][i][0];
-                    d[1] = cof[slot][i][1];
-                }
+            asm volatile("" ::"v"(pf[slot]));
             load_entry(slot, F + DL);
             // columns the last compute wavefront finished at front F - 1
 #pragma unroll
