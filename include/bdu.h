@@ -475,6 +475,16 @@ int64_t bdu_plan_rotations(int64_t m, int64_t n, int32_t *side, int64_t *idx,
  * rotations and the fold). */
 int bdu_plan_segments(int64_t m, int64_t n, int32_t *tcut, int32_t *bcut, int32_t *block, int64_t cap);
 
+/* The applier blocks of one side (0: Q, the left rotations; 1: P) for (m, n)
+ * under the current tiling, phase-1 blocks first: six values per block in
+ * out (at most cap blocks): base, lmax (-1: empty), nfront, phase, start
+ * and off as the kernels read them (the block's local column lam is matrix
+ * column base - 1 - lam in phase 1 and base - 1 + lam in phase 2; start is
+ * the staged applier's first chunk of k0 + 3 fronts of the block, off its
+ * first slot in the side's rotation stream).  Returns the number of blocks,
+ * or BDU_EINVAL. */
+int bdu_plan_blocks(int64_t m, int64_t n, int side, int64_t *out, int64_t cap);
+
 #ifdef __cplusplus
 }
 #endif

@@ -75,6 +75,7 @@ def lib():
         L.bdu_set_finite_check.argtypes = [i32]
         L.bdu_set_split_pass.argtypes = [i32]
         L.bdu_plan_segments.argtypes = [i64, i64, vp, vp, vp, i64]
+        L.bdu_plan_blocks.argtypes = [i64, i64, ctypes.c_int, vp, i64]
         L.bdu_update_householder.argtypes = [vp, vp, vp]
         L.bdu_orth_error.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.bdu_reorthogonalize.argtypes = [vp, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
@@ -121,7 +122,7 @@ def lib():
                   "bdu_get_tiling", "bdu_plan_stats", "bdu_givens_device", "bdu_timing_enable",
                   "bdu_timing_read", "bdu_batch_create", "bdu_batch_update", "bdu_batch_sync",
                   "bdu_batch_info", "bdu_batch_destroy", "bdu_autotune", "bdu_tune_save", "bdu_tune_load",
-                  "bdu_handle_tiling", "bdu_set_generation_in_lds", "bdu_set_finite_check", "bdu_set_split_pass", "bdu_plan_segments", "bdu_update_householder", "bdu_server_create", "bdu_server_open", "bdu_server_submit",
+                  "bdu_handle_tiling", "bdu_set_generation_in_lds", "bdu_set_finite_check", "bdu_set_split_pass", "bdu_plan_segments", "bdu_plan_blocks", "bdu_update_householder", "bdu_server_create", "bdu_server_open", "bdu_server_submit",
                   "bdu_server_wait", "bdu_server_poll", "bdu_server_drain", "bdu_server_pause",
                   "bdu_server_read", "bdu_server_close", "bdu_server_stats", "bdu_server_destroy"):
             getattr(L, f).restype = i32
@@ -233,6 +234,16 @@ def plan_segments(m: int, n: int):
     blk = np.empty(cnt, np.int32)
     ns = _check(L.bdu_plan_segments(m, n, tc.ctypes.data, bc.ctypes.data, blk.ctypes.data, cnt), "bdu_plan_segments")
     return tc[:ns], bc[:ns], blk
+
+
+def plan_blocks(m: int, n: int, side: int) -> np.ndarray:
+    """Applier blocks of one side (0: Q, 1: P) under the current tiling: rows
+    (base, lmax, nfront, phase, start, off)."""
+    L = lib()
+    nb = _check(L.bdu_plan_blocks(m, n, side, None, 0), "bdu_plan_blocks")
+    out = np.zeros((max(nb, 1), 6), np.int64)
+    _check(L.bdu_plan_blocks(m, n, side, out.ctypes.data, nb), "bdu_plan_blocks")
+    return out[:nb]
 
 
 def set_tiling_auto() -> None:

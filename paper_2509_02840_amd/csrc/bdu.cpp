@@ -1441,6 +1441,26 @@ int bdu_plan_segments(int64_t m, int64_t n, int32_t *tcut, int32_t *bcut, int32_
     return p->nseg;
 }
 
+int bdu_plan_blocks(int64_t m, int64_t n, int side, int64_t *out, int64_t cap)
+{
+    if (m < n || n < 2 || (side != 0 && side != 1) || cap < 0 || (cap > 0 && !out)) return BDU_EINVAL;
+    int k0, nw, rpl;
+    tiling_for(m, n, &k0, &nw, &rpl);
+    hipError_t e;
+    Plan *p = get_plan(m, n, k0, nw, false, &e);
+    const std::vector<BlockDesc> &bl = p->blocks[side];
+    for (size_t b = 0; b < bl.size() && (int64_t)b < cap; ++b) {
+        int64_t *o = out + 6 * b;
+        o[0] = bl[b].base;
+        o[1] = bl[b].lmax;
+        o[2] = bl[b].nfront;
+        o[3] = bl[b].phase;
+        o[4] = bl[b].start;
+        o[5] = bl[b].off;
+    }
+    return (int)bl.size();
+}
+
 int64_t bdu_plan_rotations(int64_t m, int64_t n, int32_t *side, int64_t *idx, int32_t *phase, int64_t *tick,
                            int64_t cap)
 {

@@ -33,6 +33,8 @@ __device__ __forceinline__ BlockDesc load_block(const BlockDesc *p, int b)
     d.nfront = q->nfront;
     d.phase = q->phase;
     d.off = q->off;
+    d.start = q->start;
+    d.pad = 0;
     return d;
 }
 
@@ -440,17 +442,16 @@ __device__ __forceinline__ void front_part(const double (&c)[K0], const double (
 // __syncthreads would also wait for the next front's first-half loads just
 // issued; they are waited for after the barrier, before the second half's
 // loads go out).
+//
+// One block's live chunks for compute wavefront w: nlive chunks of U fronts
+// from the block's front w S (the caller has run the barriers before it).
 template <int K0, int NW, int R, int MODE>
-__device__ __forceinline__ void sweep_compute_sc(const CONSTANT double *__restrict__ cs, const BlockDesc bd,
-                                                 double *lds, int w, int lane)
+__device__ __forceinline__ void sweep_compute_sc(const CONSTANT double *__restrict__ cs, double *lds, int w, int lane,
+                                                 int nlive)
 {
     using T = Staged<K0, NW, R>;
     constexpr int U = T::U, WSZ = T::WSZ, S = T::S, K = T::K, RC = T::RC;
     constexpr int H = K0 / 2;
-    const int lmax = bd.lmax;
-    if (lmax < 0) return;
-    const int nfront = bd.nfront;
-    const int lam_hi = lmax + 1;
     double buf[R][WSZ];
 #pragma unroll
     for (int r = 0; r < R; ++r)
@@ -458,13 +459,7 @@ __device__ __forceinline__ void sweep_compute_sc(const CONSTANT double *__restri
         for (int i = 0; i < WSZ; ++i) buf[r][i] = 0.0;
     const double *rin = lds + w * T::RING + lane;
     double *rout = lds + (w + 1) * T::RING + lane;
-    const int flush_end = lam_hi / 3 + K0 - 1;
-    const int nchunk = nfront / U;
-    int live_end = w + (flush_end + U) / U;
-    live_end = live_end < nchunk ? live_end : nchunk;
-    auto idle = [&](int chunks) {
-        for (int c = 0; c < chunks * U; ++c) __syncthreads();
-    };
+    const int live_end = w + nlive;
     double c[K0], sn[K0];
     // pairs [p0, p1) of front F
     auto load = [&](int F, int p0, int p1) {
@@ -476,8 +471,6 @@ __device__ __forceinline__ void sweep_compute_sc(const CONSTANT double *__restri
                 sn[p] = q[2 * p + 1];
             }
     };
-    __syncthreads();  // the memory wavefront's prologue is in LDS
-    idle(w);
     load(w * S, 0, H);
     for (int F0 = w * S; F0 < live_end * U; F0 += U) {
 #pragma unroll
@@ -530,89 +523,176 @@ __device__ __forceinline__ void sweep_compute_sc(const CONSTANT double *__restri
                 for (int j = -3 * (K0 - 1); j <= 3; ++j) asm volatile("" : "+v"(buf[r][pmod(3 * phi + j, WSZ)]));
         }
     }
-    idle(nchunk - (live_end > w ? live_end : w));
 }
 
-template <int K0, int NW, int R, int MODE>
-__device__ __forceinline__ void sweep_memory(GLOBAL double *__restrict__ X, int ld, int ncols, int row0,
-                                             const CONSTANT double *cs, const BlockDesc bd, double *lds, int lane)
+// A block as the memory wavefront sees it.
+struct MemBlock {
+    int rel;           // first chunk, relative to the launch's first block
+    int nfront, C;     // fronts of the block; live chunks of each compute wavefront
+    int dir, col0;     // matrix column of local column lam: col0 + dir lam
+    int lam_lo, lam_hi;
+    int64_t off;       // first slot of the block's pairs
+};
+
+__device__ __forceinline__ MemBlock mem_block(const BlockDesc &bd, int start0, int ncols, int K0, int U)
 {
-    using T = Staged<K0, NW, R>;
-    constexpr int U = T::U, S = T::S, K = T::K, RC = T::RC, DL = T::DL, NPF = T::NPF;
-    constexpr bool DESC = MODE < 2;
-    constexpr int DIR = DESC ? -1 : 1;
-    const int lmax = bd.lmax;
-    if (lmax < 0) return;
-    const int nfront = bd.nfront;
-    const int base = bd.base;
-    const int lam_hi = lmax + 1;
-    const int lam_lo = DESC ? (base - ncols > 0 ? base - ncols : 0) : 0;
-    const int col0 = base - 1;
-    double *rw = lds + lane;                               // ring 0
-    const double *rr = lds + NW * T::RING + lane;          // ring NW
+    MemBlock v;
+    const bool desc = bd.phase == 1;
+    v.rel = bd.start - start0;
+    v.nfront = bd.nfront;
+    v.lam_hi = bd.lmax + 1;
+    v.C = (v.lam_hi / 3 + K0 - 1 + U) / U;
+    v.dir = desc ? -1 : 1;
+    v.col0 = bd.base - 1;
+    v.lam_lo = desc ? (bd.base - ncols > 0 ? bd.base - ncols : 0) : 0;
+    v.off = bd.off;
+    return v;
+}
+
+// First block at or after b with work (lmax >= 0), or bend.
+__device__ __forceinline__ int next_block(const BlockDesc *blk, int b, int bend)
+{
+    while (b < bend && load_block(blk, b).lmax < 0) ++b;
+    return b;
+}
+
+// The memory wavefront over all blocks [bbeg, bend) of a launch, which run
+// back to back (start chunks from the plan): T chunks of U fronts, one
+// barrier per front.  Its load side follows the block of its latest
+// prologue (the block compute wavefront 0 is in or waits for): at front F
+// of that block it writes to ring 0 the columns wavefront 0 reads at front
+// F + 1 (3F + 7 .. 3F + 9, loaded DL fronts earlier into a register FIFO);
+// a block's columns 0..6 and first DL FIFO entries are loaded in its
+// prologue, the front before it starts, which also overwrites whatever the
+// load side wrote for the previous block past its end.  Its store side
+// follows the oldest block not yet written back: at front F it stores the
+// columns the last compute wavefront finished at front F - 1.  Every front
+// it also touches every 128-byte line of the pairs the compute wavefronts
+// of the load block, of the block before it and of the store block read
+// DL + 2 fronts later (one word per line, its value unused), which brings
+// them into the L2 cache for their scalar loads.  All its loads are issued
+// at every front, whether or not their data is needed, so that the
+// compiler can count them and wait only for the FIFO entry in use.  A
+// column is loaded for one block only after an earlier block's store of it
+// has completed; the plan's start chunks guarantee that (stage_starts in
+// plan.cpp).
+template <int K0, int NW, int R>
+__device__ __forceinline__ void memory_wavefront(GLOBAL double *__restrict__ X, int ld, int ncols, int row0,
+                                                 const CONSTANT double *cs, const BlockDesc *blk, int bbeg,
+                                                 int bend, int start0, int T, double *lds, int lane)
+{
+    using TS = Staged<K0, NW, R>;
+    constexpr int U = TS::U, S = TS::S, K = TS::K, RC = TS::RC, DL = TS::DL, NPF = TS::NPF;
+    double *rw = lds + lane;                          // ring 0
+    const double *rr = lds + NW * TS::RING + lane;    // ring NW
     const GLOBAL double *cg = (const GLOBAL double *)(uintptr_t)cs;
-    auto colptr = [&](int lam) -> const GLOBAL double * {
-        int c = col0 + DIR * lam;
+    auto colptr = [&](const MemBlock &v, int lam) -> const GLOBAL double * {
+        int c = v.col0 + v.dir * lam;
         c = c < 0 ? 0 : (c >= ncols ? ncols - 1 : c);
         return X + (int64_t)c * ld;
     };
-    // FIFO entry for front Fl (written to LDS during front Fl): the columns
-    // 3 Fl + 7 .. 3 Fl + 9 that wavefront 0 reads at front Fl + 1 (for its
-    // front Fl + 2), and one word of each 128-byte line of the coefficients
-    // of front Fl + 2 (lanes below NPF), loaded only to bring those lines
-    // into the L2 cache before the compute wavefronts' scalar loads.
+    // one word of every 128-byte line of front Fc's pairs (lanes below NPF;
+    // the others load the last word again, so that the load is not under a
+    // branch and the compiler can count it)
+    const int q_touch = 16 * lane < 2 * K && lane < NPF ? 16 * lane : 2 * K - 1;
+    auto touch = [&](const MemBlock &v, int Fc) -> double {
+        Fc = Fc < 0 ? 0 : (Fc < v.nfront ? Fc : v.nfront - 1);
+        return cg[2 * (v.off + (int64_t)Fc * K) + q_touch];
+    };
+    const int bfirst = next_block(blk, bbeg, bend);
+    if (bfirst >= bend) {
+        __syncthreads();
+        return;  // no work: T is 0
+    }
+    // FIFO entry for front Fl of the load block (written to LDS at front
+    // Fl): the columns 3 Fl + 7 .. 3 Fl + 9 wavefront 0 reads at front
+    // Fl + 1, and the touch of its front Fl + 2
     double colf[DL][3][R];
-    double pf[DL];
+    double pfl[DL], pfp[DL], pfs[DL];
 #pragma unroll
-    for (int j = 0; j < DL; ++j) pf[j] = 0.0;
+    for (int j = 0; j < DL; ++j) pfl[j] = pfp[j] = pfs[j] = 0.0;
+    MemBlock L = mem_block(load_block(blk, bfirst), start0, ncols, K0, U);
+    MemBlock Pv = L, St = L;  // the block before the load block; the store block
     auto load_entry = [&](int slot, int Fl) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const GLOBAL double *cp = colptr(3 * Fl + 7 + k);
+            const GLOBAL double *cp = colptr(L, 3 * Fl + 7 + k);
 #pragma unroll
             for (int r = 0; r < R; ++r) colf[slot][k][r] = cp[row0 + 64 * r];
         }
-        int Fc = Fl + 2 < nfront ? Fl + 2 : nfront - 1;
-        const GLOBAL double *cp = cg + 2 * (int64_t)Fc * K;
-        // words 0, 16, 32, ... and the last of the front's 2K: one in every
-        // 128-byte line the front's pairs touch
-        const int q = 16 * lane < 2 * K ? 16 * lane : 2 * K - 1;
-        if (lane < NPF) pf[slot] = cp[q];
+        pfl[slot] = touch(L, Fl + 2);
     };
-    // prologue: columns 0..6, then the FIFO
-    {
+    auto prologue = [&]() {
 #pragma unroll
         for (int k = 0; k <= 6; ++k) {
-            const GLOBAL double *cp = colptr(k);
+            const GLOBAL double *cp = colptr(L, k);
 #pragma unroll
             for (int r = 0; r < R; ++r) rw[(k * R + r) * 64] = cp[row0 + 64 * r];
         }
-    }
 #pragma unroll
-    for (int j = 0; j < DL; ++j) load_entry(j, j);
+        for (int j = 0; j < DL; ++j) {
+            asm volatile("" ::"v"(pfl[j]));
+            load_entry(j, j);
+        }
+    };
+    prologue();
+    int bs = bfirst;                               // store block
+    int bn = next_block(blk, bfirst + 1, bend);    // next block to load
+    int next_pro = bn < bend ? mem_block(load_block(blk, bn), start0, ncols, K0, U).rel * U - 1 : -2;
     __syncthreads();
-    for (int F0 = 0; F0 < nfront; F0 += U) {
+    for (int G0 = 0; G0 < T * U; G0 += U) {
 #pragma unroll
         for (int phi = 0; phi < U; ++phi) {
-            const int F = F0 + phi;
+            const int G = G0 + phi;
             const int slot = phi % DL;
-            // columns wavefront 0 reads at front F + 1; the prefetch word of
-            // this slot is consumed (waited for) before the slot is reused
+            // load side (past the block's end it feeds nobody; the next
+            // prologue overwrites those slots)
+            {
+                const int Fl = G - L.rel * U;
 #pragma unroll
-            for (int k = 0; k < 3; ++k)
+                for (int k = 0; k < 3; ++k)
 #pragma unroll
-                for (int r = 0; r < R; ++r) rw[(pmod(3 * phi + 7 + k, RC) * R + r) * 64] = colf[slot][k][r];
-            asm volatile("" ::"v"(pf[slot]));
-            load_entry(slot, F + DL);
-            // columns the last compute wavefront finished at front F - 1
+                    for (int r = 0; r < R; ++r) rw[(pmod(3 * phi + 7 + k, RC) * R + r) * 64] = colf[slot][k][r];
+                asm volatile("" ::"v"(pfl[slot]));
+                load_entry(slot, Fl + DL);
+                asm volatile("" ::"v"(pfp[slot]));
+                pfp[slot] = touch(Pv, G - Pv.rel * U + DL + 2);
+            }
+            // store side
+            {
+                const int Fs = G - St.rel * U;
+                asm volatile("" ::"v"(pfs[slot]));
+                pfs[slot] = touch(St, Fs + DL + 2);
+                double outv[3][R];
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const int lam = 3 * (F - 1 - (NW - 1) * S - K0 + 1) + k;
-                if (lam >= lam_lo && lam <= lam_hi) {
-                    GLOBAL double *cp = X + (int64_t)(col0 + DIR * lam) * ld;
+                for (int k = 0; k < 3; ++k)
 #pragma unroll
-                    for (int r = 0; r < R; ++r) cp[row0 + 64 * r] = rr[(pmod(3 * phi - 3 * K0 + k, RC) * R + r) * 64];
+                    for (int r = 0; r < R; ++r) outv[k][r] = rr[(pmod(3 * phi - 3 * K0 + k, RC) * R + r) * 64];
+                if (bs < bend) {
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        const int lam = 3 * (Fs - 1 - (NW - 1) * S - K0 + 1) + k;
+                        if (lam >= St.lam_lo && lam <= St.lam_hi) {
+                            GLOBAL double *cp = X + (int64_t)(St.col0 + St.dir * lam) * ld;
+#pragma unroll
+                            for (int r = 0; r < R; ++r) cp[row0 + 64 * r] = outv[k][r];
+                        }
+                    }
+                    // the block's last column is stored at this front
+                    if (Fs >= St.lam_hi / 3 + (NW - 1) * S + K0) {
+                        bs = next_block(blk, bs + 1, bend);
+                        if (bs < bend) St = mem_block(load_block(blk, bs), start0, ncols, K0, U);
+                    }
                 }
+            }
+            // the next block's prologue, the front before it starts (always
+            // the last front of a chunk: blocks start on chunk boundaries)
+            if (phi == U - 1 && G == next_pro) {
+                Pv = L;
+                L = mem_block(load_block(blk, bn), start0, ncols, K0, U);
+                prologue();
+                bn = next_block(blk, bn + 1, bend);
+                next_pro = bn < bend ? mem_block(load_block(blk, bn), start0, ncols, K0, U).rel * U - 1 : -2;
             }
             __syncthreads();
         }
@@ -654,28 +734,45 @@ void apply_staged_kernel(HandleDev *const *hs, Gate gate)
         for (int r = 0; r < R; ++r) spike_apply(X, ld, m, n, row0 + 64 * r, kptr((const double *)h->csSp));
     }
     __syncthreads();
+    // The launch's blocks run back to back from their planned start chunks
+    // (chunks of U fronts, relative to the first block): T chunks in all,
+    // the last ending when the latest block's last column is stored.  Every
+    // wavefront runs one barrier after the memory wavefront's first
+    // prologue and one per front of the T chunks.
+    constexpr int U = T::U;
+    const int start0 = bbeg < bend ? load_block(blk, bbeg).start : 0;
+    int Tch = 0;
     for (int b = bbeg; b < bend; ++b) {
         const BlockDesc bd = load_block(blk, b);
-        const CONSTANT double *cb = cs + 2 * bd.off;
-        if (w == NW) {
-            if (b < nb1) {
-                if (onQ) sweep_memory<K0, NW, R, 0>(X, ld, ncols, row0, cb, bd, lds, lane);
-                else sweep_memory<K0, NW, R, 1>(X, ld, ncols, row0, cb, bd, lds, lane);
-            } else {
-                if (onQ) sweep_memory<K0, NW, R, 2>(X, ld, ncols, row0, cb, bd, lds, lane);
-                else sweep_memory<K0, NW, R, 3>(X, ld, ncols, row0, cb, bd, lds, lane);
-            }
-        } else {
-            if (b < nb1) {
-                if (onQ) sweep_compute_sc<K0, NW, R, 0>(cb, bd, lds, w, lane);
-                else sweep_compute_sc<K0, NW, R, 1>(cb, bd, lds, w, lane);
-            } else {
-                if (onQ) sweep_compute_sc<K0, NW, R, 2>(cb, bd, lds, w, lane);
-                else sweep_compute_sc<K0, NW, R, 3>(cb, bd, lds, w, lane);
-            }
-        }
-        __syncthreads();
+        if (bd.lmax < 0) continue;
+        const int e = bd.start - start0 + bd.nfront / U;
+        Tch = Tch > e ? Tch : e;
     }
+    if (w == NW) {
+        memory_wavefront<K0, NW, R>(X, ld, ncols, row0, cs, blk, bbeg, bend, start0, Tch, lds, lane);
+        return;
+    }
+    __syncthreads();  // the memory wavefront's first prologue is in LDS
+    int cur = 0;      // chunks of barriers run so far
+    for (int b = bbeg; b < bend; ++b) {
+        const BlockDesc bd = load_block(blk, b);
+        if (bd.lmax < 0) continue;
+        const int rel = bd.start - start0;
+        const int C = ((bd.lmax + 1) / 3 + K0 - 1 + U) / U;
+        const int nc = bd.nfront / U - w;
+        const int nlive = C < nc ? C : nc;
+        for (int i = (rel + w - cur) * U; i > 0; --i) __syncthreads();
+        cur = rel + w + nlive;
+        const CONSTANT double *cb = cs + 2 * bd.off;
+        if (b < nb1) {
+            if (onQ) sweep_compute_sc<K0, NW, R, 0>(cb, lds, w, lane, nlive);
+            else sweep_compute_sc<K0, NW, R, 1>(cb, lds, w, lane, nlive);
+        } else {
+            if (onQ) sweep_compute_sc<K0, NW, R, 2>(cb, lds, w, lane, nlive);
+            else sweep_compute_sc<K0, NW, R, 3>(cb, lds, w, lane, nlive);
+        }
+    }
+    for (int i = (Tch - cur) * U; i > 0; --i) __syncthreads();
 }
 
 // The rotation primitive on arrays (checks the device arithmetic against the

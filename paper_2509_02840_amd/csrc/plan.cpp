@@ -12,6 +12,7 @@
 #include "plan.h"
 
 #include <algorithm>
+#include <climits>
 
 namespace bdu {
 
@@ -24,6 +25,57 @@ static void add_chain(std::vector<GenChain> &v, int type, int param, int len)
     c.len = len;
     c.tau0 = 0;
     v.push_back(c);
+}
+
+// Start chunks of the staged applier's blocks on one side (ncols columns of
+// Q or P).  The applier runs a launch's blocks back to back: compute
+// wavefront w is live in block b during chunks [start_b + w, start_b + w +
+// C_b) (chunks of U = K0 + 3 fronts, C_b = (lam_hi / 3 + K0 - 1 + U) / U,
+// lam_hi = lmax + 1), so block b + 1 may start once every wavefront has
+// finished block b (start_{b+1} >= start_b + C_b) -- and once the memory
+// wavefront, which moves every column between device memory and the
+// pipeline, keeps each column's order across blocks: it loads local column
+// lam of block b at front start_b U + max(-1, (lam - 7) / 3 - DL) (-1: the
+// block's prologue, the front before it starts; columns 0..6 too) and stores it at
+// front start_b U + lam / 3 + (NW - 1) U + K0.  A load of a column comes at
+// least DL + 3 fronts after every earlier block's store of it (by then the
+// store has completed: vector memory operations complete in issue order and
+// the memory wavefront has waited for a load issued after it), and a store
+// after every earlier load and store of it.  Each block takes the earliest
+// start that satisfies these against all earlier blocks of the side.
+static void stage_starts(std::vector<BlockDesc> &blk, int64_t ncols, int K0, int NW)
+{
+    const int U = K0 + 3, DL = U / 3, margin = DL + 3;
+    const int64_t none = INT64_MIN / 4;
+    std::vector<int64_t> st((size_t)ncols, none), ldf((size_t)ncols, none);
+    int64_t s = 0;  // earliest start of the next block (chunks)
+    for (BlockDesc &d : blk) {
+        d.pad = 0;
+        if (d.lmax < 0) {
+            d.start = (int32_t)s;
+            continue;
+        }
+        const int dir = d.phase == 1 ? -1 : 1, col0 = d.base - 1, lam_hi = d.lmax + 1;
+        const int C = (lam_hi / 3 + K0 - 1 + U) / U;
+        auto load_off = [&](int lam) { return lam < 7 ? -1 : std::max(-1, (lam - 7) / 3 - DL); };
+        auto store_off = [&](int lam) { return lam / 3 + (NW - 1) * U + K0; };
+        int64_t need = s * U;  // earliest first front
+        for (int lam = 0; lam <= lam_hi; ++lam) {
+            const int64_t c = col0 + (int64_t)dir * lam;
+            if (c < 0 || c >= ncols) continue;
+            if (st[c] != none) need = std::max<int64_t>(need, st[c] + margin - load_off(lam));
+            need = std::max<int64_t>(need, std::max(ldf[c], st[c]) + 1 - store_off(lam));
+        }
+        const int64_t start = (need + U - 1) / U;
+        d.start = (int32_t)start;
+        for (int lam = 0; lam <= lam_hi; ++lam) {
+            const int64_t c = col0 + (int64_t)dir * lam;
+            if (c < 0 || c >= ncols) continue;
+            ldf[c] = std::max<int64_t>(ldf[c], start * U + load_off(lam));
+            st[c] = start * U + store_off(lam);
+        }
+        s = start + C;
+    }
 }
 
 // Segments of a single-handle pass (more segments hide more of the
@@ -170,6 +222,7 @@ std::unique_ptr<Plan> build_plan(int64_t m, int64_t n, int K0, int NW, int gen_t
             }
         }
         P->slots[side] = pos;
+        stage_starts(P->blocks[side], side == 0 ? m : n, K0, NW);
     }
     // first slot of each chain on each side (same formula the applier reads)
     for (GenChain &g : ch) {

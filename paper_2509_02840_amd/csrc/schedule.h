@@ -223,6 +223,9 @@ struct BlockDesc {
     int32_t nfront;  // fronts swept (a multiple of K0 + 3), each with K slots
     int32_t phase;
     int64_t off;     // first slot of the block in the side's stream
+    int32_t start;   // staged applier: the block's first chunk of K0 + 3 fronts
+                     // (blocks run back to back; see stage_starts in plan.cpp)
+    int32_t pad;
 };
 
 }  // namespace bdu

@@ -8,6 +8,7 @@
   independently of the library's conservative row intervals.
 - The library exports every function its header declares.
 """
+import bisect
 import os
 import re
 
@@ -225,6 +226,193 @@ def _staged_protocol_violations(K0, NW, lmax, RC=15):
 @pytest.mark.parametrize("lmax", [0, 1, 2, 5, 17, 40, 100, 257])
 def test_staged_lds_protocol_is_race_free(K0, NW, RC, lmax):
     assert _staged_protocol_violations(K0, NW, lmax, RC=RC) == []
+
+
+def _pipelined_launch_violations(K0, NW, blocks, ncols, RC=15, margin=None):
+    """Replay one launch of the staged applier over plan blocks (rows base,
+    lmax, nfront, phase, start, off) the way the kernel runs them back to
+    back: every wavefront runs one barrier per front of T chunks of U fronts;
+    compute wavefront w is live in block b from chunk rel_b + w for C_b
+    chunks; the memory wavefront's load side follows the block of its last
+    prologue, its store side the oldest block not yet written back.  Returns
+    the violations of: (1) LDS: every read of a column a block needs sees
+    the write of that column across a barrier, with no other write to the
+    slot from that write's front to the read's; (2) device memory: every
+    load of a column comes at least `margin` fronts after every earlier
+    block's store of it, and every store after every earlier block's load
+    and store of it; (3) barriers: no wavefront would need to go back in
+    time (its idle count would be negative)."""
+    U = S = K0 + 3
+    DL = U // 3
+    margin = DL + 3 if margin is None else margin
+    bl = [tuple(int(x) for x in r) for r in blocks if r[1] >= 0]
+    if not bl:
+        return []
+    start0 = bl[0][4]
+    views = []
+    for base, lmax, nfront, phase, start, off in bl:
+        desc = phase == 1
+        lam_hi = lmax + 1
+        views.append(dict(rel=start - start0, nfront=nfront, lam_hi=lam_hi, C=(lam_hi // 3 + K0 - 1 + U) // U,
+                          dir=-1 if desc else 1, col0=base - 1,
+                          lam_lo=max(base - ncols, 0) if desc else 0))
+    T = max(v["rel"] + v["nfront"] // U for v in views)
+    bad = []
+    ev = {}    # (ring, slot) -> [(G, wave, order, kind, value)]
+    mem = {}   # matrix column -> [(G, order, kind, block)]
+
+    def lds(ring, lam, G, wave, order, kind, value):
+        ev.setdefault((ring, lam % RC), []).append((G, wave, order, kind, value))
+
+    def col(v, lam):
+        return v["col0"] + v["dir"] * lam
+
+    def valid(v, lam):
+        c = col(v, lam)
+        return 0 <= lam <= v["lam_hi"] and 0 <= c < ncols
+
+    def mload(b, lam, G, order):
+        v = views[b]
+        if valid(v, lam):
+            mem.setdefault(col(v, lam), []).append((G, order, "load", b))
+
+    # memory wavefront (wave NW)
+    def prologue(b, G):
+        for lam in range(7):
+            lds(0, lam, G, NW, 5, "w", (b, lam))
+            mload(b, lam, G, 5)
+        for j in range(DL):
+            for k in range(3):
+                mload(b, 3 * j + 7 + k, G, 6)
+    L = St = 0
+    prologue(0, -1)
+    nxt = 1
+    next_pro = views[1]["rel"] * U - 1 if len(views) > 1 else -2
+    for G in range(T * U):
+        v = views[L]
+        Fl = G - v["rel"] * U
+        if Fl < v["C"] * U - 1:
+            for k in range(3):
+                lds(0, 3 * Fl + 7 + k, G, NW, 0, "w", (L, 3 * Fl + 7 + k))
+                mload(L, 3 * (Fl + DL) + 7 + k, G, 1)
+        if St < len(views):
+            vs = views[St]
+            Fs = G - vs["rel"] * U
+            for k in range(3):
+                lam = 3 * (Fs - 1 - (NW - 1) * S - K0 + 1) + k
+                if vs["lam_lo"] <= lam <= vs["lam_hi"]:
+                    lds(NW, lam, G, NW, 2, "r", (St, lam))
+                    if valid(vs, lam):
+                        mem.setdefault(col(vs, lam), []).append((G, 3, "store", St))
+            if Fs >= vs["lam_hi"] // 3 + (NW - 1) * S + K0:
+                St += 1
+        if G == next_pro:
+            L = nxt
+            prologue(L, G)
+            nxt += 1
+            next_pro = views[nxt]["rel"] * U - 1 if nxt < len(views) else -2
+    if nxt < len(views):
+        bad.append(("prologue never reached", nxt))
+    if St < len(views):
+        bad.append(("blocks not written back", St))
+    # compute wavefronts
+    for w in range(NW):
+        cur = 0
+        for b, v in enumerate(views):
+            nlive = min(v["C"], v["nfront"] // U - w)
+            if v["rel"] + w < cur:
+                bad.append(("barrier count", w, b))
+            cur = v["rel"] + w + nlive
+            for f in range(nlive * U):
+                G = (v["rel"] + w) * U + f
+                lams = ([0, 1, 2, 3] if f == 0 else []) + [3 * f + 4, 3 * f + 5, 3 * f + 6]
+                for lam in lams:
+                    if lam <= v["lam_hi"]:
+                        lds(w, lam, G, w, 1, "r", (b, lam))
+                for k in range(3):
+                    lam = 3 * (f - K0 + 1) + k
+                    if lam >= 0:
+                        lds(w + 1, lam, G, w, 3, "w", (b, lam))
+        if cur > T:
+            bad.append(("barrier count at the end", w))
+    # (1) LDS hand-overs: the slot's last write before the read's front is
+    # the value's, every write at that front comes from one wavefront (in
+    # its program order), and nothing writes the slot at the read's front
+    for key, es in ev.items():
+        writes = sorted(e for e in es if e[3] == "w")
+        fronts = [wr[0] for wr in writes]
+        for G, wave, order, kind, value in es:
+            if kind != "r":
+                continue
+            j = bisect.bisect_left(fronts, G) - 1
+            if j < 0 or writes[j][4] != value:
+                bad.append(("not the slot's last write", key, G, value, writes[j][4] if j >= 0 else None))
+                continue
+            Gw = fronts[j]
+            same = writes[bisect.bisect_left(fronts, Gw):j + 1]
+            if any(wr[1] != writes[j][1] for wr in same):
+                bad.append(("two wavefronts write the slot in one front", key, Gw, value))
+            if bisect.bisect_right(fronts, G) != bisect.bisect_left(fronts, G):
+                bad.append(("slot written in the read's front", key, G, value))
+    # (2) device memory: each access of a block against every access of an
+    # earlier block to the same column, whatever their order in time
+    for c, es in mem.items():
+        for G, o, kind, b in es:
+            for G2, o2, kind2, b2 in es:
+                if b2 >= b:
+                    continue
+                if kind == "load" and kind2 == "store" and G < G2 + margin:
+                    bad.append(("load too soon after an earlier block's store", c, b, G, b2, G2))
+                if kind == "store" and (G, o) <= (G2, o2):
+                    bad.append(("store before an earlier block's access", c, b, G, b2, G2))
+    return bad
+
+
+_PIPE_TILINGS = [(12, 3, 1, 15), (12, 7, 1, 15), (12, 15, 1, 15), (18, 3, 1, 21), (18, 5, 1, 21), (18, 7, 1, 21)]
+
+
+@pytest.mark.parametrize("k0,nw,rpl,RC", _PIPE_TILINGS)
+@pytest.mark.parametrize("m,n", [(40, 40), (130, 97), (257, 191), (420, 150), (900, 900)])
+def test_pipelined_staged_launches_are_race_free(k0, nw, rpl, RC, m, n):
+    """Every launch the plan makes (the whole pass, each phase, each
+    segment) on both sides replays without an LDS race, a device-memory
+    reordering or a barrier mismatch."""
+    saved = bdu.get_tiling()
+    try:
+        bdu.set_tiling(k0, nw, rpl)
+        tcut, bcut, _ = bdu.plan_segments(m, n)
+        for side, ncols in ((0, m), (1, n)):
+            blocks = bdu.plan_blocks(m, n, side)
+            nb1 = int(np.sum(blocks[:, 3] == 1))
+            parts = [(0, len(blocks)), (0, nb1), (nb1, len(blocks))]
+            prev = 0
+            for c in bcut:
+                parts.append((prev, int(c)))
+                prev = int(c)
+            for a, b in parts:
+                assert _pipelined_launch_violations(k0, nw, blocks[a:b], ncols, RC=RC) == [], (side, a, b)
+    finally:
+        bdu.set_tiling(*saved)
+
+
+def test_pipelined_checker_sees_a_reordering():
+    """Blocks started one chunk after the previous one's live chunks, ignoring
+    the device-memory order, would load columns before they are stored."""
+    saved = bdu.get_tiling()
+    try:
+        bdu.set_tiling(12, 15, 1)
+        blocks = bdu.plan_blocks(600, 600, 1).copy()
+        U = 15
+        s = 0
+        for r in blocks:
+            if r[1] < 0:
+                continue
+            r[4] = s
+            s += ((r[1] + 1) // 3 + 12 - 1 + U) // U
+        bad = _pipelined_launch_violations(12, 15, blocks, 600)
+        assert any(b[0].startswith("load too soon") for b in bad)
+    finally:
+        bdu.set_tiling(*saved)
 
 
 def test_staged_protocol_checker_sees_a_race():
