@@ -395,6 +395,36 @@ def test_pipelined_staged_launches_are_race_free(k0, nw, rpl, RC, m, n):
         bdu.set_tiling(*saved)
 
 
+def test_plan_blocks_boundary():
+    """bdu_plan_blocks: argument errors, and the layout the kernels read
+    (phase-1 blocks first, slots back to back, start chunks non-decreasing
+    and at least the previous block's live chunks apart)."""
+    L = bdu.lib()
+    assert L.bdu_plan_blocks(5, 6, 0, None, 0) == bdu.BDU_EINVAL   # m < n
+    assert L.bdu_plan_blocks(6, 6, 2, None, 0) == bdu.BDU_EINVAL   # side
+    assert L.bdu_plan_blocks(6, 6, 0, None, -1) == bdu.BDU_EINVAL  # cap
+    assert L.bdu_plan_blocks(6, 6, 0, None, 3) == bdu.BDU_EINVAL   # no room
+    saved = bdu.get_tiling()
+    try:
+        for k0, nw in ((12, 15), (12, 7), (18, 5)):
+            bdu.set_tiling(k0, nw, 1)
+            U = k0 + 3
+            K = k0 * nw
+            for side in (0, 1):
+                b = bdu.plan_blocks(300, 260, side)
+                st = bdu.plan_stats(300, 260)
+                ph = b[:, 3]
+                assert list(ph) == sorted(ph)
+                assert np.all(b[1:, 5] == b[:-1, 5] + b[:-1, 2] * K)
+                assert b[-1, 5] + b[-1, 2] * K == st["left_slots" if side == 0 else "right_slots"]
+                assert np.all(b[:, 2] % U == 0)
+                live = [(b[i, 4], ((b[i, 1] + 1) // 3 + k0 - 1 + U) // U) for i in range(len(b)) if b[i, 1] >= 0]
+                for (s0, c0), (s1, _) in zip(live, live[1:]):
+                    assert s1 >= s0 + c0
+    finally:
+        bdu.set_tiling(*saved)
+
+
 def test_pipelined_checker_sees_a_reordering():
     """Blocks started one chunk after the previous one's live chunks, ignoring
     the device-memory order, would load columns before they are stored."""
