@@ -300,7 +300,7 @@ __global__ __launch_bounds__(kGenThreads) void gen_kernel(HandleDev *const *hs, 
             vb = P1 ? uy : yv[1];
         }
         double c, sn, rr;
-        givens_m<P1 ? 1 : 2>(va, vb, c, sn, rr);
+        givens_fast<P1 ? 1 : 2>(va, vb, c, sn, rr);
 #pragma unroll
         for (int q = 0; q < 5; ++q) rot(c, sn, xv[q], yv[q]);
         rot(c, sn, ux, uy);

@@ -55,12 +55,62 @@ __device__ __forceinline__ void givens_m(double a, double b, double &c, double &
     r = ident ? (m1 ? b : a) : rs * unsc;
 }
 
+// The same generator, faster when the magnitudes of a and b lie in
+// [2^-370, 2^370] on every active lane of the wavefront (a wave-uniform
+// test; otherwise the general form above runs).  In that range no scaling
+// applies, the target is nonzero, r^2 = a^2 + b^2 is at least 2^-740, and
+// both quotients and 1/r are normal numbers, so the IEEE square root and the
+// two IEEE divisions by r reduce to their core sequences with the same
+// correctly rounded results: the square root as an rsq estimate with two
+// Newton-Raphson corrections, each division as the reciprocal refined twice,
+// the product and one residual correction.  Their scaling and special-value
+// steps only change operands outside the range.  The two divisions share
+// the reciprocal of r.
+template <int MODE>
+__device__ __forceinline__ void givens_fast(double a, double b, double &c, double &s, double &r)
+{
+    const double fa = fabs(a), fb = fabs(b);
+    const bool in = fa >= 0x1p-370 && fa <= 0x1p370 && fb >= 0x1p-370 && fb <= 0x1p370;
+    if (!__all(in)) {
+        givens_m<MODE>(a, b, c, s, r);
+        return;
+    }
+    constexpr bool m1 = MODE == 1;
+    const double x = fma(a, a, b * b);
+    // square root of x
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = y * 0.5;
+    const double t = fma(-h, g, 0.5);
+    g = fma(g, t, g);
+    h = fma(h, t, h);
+    double d = fma(-g, g, x);
+    g = fma(d, h, g);
+    d = fma(-g, g, x);
+    g = fma(d, h, g);
+    const double rs = g;
+    // 1/rs, refined twice
+    double rc = __builtin_amdgcn_rcp(rs);
+    double e = fma(-rs, rc, 1.0);
+    rc = fma(rc, e, rc);
+    e = fma(-rs, rc, 1.0);
+    rc = fma(rc, e, rc);
+    auto quot = [&](double n) {
+        const double q0 = n * rc;
+        const double rem = fma(-rs, q0, n);
+        return fma(rem, rc, q0);
+    };
+    const double p = quot(m1 ? b : a), q = quot(m1 ? a : b);
+    c = p;
+    s = m1 ? q : -q;
+    r = rs;
+}
+
 __device__ __forceinline__ void givens(double a, double b, int mode, double &c, double &s, double &r)
 {
     if (mode == 1)
-        givens_m<1>(a, b, c, s, r);
+        givens_fast<1>(a, b, c, s, r);
     else
-        givens_m<2>(a, b, c, s, r);
+        givens_fast<2>(a, b, c, s, r);
 }
 
 __device__ __forceinline__ void rot(double c, double s, double &x, double &y)

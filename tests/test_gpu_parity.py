@@ -51,6 +51,30 @@ def test_rotation_primitive_bit_exact(bdu, oracle):
         _eq(f"r mode {mode}", r, ref[:, 2])
 
 
+def test_rotation_primitive_fast_range_bit_exact(bdu, oracle):
+    """Magnitudes inside the generator's fast range [2^-370, 2^370] in whole
+    wavefronts of 64 (which then take the shortened square root and
+    divisions), and wavefronts with one lane on or just past a bound."""
+    rng = np.random.default_rng(41)
+    k = 64 * 400
+    a = rng.standard_normal(k) * 10.0 ** rng.uniform(-100, 100, k)
+    b = rng.standard_normal(k) * 10.0 ** rng.uniform(-100, 100, k)
+    lo, hi = 2.0 ** -370, 2.0 ** 370
+    edges = [lo, np.nextafter(lo, 0.0), hi, np.nextafter(hi, np.inf), -lo, -hi]
+    for w in range(0, k // 64, 5):
+        x = edges[(w // 5) % len(edges)]
+        if (w // 5) % 2:
+            a[64 * w + w % 64] = x
+        else:
+            b[64 * w + (3 * w) % 64] = x
+    for mode in (1, 2):
+        c, s, r = bdu.givens_device(a, b, mode)
+        ref = np.array([oracle.givens(x, y, mode) for x, y in zip(a, b)])
+        _eq(f"c mode {mode}", c, ref[:, 0])
+        _eq(f"s mode {mode}", s, ref[:, 1])
+        _eq(f"r mode {mode}", r, ref[:, 2])
+
+
 @pytest.mark.parametrize("m,n", [(2, 2), (64, 64), (65, 63), (200, 200), (4000, 2000)])
 def test_projection_bit_exact(bdu, oracle, m, n):
     f = W.factorization(m, n, 41)
